@@ -1,0 +1,159 @@
+/*
+ * ntrupkg.h -- batched Streamlined NTRU Prime key generation on AMD MI355X
+ * (gfx950).  C ABI; no C++ or torch types.
+ *
+ * What it computes (OpenSSLNTRU paper, arXiv 2106.08759):
+ *   KeyGen, Section 3.1: g small and invertible in R/3, 1/g in R/3, f in
+ *   Short, h = g/(3f) in R/q, key pair (h, (f, 1/g)); batched as in
+ *   Algorithm 1 (BatchKeyGen), the R/q reciprocals of a group of G keys shared
+ *   by Montgomery's trick (Section 2.2: prefix products, one reciprocal,
+ *   back-substitution; 3G-3 products + 1 reciprocal for G keys).  The R/3
+ *   reciprocal is computed per key by constant-time divsteps (the extended-gcd
+ *   algorithm of Bernstein and Yang that Section 3.1 cites), which also
+ *   decides invertibility.  R = Z[x]/(x^p - x - 1), parameter sets of
+ *   Section 2.1 plus sntrup1277 (q = 7879, w = 492).
+ *
+ * Determinism.  Key i of a call is a pure function of (seed, p, first_index+i):
+ *   randomness is ChaCha20 (RFC 8439 block function) keyed by the 32-byte
+ *   seed with nonce (key index u64 LE || p u16 LE || stream u16 LE); stream 0
+ *   gives f, stream 1+k the k-th attempt at g.  So a key does not depend on n,
+ *   on the group size, on the launch form or on other jobs in the same call.
+ *
+ * Encodings (the paper defines none; these are this library's):
+ *   pk: h_i + (q-1)/2 packed as 13-bit little-endian fields, ceil(13p/8) B;
+ *   sk: f then 1/g, each coefficient c as c+1 in 2 bits, four per byte,
+ *       least significant first, ceil(p/4) B each.
+ *
+ * Memory.  Key buffers are DEVICE pointers owned by the caller; the library
+ * never frees them.  The context owns a device workspace that it grows on
+ * demand (hipMalloc outside of any capture); ntrup_ctx_reserve sizes it in
+ * advance so that later calls allocate nothing.
+ *
+ * Streams.  hipStream_t is passed as void*; NULL = the default stream.  All
+ * keygen entry points are asynchronous: they return after enqueueing.
+ * ntrup_ctx_status synchronises a stream and reports key-level failures.
+ *
+ * Errors.  0 on success, negative codes below; nothing aborts or prints.
+ * A context is used by one host thread at a time.
+ */
+#ifndef NTRUPKG_H
+#define NTRUPKG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define NTRUP_OK 0
+#define NTRUP_EIO (-5)      /* a HIP call failed; see ntrup_last_hip_error */
+#define NTRUP_EAGAIN (-11)  /* some key found no invertible g within 64 draws */
+#define NTRUP_ENOMEM (-12)  /* device allocation failed */
+#define NTRUP_EINVAL (-22)  /* bad parameter set, size, pointer or config */
+#define NTRUP_EFAULT (-14)  /* a group product was not a unit (cannot happen in a field) */
+
+#define NTRUP_MAX_ATTEMPTS 64
+
+typedef struct ntrup_ctx ntrup_ctx;
+
+/* Sizes of parameter set p in {653, 761, 857, 1277} (Section 2.1).  Any
+   output pointer may be NULL.  Returns NTRUP_EINVAL for other p. */
+int ntrup_params(int p, int *q, int *w, size_t *pk_bytes, size_t *sk_bytes);
+
+/* Create a context on HIP device `device`.  *out receives the handle. */
+int ntrup_ctx_create(ntrup_ctx **out, int device);
+int ntrup_ctx_destroy(ntrup_ctx *ctx);
+
+/* Pre-size the workspace for calls of up to n keys of ring degree p. */
+int ntrup_ctx_reserve(ntrup_ctx *ctx, int p, size_t n);
+
+/* Bytes of device workspace currently held. */
+size_t ntrup_ctx_workspace_bytes(const ntrup_ctx *ctx);
+
+/* Last hipError_t seen by the context (0 if none). */
+int ntrup_last_hip_error(const ntrup_ctx *ctx);
+const char *ntrup_strerror(int code);
+
+/* Tuning knobs per parameter set (chosen by the autotuner or the caller).
+ *   group_size     Montgomery group size G, 1..1024 (Section 2.2's n)
+ *   lanes_per_key  1 or 2 lanes per key for the R/3 divsteps
+ *   retry_passes   0..8 compacted passes over keys whose g was not a unit,
+ *                  before a final pass that loops up to 64 draws
+ *   use_graph      replay the pipeline from a captured hipGraph when the
+ *                  call's arguments repeat                                   */
+typedef struct {
+    int group_size;
+    int lanes_per_key;
+    int retry_passes;
+    int use_graph;
+} ntrup_config;
+
+int ntrup_get_config(const ntrup_ctx *ctx, int p, ntrup_config *cfg);
+int ntrup_set_config(ntrup_ctx *ctx, int p, const ntrup_config *cfg);
+
+/* Batched KeyGen (Algorithm 1): keys first_index .. first_index+n-1.
+ *   seed  HOST pointer, 32 bytes (copied into the launch; may be freed after)
+ *   pk    device, n * pk_bytes(p) bytes, row-major by key
+ *   sk    device, n * sk_bytes(p) bytes, row-major by key
+ * n >= 1 and n <= 2^31 - 1.  Asynchronous on `stream`.  Key-level failures
+ * (no invertible g in 64 draws, probability < 2^-300 per key) are reported by
+ * ntrup_ctx_status. */
+int ntrup_batch_keygen(ntrup_ctx *ctx, int p, const uint8_t *seed, uint64_t first_index, size_t n,
+                       uint8_t *pk, uint8_t *sk, void *stream);
+
+/* The plain form, KeyGen of Section 3.1 one key per launch sequence (group
+ * size 1, no batching): same outputs as ntrup_batch_keygen. */
+int ntrup_keygen_plain(ntrup_ctx *ctx, int p, const uint8_t *seed, uint64_t first_index, size_t n,
+                       uint8_t *pk, uint8_t *sk, void *stream);
+
+/* Several parameter sets in one call (same seed); outputs identical to one
+ * ntrup_batch_keygen per job. */
+typedef struct {
+    int p;
+    uint64_t first_index;
+    size_t n;
+    uint8_t *pk; /* device */
+    uint8_t *sk; /* device */
+} ntrup_job;
+
+int ntrup_batch_keygen_mixed(ntrup_ctx *ctx, const uint8_t *seed, const ntrup_job *jobs, size_t njobs,
+                             void *stream);
+
+/* Synchronise `stream` and report the last keygen call on this context:
+ * 0, NTRUP_EAGAIN, NTRUP_EFAULT or NTRUP_EIO. */
+int ntrup_ctx_status(ntrup_ctx *ctx, void *stream);
+
+/* ---- single operations (kernel-level access, used by the tests) ----------
+ * All arrays are device pointers, row-major [n][p], centered coefficients.
+ * Each runs the same device code as the keygen pipeline.                   */
+
+/* c = a * b in R/q (Section 2.1).  |a|,|b| <= (q-1)/2.  small_a != 0 selects
+ * the small-operand path, which requires |a_j| <= 3. */
+int ntrup_op_mul_rq(ntrup_ctx *ctx, int p, const int16_t *a, const int16_t *b, int16_t *c, size_t n,
+                    int small_a, void *stream);
+
+/* out = 1/a in R/q by divsteps; ok[i] = 1 iff a_i is a unit. */
+int ntrup_op_recip_rq(ntrup_ctx *ctx, int p, const int16_t *a, int16_t *out, int32_t *ok, size_t n,
+                      void *stream);
+
+/* out = 1/a in R/3 by bitsliced divsteps (coefficients in {-1,0,1});
+ * ok[i] = 1 iff a_i is a unit (out_i undefined otherwise). */
+int ntrup_op_recip_r3(ntrup_ctx *ctx, int p, const int8_t *a, int8_t *out, int32_t *ok, size_t n,
+                      void *stream);
+
+/* Montgomery batch inversion (Section 2.2) in R/q over consecutive groups of
+ * group_size rows: out_i = 1/a_i.  Every a_i must be nonzero. */
+int ntrup_op_batch_inv_rq(ntrup_ctx *ctx, int p, const int16_t *a, int16_t *out, size_t n,
+                          size_t group_size, void *stream);
+
+/* The samplers: f (Short) and the attempt-th g (small) of keys
+ * first_index .. first_index+n-1, as int8 rows. */
+int ntrup_op_sample(ntrup_ctx *ctx, int p, const uint8_t *seed, uint64_t first_index, size_t n, int attempt,
+                    int8_t *f, int8_t *g, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NTRUPKG_H */

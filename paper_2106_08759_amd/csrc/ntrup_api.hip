@@ -1,0 +1,514 @@
+// C ABI of the batched KeyGen library: argument checking, workspace, launch
+// sequencing and hipGraph replay.  See include/ntrupkg.h for the contract.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <new>
+#include <vector>
+
+#include "../../include/ntrupkg.h"
+#include "ntrup_kernels.h"
+
+using namespace ntrup;
+
+namespace {
+
+constexpr int kParams[4] = {653, 761, 857, 1277};
+constexpr int kCounterInts = 64;  // [0, 16): list counts; [32]: error bits
+
+int param_slot(int p) {
+    for (int i = 0; i < 4; i++)
+        if (kParams[i] == p) return i;
+    return -1;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Workspace of one pipeline of n keys of degree p.
+struct Ws {
+    int8_t* f_rows;
+    uint32_t* gbits;
+    uint32_t* ibits;
+    int16_t* bscr;
+    uint8_t* attempts;
+    int* lists[2];
+    int* counters;
+};
+
+size_t ws_bytes(int p, size_t n) {
+    const size_t wn = (size_t)ceil_div(p, 32);
+    return align256(n * p) + 2 * align256(wn * 2 * n * 4) + align256(n * p * 2) + align256(n) +
+           2 * align256(n * 4) + align256(kCounterInts * 4);
+}
+
+Ws carve(void* base, int p, size_t n) {
+    const size_t wn = (size_t)ceil_div(p, 32);
+    char* c = (char*)base;
+    Ws w;
+    w.f_rows = (int8_t*)c;       c += align256(n * p);
+    w.gbits = (uint32_t*)c;      c += align256(wn * 2 * n * 4);
+    w.ibits = (uint32_t*)c;      c += align256(wn * 2 * n * 4);
+    w.bscr = (int16_t*)c;        c += align256(n * p * 2);
+    w.attempts = (uint8_t*)c;    c += align256(n);
+    w.lists[0] = (int*)c;        c += align256(n * 4);
+    w.lists[1] = (int*)c;        c += align256(n * 4);
+    w.counters = (int*)c;
+    return w;
+}
+
+struct GraphKey {
+    int p;
+    size_t n;
+    uint64_t first_index;
+    uint32_t seed[8];
+    void* pk;
+    void* sk;
+    void* ws;
+    ntrup_config cfg;
+    bool operator==(const GraphKey& o) const { return memcmp(this, &o, sizeof(*this)) == 0; }
+};
+
+}  // namespace
+
+struct ntrup_ctx {
+    int device = 0;
+    int last_hip_error = 0;
+    void* ws = nullptr;
+    size_t ws_cap = 0;
+    ntrup_config cfg[4];
+    std::vector<int*> last_err;     // error words of the last keygen call
+    hipStream_t cap_stream = nullptr;
+    bool have_graph = false;
+    GraphKey gkey;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+int hip_fail(ntrup_ctx* ctx, hipError_t e) {
+    ctx->last_hip_error = (int)e;
+    return NTRUP_EIO;
+}
+
+#define NTRUP_HIP(ctx, expr)                             \
+    do {                                                 \
+        hipError_t e_ = (expr);                          \
+        if (e_ != hipSuccess) return hip_fail(ctx, e_);  \
+    } while (0)
+
+int set_device(ntrup_ctx* ctx) {
+    NTRUP_HIP(ctx, hipSetDevice(ctx->device));
+    return 0;
+}
+
+int ensure_ws(ntrup_ctx* ctx, size_t bytes) {
+    if (bytes <= ctx->ws_cap) return 0;
+    if (ctx->ws) {
+        NTRUP_HIP(ctx, hipDeviceSynchronize());
+        NTRUP_HIP(ctx, hipFree(ctx->ws));
+        ctx->ws = nullptr;
+        ctx->ws_cap = 0;
+        ctx->have_graph = false;  // captured pointers are stale
+    }
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+        ctx->last_hip_error = (int)e;
+        return NTRUP_ENOMEM;
+    }
+    ctx->ws = p;
+    ctx->ws_cap = bytes;
+    return 0;
+}
+
+Seed make_seed(const uint8_t* s) {
+    Seed k;
+    for (int i = 0; i < 8; i++)
+        k.k[i] = (uint32_t)s[4 * i] | ((uint32_t)s[4 * i + 1] << 8) | ((uint32_t)s[4 * i + 2] << 16) |
+                 ((uint32_t)s[4 * i + 3] << 24);
+    return k;
+}
+
+unsigned grid_for(size_t items, size_t per_block) { return (unsigned)((items + per_block - 1) / per_block); }
+
+// Enqueue the whole KeyGen pipeline of one job on `st`.  zero_err: also clear
+// the error word (once per API call).
+template <int P>
+int enqueue_keygen(ntrup_ctx* ctx, const ntrup_config& cfg, const Seed& seed, uint64_t first_index,
+                   size_t n, uint8_t* pk, uint8_t* sk, const Ws& w, hipStream_t st, bool zero_err) {
+    hipLaunchKernelGGL(zero_ints_kernel, dim3(1), dim3(64), 0, st, w.counters, zero_err ? kCounterInts : 16);
+    hipLaunchKernelGGL(sample_short_kernel<P>, dim3(grid_for(n, 4)), dim3(256), 0, st, seed, first_index, (int)n,
+                       w.f_rows);
+    R3Args a;
+    a.seed = seed;
+    a.first_index = first_index;
+    a.n = (int)n;
+    a.attempts = w.attempts;
+    a.gbits = w.gbits;
+    a.ibits = w.ibits;
+    a.err = w.counters + 32;
+    a.g_in = nullptr;
+    const int R = cfg.retry_passes;
+    for (int pass = 0; pass <= R + 1; pass++) {
+        const bool last = pass == R + 1;
+        a.list_in = pass == 0 ? nullptr : w.lists[(pass - 1) & 1];
+        a.count_in = pass == 0 ? nullptr : w.counters + (pass - 1);
+        a.list_out = last ? nullptr : w.lists[pass & 1];
+        a.count_out = last ? nullptr : w.counters + pass;
+        a.max_rounds = last ? kMaxAttempts : 1;
+        if (cfg.lanes_per_key == 2)
+            hipLaunchKernelGGL((r3_kernel<P, 2>), dim3(grid_for(n, 32)), dim3(64), 0, st, a);
+        else
+            hipLaunchKernelGGL((r3_kernel<P, 1>), dim3(grid_for(n, 64)), dim3(64), 0, st, a);
+    }
+    GroupArgs g;
+    g.n = (int)n;
+    g.G = cfg.group_size;
+    g.f_rows = w.f_rows;
+    g.gbits = w.gbits;
+    g.ibits = w.ibits;
+    g.bscr = w.bscr;
+    g.pk = pk;
+    g.sk = sk;
+    g.err = w.counters + 32;
+    g.a_in = nullptr;
+    g.c_out = nullptr;
+    hipLaunchKernelGGL((group_kernel<P, true>), dim3(grid_for(n, cfg.group_size)), dim3(64), 0, st, g);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(ctx, e);
+    return 0;
+}
+
+int enqueue_dispatch(ntrup_ctx* ctx, int p, const ntrup_config& cfg, const Seed& seed, uint64_t first_index,
+                     size_t n, uint8_t* pk, uint8_t* sk, const Ws& w, hipStream_t st, bool zero_err) {
+    switch (p) {
+        case 653: return enqueue_keygen<653>(ctx, cfg, seed, first_index, n, pk, sk, w, st, zero_err);
+        case 761: return enqueue_keygen<761>(ctx, cfg, seed, first_index, n, pk, sk, w, st, zero_err);
+        case 857: return enqueue_keygen<857>(ctx, cfg, seed, first_index, n, pk, sk, w, st, zero_err);
+        case 1277: return enqueue_keygen<1277>(ctx, cfg, seed, first_index, n, pk, sk, w, st, zero_err);
+    }
+    return NTRUP_EINVAL;
+}
+
+bool valid_config(const ntrup_config& c) {
+    return c.group_size >= 1 && c.group_size <= 1024 && (c.lanes_per_key == 1 || c.lanes_per_key == 2) &&
+           c.retry_passes >= 0 && c.retry_passes <= 8 && (c.use_graph == 0 || c.use_graph == 1);
+}
+
+int check_job(int p, size_t n, const void* pk, const void* sk) {
+    if (param_slot(p) < 0 || n == 0 || n > 0x7FFFFFFF || !pk || !sk) return NTRUP_EINVAL;
+    return 0;
+}
+
+template <int P>
+int op_recip_r3(ntrup_ctx* ctx, int lpk, const int8_t* a, int8_t* out, int32_t* ok, size_t n, hipStream_t st) {
+    if (int r = ensure_ws(ctx, ws_bytes(P, n))) return r;
+    const Ws w = carve(ctx->ws, P, n);
+    R3Args ar;
+    memset(&ar, 0, sizeof ar);
+    ar.n = (int)n;
+    ar.max_rounds = 1;
+    ar.attempts = w.attempts;
+    ar.gbits = w.gbits;
+    ar.ibits = w.ibits;
+    ar.err = w.counters + 32;
+    ar.g_in = a;
+    if (lpk == 2) hipLaunchKernelGGL((r3_kernel<P, 2>), dim3(grid_for(n, 32)), dim3(64), 0, st, ar);
+    else hipLaunchKernelGGL((r3_kernel<P, 1>), dim3(grid_for(n, 64)), dim3(64), 0, st, ar);
+    hipLaunchKernelGGL(unpack_bits_kernel<P>, dim3(grid_for(n, 256)), dim3(256), 0, st, (int)n, w.ibits, out);
+    hipLaunchKernelGGL(copy_flags_kernel, dim3(grid_for(n, 256)), dim3(256), 0, st, (int)n, w.attempts, ok);
+    NTRUP_HIP(ctx, hipGetLastError());
+    return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ntrup_params(int p, int* q, int* w, size_t* pkb, size_t* skb) {
+    int qq, ww;
+    switch (p) {
+        case 653: qq = Param<653>::q; ww = Param<653>::w; break;
+        case 761: qq = Param<761>::q; ww = Param<761>::w; break;
+        case 857: qq = Param<857>::q; ww = Param<857>::w; break;
+        case 1277: qq = Param<1277>::q; ww = Param<1277>::w; break;
+        default: return NTRUP_EINVAL;
+    }
+    if (q) *q = qq;
+    if (w) *w = ww;
+    if (pkb) *pkb = (size_t)pk_bytes(p);
+    if (skb) *skb = (size_t)sk_bytes(p);
+    return 0;
+}
+
+const char* ntrup_strerror(int code) {
+    switch (code) {
+        case NTRUP_OK: return "ok";
+        case NTRUP_EIO: return "HIP call failed";
+        case NTRUP_EAGAIN: return "no invertible g within the attempt cap";
+        case NTRUP_ENOMEM: return "device allocation failed";
+        case NTRUP_EINVAL: return "invalid argument";
+        case NTRUP_EFAULT: return "group product not a unit";
+    }
+    return "unknown error";
+}
+
+int ntrup_ctx_create(ntrup_ctx** out, int device) {
+    if (!out) return NTRUP_EINVAL;
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return NTRUP_EINVAL;
+    ntrup_ctx* ctx = new (std::nothrow) ntrup_ctx();
+    if (!ctx) return NTRUP_ENOMEM;
+    ctx->device = device;
+    for (int i = 0; i < 4; i++) ctx->cfg[i] = ntrup_config{32, kParams[i] > 800 ? 2 : 1, 1, 1};
+    if (set_device(ctx) != 0 || hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+        delete ctx;
+        return NTRUP_EIO;
+    }
+    *out = ctx;
+    return 0;
+}
+
+int ntrup_ctx_destroy(ntrup_ctx* ctx) {
+    if (!ctx) return NTRUP_EINVAL;
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    if (ctx->exec) (void)hipGraphExecDestroy(ctx->exec);
+    if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+    if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+    if (ctx->ws) (void)hipFree(ctx->ws);
+    delete ctx;
+    return 0;
+}
+
+int ntrup_ctx_reserve(ntrup_ctx* ctx, int p, size_t n) {
+    if (!ctx || param_slot(p) < 0 || n == 0) return NTRUP_EINVAL;
+    if (int r = set_device(ctx)) return r;
+    return ensure_ws(ctx, ws_bytes(p, n));
+}
+
+size_t ntrup_ctx_workspace_bytes(const ntrup_ctx* ctx) { return ctx ? ctx->ws_cap : 0; }
+
+int ntrup_last_hip_error(const ntrup_ctx* ctx) { return ctx ? ctx->last_hip_error : 0; }
+
+int ntrup_get_config(const ntrup_ctx* ctx, int p, ntrup_config* cfg) {
+    const int s = param_slot(p);
+    if (!ctx || s < 0 || !cfg) return NTRUP_EINVAL;
+    *cfg = ctx->cfg[s];
+    return 0;
+}
+
+int ntrup_set_config(ntrup_ctx* ctx, int p, const ntrup_config* cfg) {
+    const int s = param_slot(p);
+    if (!ctx || s < 0 || !cfg || !valid_config(*cfg)) return NTRUP_EINVAL;
+    ctx->cfg[s] = *cfg;
+    return 0;
+}
+
+int ntrup_batch_keygen(ntrup_ctx* ctx, int p, const uint8_t* seed, uint64_t first_index, size_t n, uint8_t* pk,
+                       uint8_t* sk, void* stream) {
+    if (!ctx || !seed) return NTRUP_EINVAL;
+    if (int r = check_job(p, n, pk, sk)) return r;
+    if (int r = set_device(ctx)) return r;
+    if (int r = ensure_ws(ctx, ws_bytes(p, n))) return r;
+    const ntrup_config& cfg = ctx->cfg[param_slot(p)];
+    const Seed sd = make_seed(seed);
+    const Ws w = carve(ctx->ws, p, n);
+    hipStream_t st = (hipStream_t)stream;
+    ctx->last_err.assign(1, w.counters + 32);
+    if (!cfg.use_graph) return enqueue_dispatch(ctx, p, cfg, sd, first_index, n, pk, sk, w, st, true);
+
+    GraphKey key;
+    memset(&key, 0, sizeof key);
+    key.p = p;
+    key.n = n;
+    key.first_index = first_index;
+    memcpy(key.seed, sd.k, sizeof key.seed);
+    key.pk = pk;
+    key.sk = sk;
+    key.ws = ctx->ws;
+    key.cfg = cfg;
+    if (!ctx->have_graph || !(ctx->gkey == key)) {
+        if (ctx->exec) { (void)hipGraphExecDestroy(ctx->exec); ctx->exec = nullptr; }
+        if (ctx->graph) { (void)hipGraphDestroy(ctx->graph); ctx->graph = nullptr; }
+        ctx->have_graph = false;
+        NTRUP_HIP(ctx, hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
+        int r = enqueue_dispatch(ctx, p, cfg, sd, first_index, n, pk, sk, w, ctx->cap_stream, true);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(ctx->cap_stream, &g);
+        if (r) { if (g) (void)hipGraphDestroy(g); return r; }
+        if (e != hipSuccess) return hip_fail(ctx, e);
+        ctx->graph = g;
+        NTRUP_HIP(ctx, hipGraphInstantiate(&ctx->exec, g, nullptr, nullptr, 0));
+        ctx->gkey = key;
+        ctx->have_graph = true;
+    }
+    NTRUP_HIP(ctx, hipGraphLaunch(ctx->exec, st));
+    return 0;
+}
+
+int ntrup_keygen_plain(ntrup_ctx* ctx, int p, const uint8_t* seed, uint64_t first_index, size_t n, uint8_t* pk,
+                       uint8_t* sk, void* stream) {
+    if (!ctx || !seed) return NTRUP_EINVAL;
+    if (int r = check_job(p, n, pk, sk)) return r;
+    if (int r = set_device(ctx)) return r;
+    if (int r = ensure_ws(ctx, ws_bytes(p, 1))) return r;
+    ntrup_config cfg = ctx->cfg[param_slot(p)];
+    cfg.group_size = 1;
+    const Seed sd = make_seed(seed);
+    const Ws w = carve(ctx->ws, p, 1);
+    ctx->last_err.assign(1, w.counters + 32);
+    size_t pkb, skb;
+    ntrup_params(p, nullptr, nullptr, &pkb, &skb);
+    for (size_t i = 0; i < n; i++) {
+        int r = enqueue_dispatch(ctx, p, cfg, sd, first_index + i, 1, pk + i * pkb, sk + i * skb, w,
+                                 (hipStream_t)stream, i == 0);
+        if (r) return r;
+    }
+    return 0;
+}
+
+int ntrup_batch_keygen_mixed(ntrup_ctx* ctx, const uint8_t* seed, const ntrup_job* jobs, size_t njobs,
+                             void* stream) {
+    if (!ctx || !seed || !jobs || njobs == 0) return NTRUP_EINVAL;
+    size_t total = 0;
+    for (size_t j = 0; j < njobs; j++) {
+        if (int r = check_job(jobs[j].p, jobs[j].n, jobs[j].pk, jobs[j].sk)) return r;
+        total += ws_bytes(jobs[j].p, jobs[j].n);
+    }
+    if (int r = set_device(ctx)) return r;
+    if (int r = ensure_ws(ctx, total)) return r;
+    const Seed sd = make_seed(seed);
+    ctx->last_err.clear();
+    char* base = (char*)ctx->ws;
+    for (size_t j = 0; j < njobs; j++) {
+        const Ws w = carve(base, jobs[j].p, jobs[j].n);
+        base += ws_bytes(jobs[j].p, jobs[j].n);
+        ctx->last_err.push_back(w.counters + 32);
+        int r = enqueue_dispatch(ctx, jobs[j].p, ctx->cfg[param_slot(jobs[j].p)], sd, jobs[j].first_index,
+                                 jobs[j].n, jobs[j].pk, jobs[j].sk, w, (hipStream_t)stream, true);
+        if (r) return r;
+    }
+    return 0;
+}
+
+int ntrup_ctx_status(ntrup_ctx* ctx, void* stream) {
+    if (!ctx) return NTRUP_EINVAL;
+    if (int r = set_device(ctx)) return r;
+    NTRUP_HIP(ctx, hipStreamSynchronize((hipStream_t)stream));
+    int bits = 0;
+    for (int* e : ctx->last_err) {
+        int v = 0;
+        NTRUP_HIP(ctx, hipMemcpy(&v, e, sizeof v, hipMemcpyDeviceToHost));
+        bits |= v;
+    }
+    if (bits & 2) return NTRUP_EFAULT;
+    if (bits & 1) return NTRUP_EAGAIN;
+    return 0;
+}
+
+// ---------------------------------------------------------------- single ops
+
+int ntrup_op_mul_rq(ntrup_ctx* ctx, int p, const int16_t* a, const int16_t* b, int16_t* c, size_t n, int small_a,
+                    void* stream) {
+    if (!ctx || param_slot(p) < 0 || !a || !b || !c || n == 0 || n > 0x7FFFFFFF) return NTRUP_EINVAL;
+    if (int r = set_device(ctx)) return r;
+    hipStream_t st = (hipStream_t)stream;
+    const dim3 grid((unsigned)n), blk(64);
+#define NTRUP_MUL(PP)                                                                              \
+    case PP:                                                                                       \
+        if (small_a) hipLaunchKernelGGL((mul_kernel<PP, false>), grid, blk, 0, st, (int)n, a, b, c); \
+        else hipLaunchKernelGGL((mul_kernel<PP, true>), grid, blk, 0, st, (int)n, a, b, c);          \
+        break;
+    switch (p) { NTRUP_MUL(653) NTRUP_MUL(761) NTRUP_MUL(857) NTRUP_MUL(1277) }
+#undef NTRUP_MUL
+    NTRUP_HIP(ctx, hipGetLastError());
+    return 0;
+}
+
+int ntrup_op_recip_rq(ntrup_ctx* ctx, int p, const int16_t* a, int16_t* out, int32_t* ok, size_t n, void* stream) {
+    if (!ctx || param_slot(p) < 0 || !a || !out || !ok || n == 0 || n > 0x7FFFFFFF) return NTRUP_EINVAL;
+    if (int r = set_device(ctx)) return r;
+    hipStream_t st = (hipStream_t)stream;
+    const dim3 grid((unsigned)n), blk(64);
+    switch (p) {
+        case 653: hipLaunchKernelGGL(recip_q_kernel<653>, grid, blk, 0, st, (int)n, a, out, ok); break;
+        case 761: hipLaunchKernelGGL(recip_q_kernel<761>, grid, blk, 0, st, (int)n, a, out, ok); break;
+        case 857: hipLaunchKernelGGL(recip_q_kernel<857>, grid, blk, 0, st, (int)n, a, out, ok); break;
+        case 1277: hipLaunchKernelGGL(recip_q_kernel<1277>, grid, blk, 0, st, (int)n, a, out, ok); break;
+    }
+    NTRUP_HIP(ctx, hipGetLastError());
+    return 0;
+}
+
+
+int ntrup_op_recip_r3(ntrup_ctx* ctx, int p, const int8_t* a, int8_t* out, int32_t* ok, size_t n, void* stream) {
+    if (!ctx || param_slot(p) < 0 || !a || !out || !ok || n == 0 || n > 0x7FFFFFFF) return NTRUP_EINVAL;
+    if (int r = set_device(ctx)) return r;
+    const int lpk = ctx->cfg[param_slot(p)].lanes_per_key;
+    hipStream_t st = (hipStream_t)stream;
+    switch (p) {
+        case 653: return op_recip_r3<653>(ctx, lpk, a, out, ok, n, st);
+        case 761: return op_recip_r3<761>(ctx, lpk, a, out, ok, n, st);
+        case 857: return op_recip_r3<857>(ctx, lpk, a, out, ok, n, st);
+        case 1277: return op_recip_r3<1277>(ctx, lpk, a, out, ok, n, st);
+    }
+    return NTRUP_EINVAL;
+}
+
+int ntrup_op_batch_inv_rq(ntrup_ctx* ctx, int p, const int16_t* a, int16_t* out, size_t n, size_t group_size,
+                          void* stream) {
+    if (!ctx || param_slot(p) < 0 || !a || !out || n == 0 || n > 0x7FFFFFFF || group_size == 0 ||
+        group_size > 1024)
+        return NTRUP_EINVAL;
+    if (int r = set_device(ctx)) return r;
+    if (int r = ensure_ws(ctx, ws_bytes(p, n))) return r;
+    const Ws w = carve(ctx->ws, p, n);
+    hipStream_t st = (hipStream_t)stream;
+    GroupArgs g;
+    memset(&g, 0, sizeof g);
+    g.n = (int)n;
+    g.G = (int)group_size;
+    g.bscr = w.bscr;
+    g.err = w.counters + 32;
+    g.a_in = a;
+    g.c_out = out;
+    ctx->last_err.assign(1, w.counters + 32);
+    hipLaunchKernelGGL(zero_ints_kernel, dim3(1), dim3(64), 0, st, w.counters, kCounterInts);
+    const dim3 grid(grid_for(n, group_size)), blk(64);
+    switch (p) {
+        case 653: hipLaunchKernelGGL((group_kernel<653, false>), grid, blk, 0, st, g); break;
+        case 761: hipLaunchKernelGGL((group_kernel<761, false>), grid, blk, 0, st, g); break;
+        case 857: hipLaunchKernelGGL((group_kernel<857, false>), grid, blk, 0, st, g); break;
+        case 1277: hipLaunchKernelGGL((group_kernel<1277, false>), grid, blk, 0, st, g); break;
+    }
+    NTRUP_HIP(ctx, hipGetLastError());
+    return 0;
+}
+
+int ntrup_op_sample(ntrup_ctx* ctx, int p, const uint8_t* seed, uint64_t first_index, size_t n, int attempt,
+                    int8_t* f, int8_t* g, void* stream) {
+    if (!ctx || param_slot(p) < 0 || !seed || n == 0 || n > 0x7FFFFF || attempt < 0 ||
+        attempt >= NTRUP_MAX_ATTEMPTS)
+        return NTRUP_EINVAL;
+    if (int r = set_device(ctx)) return r;
+    const Seed sd = make_seed(seed);
+    hipStream_t st = (hipStream_t)stream;
+    const unsigned gw = grid_for(n * (size_t)ceil_div(p, 32), 256);
+#define NTRUP_SAMPLE(PP)                                                                                      \
+    case PP:                                                                                                  \
+        if (f) hipLaunchKernelGGL(sample_short_kernel<PP>, dim3(grid_for(n, 4)), dim3(256), 0, st, sd,        \
+                                  first_index, (int)n, f);                                                    \
+        if (g) hipLaunchKernelGGL(sample_small_kernel<PP>, dim3(gw), dim3(256), 0, st, sd, first_index, (int)n, \
+                                  attempt, g);                                                                \
+        break;
+    switch (p) { NTRUP_SAMPLE(653) NTRUP_SAMPLE(761) NTRUP_SAMPLE(857) NTRUP_SAMPLE(1277) }
+#undef NTRUP_SAMPLE
+    NTRUP_HIP(ctx, hipGetLastError());
+    return 0;
+}
+
+}  // extern "C"

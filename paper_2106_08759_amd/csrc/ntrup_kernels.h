@@ -1,0 +1,499 @@
+// Kernels of the batched KeyGen pipeline (OpenSSLNTRU paper, Section 3.1,
+// Algorithm 1 BatchKeyGen with the R/q reciprocals batched by Montgomery's
+// trick of Section 2.2 and the R/3 reciprocal taken per key):
+//
+//   sample_short_kernel  f in Short, one wave per key (ChaCha20 + bitonic sort)
+//   r3_kernel            g small, resampled until invertible; 1/g in R/3;
+//                        one key per lane (or lane pair), bitsliced divsteps
+//   group_kernel         per Montgomery group of G keys, one wave:
+//                        prefix products b_i = a_i b_{i-1} of a_i = 3 f_i,
+//                        one divstep reciprocal t_G = 1/b_G, back-substitution
+//                        c_i = t_i b_{i-1}, t_{i-1} = t_i a_i, then
+//                        h_i = g_i c_i and the encoded pk / sk bytes
+//
+// Workspace layouts (n keys):
+//   f_rows  int8   [n][p]         f, centered
+//   gbits   uint32 [WN][2][n]     accepted g, bitsliced (plane 0: c != 0,
+//   ibits   uint32 [WN][2][n]     1/g          plane 1: c == -1), natural order
+//   bscr    int16  [n][p]         prefix products of each group
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <utility>
+
+#include "ntrup_chacha.h"
+#include "ntrup_params.h"
+#include "ntrup_r3.h"
+#include "ntrup_rq.h"
+
+namespace ntrup {
+
+// ----------------------------------------------------------------------------
+// Short sampler: L_i = (r_i & ~3) | v_i, v_i = 2(r_i & 1) for i < w, else 1;
+// sort L ascending as u32; f_i = (L_i & 3) - 1.  The sort key is the top 30
+// bits of each word, so the w nonzeros land on uniformly random positions
+// with independent random signs (the definition of Short, Section 2.1).
+// ----------------------------------------------------------------------------
+template <int P>
+struct ShortShape {
+    static constexpr int NS = P <= 1024 ? 1024 : 2048;  // sorting network size
+    static constexpr int EPL = NS / 64;                 // elements per lane
+};
+
+// Bitonic sort of 64*EPL words held blocked across the wave (lane l holds
+// elements [EPL*l, EPL*l + EPL)), ascending.  Branch-free min/max only.
+template <int EPL>
+__device__ __forceinline__ void bitonic_sort_wave(uint32_t (&L)[EPL], int lane) {
+    constexpr int NS = 64 * EPL;
+#pragma unroll
+    for (int k = 2; k <= NS; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            if (j >= EPL) {
+                const int lj = j / EPL;
+#pragma unroll
+                for (int e = 0; e < EPL; e++) {
+                    const uint32_t o = (uint32_t)__shfl_xor((int)L[e], lj);
+                    const int i = lane * EPL + e;
+                    const bool keep_min = ((i & j) == 0) == ((i & k) == 0);
+                    L[e] = keep_min ? min(L[e], o) : max(L[e], o);
+                }
+            } else {
+#pragma unroll
+                for (int e = 0; e < EPL; e++) {
+                    if ((e & j) == 0) {
+                        const int e2 = e | j;
+                        const bool up = ((lane * EPL + e) & k) == 0;
+                        const uint32_t a = L[e], b = L[e2];
+                        const uint32_t lo = min(a, b), hi = max(a, b);
+                        L[e] = up ? lo : hi;
+                        L[e2] = up ? hi : lo;
+                    }
+                }
+            }
+        }
+    }
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void sample_short_kernel(Seed seed, uint64_t first_index, int n,
+                                                           int8_t* __restrict__ f_rows) {
+    constexpr int W = Param<P>::w;
+    constexpr int EPL = ShortShape<P>::EPL;
+    const int lane = lane_id();
+    const int key = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (key >= n) return;  // whole wave
+    uint32_t L[EPL];
+#pragma unroll
+    for (int b = 0; b < EPL / 16; b++) {
+        uint32_t r[16];
+        chacha_block(seed, first_index + (uint64_t)key, P, 0, (uint32_t)(lane * (EPL / 16) + b), r);
+#pragma unroll
+        for (int e = 0; e < 16; e++) L[16 * b + e] = r[e];
+    }
+#pragma unroll
+    for (int e = 0; e < EPL; e++) {
+        const int i = lane * EPL + e;
+        const uint32_t v = (i < W) ? 2u * (L[e] & 1u) : 1u;
+        L[e] = (i < P) ? ((L[e] & ~3u) | v) : 0xFFFFFFFFu;
+    }
+    bitonic_sort_wave<EPL>(L, lane);
+    int8_t* row = f_rows + (size_t)key * P;
+#pragma unroll
+    for (int e = 0; e < EPL; e++) {
+        const int i = lane * EPL + e;
+        if (i < P) row[i] = (int8_t)((int)(L[e] & 3u) - 1);
+    }
+}
+
+// ----------------------------------------------------------------------------
+// Small sampler: g_i = floor(3 r_i / 2^32) - 1 from stream 1 + attempt.
+// Natural-order bitsliced word k (coefficients 32k .. 32k+31).
+// ----------------------------------------------------------------------------
+template <int P>
+__device__ __forceinline__ void sample_small_word(const Seed& seed, uint64_t index, int attempt, int k,
+                                                  uint32_t& mw, uint32_t& sw) {
+    mw = 0;
+    sw = 0;
+#pragma unroll
+    for (int half = 0; half < 2; half++) {
+        const int blk = 2 * k + half;
+        if (16 * blk < P) {
+            uint32_t r[16];
+            chacha_block(seed, index, P, 1 + attempt, (uint32_t)blk, r);
+#pragma unroll
+            for (int e = 0; e < 16; e++) {
+                const int i = 16 * blk + e;
+                const uint32_t u = __umulhi(r[e], 3u);  // 0, 1, 2 -> -1, 0, 1
+                const uint32_t live = (i < P) ? 1u : 0u;
+                mw |= ((u != 1u) & live) << (16 * half + e);
+                sw |= ((u == 0u) & live) << (16 * half + e);
+            }
+        }
+    }
+}
+
+// ----------------------------------------------------------------------------
+// R/3 stage.  Main pass: slot -> key.  Retry pass: keys from list_in.  Each
+// round draws a fresh g for the keys not yet done; keys still pending after
+// max_rounds go to list_out (wave-aggregated atomics), or, without list_out,
+// count as exhausted.
+// ----------------------------------------------------------------------------
+struct R3Args {
+    Seed seed;
+    uint64_t first_index;
+    int n;
+    int max_rounds;
+    const int* list_in;     // null in the main pass
+    const int* count_in;
+    int* list_out;          // null: no further pass
+    int* count_out;
+    uint8_t* attempts;      // [n] g samples drawn
+    uint32_t* gbits;        // [WN][2][n]
+    uint32_t* ibits;        // [WN][2][n]
+    int* err;               // |= 1 when a key exhausts kMaxAttempts
+    const int8_t* g_in;     // test entry: explicit g rows [n][p], one round, no sampling
+};
+
+template <int P, int LPK>
+__global__ __launch_bounds__(64) void r3_kernel(R3Args args) {
+    using S = R3Shape<P, LPK>;
+    constexpr int W2 = S::W2;
+    __shared__ uint32_t nat[S::KPW][2][S::WT];
+    __shared__ uint32_t vst[S::KPW][2][S::WT];
+    const int lane = lane_id();
+    const int kl = lane / LPK;
+    const int h = (LPK == 2) ? (lane & 1) : 0;
+    const int slot = blockIdx.x * S::KPW + kl;
+    int key = -1, attempt = 0;
+    if (args.list_in) {
+        if (slot < *args.count_in) {
+            key = args.list_in[slot];
+            attempt = args.attempts[key];
+        }
+    } else if (slot < args.n) {
+        key = slot;
+    }
+    if (__ballot(key >= 0) == 0) return;  // whole wave idle
+    const uint64_t index = args.first_index + (uint64_t)(key < 0 ? 0 : key);
+    bool done = key < 0;
+    uint32_t* nm = nat[kl][0];
+    uint32_t* ns = nat[kl][1];
+    for (int round = 0; round < args.max_rounds; round++) {
+        if (__all(done)) break;
+        for (int k = h; k < S::WT; k += LPK) {
+            uint32_t mw = 0, sw = 0;
+            if (k < S::WN) {
+                if (args.g_in) {
+                    const int8_t* row = args.g_in + (size_t)(key < 0 ? 0 : key) * P;
+#pragma unroll 4
+                    for (int e = 0; e < 32; e++) {
+                        const int i = 32 * k + e;
+                        const int c = (i < P) ? row[i] : 0;
+                        mw |= (uint32_t)(c != 0) << e;
+                        sw |= (uint32_t)(c < 0) << e;
+                    }
+                } else {
+                    sample_small_word<P>(args.seed, index, attempt, k, mw, sw);
+                }
+            }
+            nm[k] = mw;
+            ns[k] = sw;
+        }
+        __syncthreads();
+        uint32_t gm[W2], gs[W2], vm[W2], vs[W2];
+#pragma unroll
+        for (int k = 0; k < W2; k++) {
+            gm[k] = load_reversed<P, LPK>(nm, h * W2 + k);
+            gs[k] = load_reversed<P, LPK>(ns, h * W2 + k);
+        }
+        const int delta = r3_divsteps<P, LPK>(gm, gs, vm, vs, h);
+#pragma unroll
+        for (int k = 0; k < W2; k++) {
+            vst[kl][0][h * W2 + k] = vm[k];
+            vst[kl][1][h * W2 + k] = vs[k];
+        }
+        __syncthreads();
+        if (!done && delta == 0) {
+            for (int k = h; k < S::WN; k += LPK) {
+                const size_t n = (size_t)args.n;
+                args.gbits[(size_t)(2 * k) * n + key] = nm[k];
+                args.gbits[(size_t)(2 * k + 1) * n + key] = ns[k] & nm[k];
+                args.ibits[(size_t)(2 * k) * n + key] = load_output<P, LPK>(vst[kl][0], k);
+                args.ibits[(size_t)(2 * k + 1) * n + key] = load_output<P, LPK>(vst[kl][1], k);
+            }
+            if (h == 0) args.attempts[key] = (uint8_t)(attempt + 1);
+            done = true;
+        } else if (!done) {
+            attempt++;
+            if (attempt >= kMaxAttempts || args.g_in) {
+                if (h == 0) {
+                    args.attempts[key] = args.g_in ? (uint8_t)0 : (uint8_t)attempt;
+                    if (!args.g_in) atomicOr(args.err, 1);
+                }
+                done = true;
+            }
+        }
+        __syncthreads();
+    }
+    const bool pend = !done && h == 0;
+    if (args.list_out) {
+        if (pend) args.attempts[key] = (uint8_t)attempt;
+        const unsigned long long m = __ballot(pend);
+        if (m) {
+            int base = 0;
+            if (lane == 0) base = atomicAdd(args.count_out, __popcll(m));
+            base = __shfl(base, 0);
+            if (pend) args.list_out[base + __popcll(m & ((1ull << lane) - 1ull))] = key;
+        }
+    } else if (pend) {
+        atomicOr(args.err, 1);
+    }
+}
+
+// ----------------------------------------------------------------------------
+// Montgomery group stage.
+// ----------------------------------------------------------------------------
+struct GroupArgs {
+    int n;
+    int G;
+    const int8_t* f_rows;
+    const uint32_t* gbits;
+    const uint32_t* ibits;
+    int16_t* bscr;
+    uint8_t* pk;
+    uint8_t* sk;
+    int* err;               // |= 2 when a group product is not a unit
+    const int16_t* a_in;    // batch-inverse entry: invert these rows (centered) ...
+    int16_t* c_out;         // ... and write the reciprocals here
+};
+
+template <int P>
+struct GroupLds {
+    using S = RqShape<P>;
+    int32_t A[S::JP];
+    int32_t A2[S::JP];
+    int32_t Bb[S::JP];
+    int32_t Cb[S::JP];
+    int32_t E[S::ELEN];
+};
+
+template <int P>
+__device__ __forceinline__ void store_lds(const int32_t (&acc)[RqShape<P>::R], int32_t* dst) {
+    constexpr int R = RqShape<P>::R;
+    const int lane = lane_id();
+#pragma unroll
+    for (int t = 0; t < R; t++)
+        if (R * lane + t < P) dst[R * lane + t] = acc[t];
+}
+
+template <int P>
+__device__ __forceinline__ void store_row(const int32_t (&acc)[RqShape<P>::R], int16_t* row) {
+    constexpr int R = RqShape<P>::R;
+    const int lane = lane_id();
+#pragma unroll
+    for (int t = 0; t < R; t++)
+        if (R * lane + t < P) row[R * lane + t] = (int16_t)acc[t];
+}
+
+// dst[j] = 3 f_j (j < p), 0 up to JP
+template <int P>
+__device__ __forceinline__ void load_3f(const int8_t* row, int32_t* dst) {
+    for (int j = lane_id(); j < RqShape<P>::JP; j += 64) dst[j] = (j < P) ? 3 * (int32_t)row[j] : 0;
+}
+
+template <int P>
+__device__ __forceinline__ void load_row16(const int16_t* row, int32_t* dst) {
+    for (int j = lane_id(); j < RqShape<P>::JP; j += 64) dst[j] = (j < P) ? (int32_t)row[j] : 0;
+}
+
+// dst[j] = g_j from the bitsliced words of key `key`
+template <int P>
+__device__ __forceinline__ void load_g(const uint32_t* gbits, int n, int key, int32_t* dst) {
+    constexpr int WN = ceil_div(P, 32);
+    constexpr int JP = RqShape<P>::JP;
+    const int lane = lane_id();
+    for (int j = P + lane; j < JP; j += 64) dst[j] = 0;
+    if (lane < WN) {
+        const uint32_t m = gbits[(size_t)(2 * lane) * n + key];
+        const uint32_t s = gbits[(size_t)(2 * lane + 1) * n + key];
+#pragma unroll 8
+        for (int e = 0; e < 32; e++) {
+            const int j = 32 * lane + e;
+            if (j < P) dst[j] = (int32_t)((m >> e) & 1u) * (1 - 2 * (int32_t)((s >> e) & 1u));
+        }
+    }
+}
+
+// pk: h_i + (q-1)/2 as 13-bit little-endian fields; sk: f then 1/g as 2-bit
+// fields c + 1, four per byte, least significant first.
+template <int P>
+__device__ __forceinline__ void encode_key(const GroupArgs& a, int key, const int32_t* H) {
+    constexpr int Q = Param<P>::q;
+    constexpr int PKB = pk_bytes(P), SKH = sk_half_bytes(P);
+    const int lane = lane_id();
+    uint8_t* pk = a.pk + (size_t)key * PKB;
+    for (int b = lane; b < PKB; b += 64) {
+        const int bit = 8 * b, i0 = bit / 13, o = bit - 13 * i0;
+        const uint32_t v0 = (uint32_t)(H[i0] + (Q - 1) / 2);
+        const uint32_t v1 = (i0 + 1 < P) ? (uint32_t)(H[i0 + 1] + (Q - 1) / 2) : 0u;
+        pk[b] = (uint8_t)((v0 | (v1 << 13)) >> o);
+    }
+    uint8_t* sk = a.sk + (size_t)key * 2 * SKH;
+    const int8_t* f = a.f_rows + (size_t)key * P;
+    for (int b = lane; b < SKH; b += 64) {
+        uint32_t bf = 0, bi = 0;
+        const int w = b >> 3, sh = (4 * b) & 31;
+        const uint32_t m = a.ibits[(size_t)(2 * w) * a.n + key] >> sh;
+        const uint32_t s = a.ibits[(size_t)(2 * w + 1) * a.n + key] >> sh;
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+            const int i = 4 * b + e;
+            if (i < P) {
+                bf |= (uint32_t)(f[i] + 1) << (2 * e);
+                const uint32_t mb = (m >> e) & 1u, sb = (s >> e) & 1u;
+                bi |= (mb ? (sb ? 0u : 2u) : 1u) << (2 * e);
+            }
+        }
+        sk[b] = (uint8_t)bf;
+        sk[SKH + b] = (uint8_t)bi;
+    }
+}
+
+// KEYGEN = true: a_i = 3 f_i (small), outputs encoded keys.
+// KEYGEN = false: a_i = a_in rows (big), outputs c_i = 1/a_i to c_out.
+template <int P, bool KEYGEN>
+__global__ __launch_bounds__(64) void group_kernel(GroupArgs args) {
+    using S = RqShape<P>;
+    constexpr int R = S::R;
+    __shared__ GroupLds<P> L;
+    const int lane = lane_id();
+    const int k0 = blockIdx.x * args.G;
+    const int gsz = min(args.G, args.n - k0);
+    if (gsz <= 0) return;
+    int32_t acc[R], acc2[R];
+
+    auto load_a = [&](int key, int32_t* dst) {
+        if (KEYGEN) load_3f<P>(args.f_rows + (size_t)key * P, dst);
+        else load_row16<P>(args.a_in + (size_t)key * P, dst);
+    };
+
+    // prefix products: b_1 = a_1, b_i = a_i b_{i-1}
+    load_a(k0, L.Bb);
+    __syncthreads();
+    for (int j = lane; j < P; j += 64) args.bscr[(size_t)k0 * P + j] = (int16_t)L.Bb[j];
+    for (int i = 1; i < gsz; i++) {
+        load_a(k0 + i, L.A);
+        build_E<P>(L.Bb, L.E);
+        __syncthreads();
+        mul_wave<P, !KEYGEN>(L.A, L.Bb, L.E, acc);
+        __syncthreads();
+        store_lds<P>(acc, L.Bb);
+        store_row<P>(acc, args.bscr + (size_t)(k0 + i) * P);
+        __syncthreads();
+    }
+    // one reciprocal per group: t = 1/b_gsz
+    const int ok = recip_wave<P>(L.Bb, L.Bb, L.E);
+    if (!ok && lane == 0) atomicOr(args.err, 2);
+
+    auto finish = [&](int key, const int32_t* C) {
+        // C holds c = 1/a of this key
+        if (KEYGEN) {
+            load_g<P>(args.gbits, args.n, key, L.A);
+            build_E<P>(C, L.E);
+            __syncthreads();
+            mul_wave<P, false>(L.A, C, L.E, acc);   // h = g c
+            __syncthreads();
+            store_lds<P>(acc, L.A2);
+            __syncthreads();
+            encode_key<P>(args, key, L.A2);
+        } else {
+            for (int j = lane; j < P; j += 64) args.c_out[(size_t)key * P + j] = (int16_t)C[j];
+        }
+        __syncthreads();
+    };
+
+    // back-substitution: c_i = t_i b_{i-1}, t_{i-1} = t_i a_i (t_i in Bb)
+    for (int i = gsz - 1; i >= 1; i--) {
+        load_row16<P>(args.bscr + (size_t)(k0 + i - 1) * P, L.A);
+        load_a(k0 + i, L.A2);
+        build_E<P>(L.Bb, L.E);
+        __syncthreads();
+        mul_wave<P, true>(L.A, L.Bb, L.E, acc);          // c_i
+        mul_wave<P, !KEYGEN>(L.A2, L.Bb, L.E, acc2);     // t_{i-1}
+        __syncthreads();
+        store_lds<P>(acc, L.Cb);
+        store_lds<P>(acc2, L.Bb);
+        __syncthreads();
+        finish(k0 + i, L.Cb);
+    }
+    finish(k0, L.Bb);  // c_1 = t_1
+}
+
+// ----------------------------------------------------------------------------
+// Single-operation entry points (used by the kernel-level tests).
+// ----------------------------------------------------------------------------
+template <int P, bool BIG>
+__global__ __launch_bounds__(64) void mul_kernel(int n, const int16_t* a, const int16_t* b, int16_t* c) {
+    __shared__ GroupLds<P> L;
+    const int e = blockIdx.x;
+    if (e >= n) return;
+    int32_t acc[RqShape<P>::R];
+    load_row16<P>(a + (size_t)e * P, L.A);
+    load_row16<P>(b + (size_t)e * P, L.Bb);
+    __syncthreads();
+    build_E<P>(L.Bb, L.E);
+    __syncthreads();
+    mul_wave<P, BIG>(L.A, L.Bb, L.E, acc);
+    store_row<P>(acc, c + (size_t)e * P);
+}
+
+template <int P>
+__global__ __launch_bounds__(64) void recip_q_kernel(int n, const int16_t* a, int16_t* out, int32_t* ok) {
+    __shared__ GroupLds<P> L;
+    const int e = blockIdx.x;
+    if (e >= n) return;
+    load_row16<P>(a + (size_t)e * P, L.Bb);
+    __syncthreads();
+    const int r = recip_wave<P>(L.Bb, L.Bb, L.E);
+    for (int j = lane_id(); j < P; j += 64) out[(size_t)e * P + j] = (int16_t)L.Bb[j];
+    if (lane_id() == 0) ok[e] = r;
+}
+
+// int8 rows [n][p] from bitsliced words [WN][2][n]
+template <int P>
+__global__ __launch_bounds__(256) void unpack_bits_kernel(int n, const uint32_t* bits, int8_t* rows) {
+    const int key = blockIdx.x * blockDim.x + threadIdx.x;
+    if (key >= n) return;
+    for (int k = 0; k < ceil_div(P, 32); k++) {
+        const uint32_t m = bits[(size_t)(2 * k) * n + key], s = bits[(size_t)(2 * k + 1) * n + key];
+        for (int e = 0; e < 32 && 32 * k + e < P; e++)
+            rows[(size_t)key * P + 32 * k + e] = (int8_t)(((m >> e) & 1u) * (1 - 2 * ((s >> e) & 1u)));
+    }
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void sample_small_kernel(Seed seed, uint64_t first_index, int n, int attempt,
+                                                           int8_t* rows) {
+    constexpr int WN = ceil_div(P, 32);
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n * WN) return;
+    const int key = t / WN, k = t % WN;
+    uint32_t m, s;
+    sample_small_word<P>(seed, first_index + (uint64_t)key, attempt, k, m, s);
+    for (int e = 0; e < 32 && 32 * k + e < P; e++)
+        rows[(size_t)key * P + 32 * k + e] = (int8_t)(((m >> e) & 1u) * (1 - 2 * ((s >> e) & 1u)));
+}
+
+__global__ void copy_flags_kernel(int n, const uint8_t* src, int32_t* dst) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = src[i];
+}
+
+__global__ void zero_ints_kernel(int* p, int count) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = 0;
+}
+
+}  // namespace ntrup

@@ -1,0 +1,185 @@
+// Per-key reciprocal in R/3 = (Z/3)[x]/(x^p - x - 1) by constant-time
+// divsteps, bitsliced, one key per lane (or per pair of lanes).
+//
+// KeyGen (OpenSSLNTRU paper, Section 3.1) needs 1/g in R/3 and needs g to be
+// invertible; the paper notes that earlier NTRU Prime software obtained
+// invertibility as a side effect of a constant-time extended-gcd (the
+// Bernstein-Yang divstep algorithm it cites in Section 3.1).  This kernel is
+// that per-key form: a fixed 2p-1 divsteps on (f, g) = (reversed x^p-x-1,
+// reversed g), with secret-independent control flow and memory access.
+//
+// Divstep (delta, f, g), f(0) != 0:
+//   if delta > 0 and g(0) != 0:  (1 - delta, g, (g(0) f - f(0) g) / x)
+//   else                         (1 + delta, f, (f(0) g - g(0) f) / x)
+// with (v, r) updated by the same matrix but multiplied by x instead of
+// divided.  Starting from delta = 1, v = 0, r = 1, after 2p-1 steps g is a
+// unit iff delta = 0, and then 1/g has coefficient i equal to f(0)^-1 v[p-i].
+// Any unit multiple of the (g, r) row may be used at each step; over F_3 the
+// row is taken as s*g + f with s = -g(0)/f(0) (s^2 = 1), so one F_3 add per
+// coefficient suffices.
+//
+// Bitsliced representation: 32 coefficients per word pair (m, s) with
+// m = (c != 0) and s = (c == -1); s is a don't-care where m = 0 inside the
+// loop and canonical (s & m) in every stored output.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ntrup_chacha.h"
+#include "ntrup_params.h"
+
+namespace ntrup {
+
+template <int P, int LPK>
+struct R3Shape {
+    static_assert(LPK == 1 || LPK == 2, "one or two lanes per key");
+    static constexpr int W = ceil_div(P + 1, 32);   // words holding p+1 coefficients
+    static constexpr int W2 = ceil_div(W, LPK);     // words per lane
+    static constexpr int WT = W2 * LPK;             // padded words per polynomial
+    static constexpr int NT = 32 * WT;              // padded bit length
+    static constexpr int D = NT - P;                // reversal offset (>= 1)
+    static constexpr int WN = ceil_div(P, 32);      // words of a natural p-coefficient poly
+    static constexpr int KPW = 64 / LPK;            // keys per wave
+    using Words = uint32_t[W2];                     // one plane of one lane
+    static_assert(D >= 1, "room for x^p");
+};
+
+// Pair-lane helpers: value of the other lane of the pair, of the next lane
+// (lane+1) and of the previous lane (lane-1).  DPP quad permutes stay inside
+// groups of four lanes, so pairs (2k, 2k+1) never see a foreign key.
+__device__ __forceinline__ uint32_t pair_swap(uint32_t x) {
+    // quad_perm [1,0,3,2]
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0xB1, 0xF, 0xF, true);
+}
+__device__ __forceinline__ uint32_t pair_even(uint32_t x) {
+    // quad_perm [0,0,2,2]: both lanes of the pair read the even lane
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0xA0, 0xF, 0xF, true);
+}
+
+// 1 + 2 + 3 input boolean helpers; hipcc turns these into v_bitop3/v_bfi.
+__device__ __forceinline__ uint32_t sel(uint32_t mask, uint32_t a, uint32_t b) {
+    return (a & mask) | (b & ~mask);
+}
+
+// Natural-order bitsliced words of a small polynomial c_0..c_{p-1} staged in
+// LDS as [plane][WT] (plane 0 = m, plane 1 = s), zero beyond p.
+//
+// load_reversed: word k of (reversed c as a degree-(p-1) polynomial), i.e.
+// bit i = c_{p-1-i} for i < p, 0 above.  With Rv = the bit-reversal of the
+// NT-bit natural string, that is (Rv >> D).
+template <int P, int LPK>
+__device__ __forceinline__ uint32_t load_reversed(const uint32_t* nat, int k) {
+    using S = R3Shape<P, LPK>;
+    const int a = k + S::D / 32, o = S::D % 32;
+    uint32_t lo = (a < S::WT) ? __builtin_bitreverse32(nat[S::WT - 1 - a]) : 0u;
+    uint32_t hi = (a + 1 < S::WT) ? __builtin_bitreverse32(nat[S::WT - 2 - a]) : 0u;
+    return o ? __builtin_amdgcn_alignbit(hi, lo, o) : lo;
+}
+
+// Word k of the natural-order output u with u_j = v[p - j] for j < p, taken
+// from the NT-bit string v staged in LDS: u = bitreverse(v) >> (D - 1),
+// masked to p bits.
+template <int P, int LPK>
+__device__ __forceinline__ uint32_t load_output(const uint32_t* vst, int k) {
+    using S = R3Shape<P, LPK>;
+    const int a = k + (S::D - 1) / 32, o = (S::D - 1) % 32;
+    uint32_t lo = (a < S::WT) ? __builtin_bitreverse32(vst[S::WT - 1 - a]) : 0u;
+    uint32_t hi = (a + 1 < S::WT) ? __builtin_bitreverse32(vst[S::WT - 2 - a]) : 0u;
+    uint32_t w = o ? __builtin_amdgcn_alignbit(hi, lo, o) : lo;
+    const int valid = P - 32 * k;
+    if (valid < 32) w &= (valid <= 0) ? 0u : ((1u << valid) - 1u);
+    return w;
+}
+
+// The divstep loop.  In: this lane's W2 words of reversed g (gm, gs).  Out:
+// v words (vm, vs) scaled by f(0)^-1, and the final delta.  h = lane index
+// inside the key (0 or 1); the even lane holds coefficient 0.
+template <int P, int LPK>
+__device__ __forceinline__ int r3_divsteps(typename R3Shape<P, LPK>::Words& gm,
+                                           typename R3Shape<P, LPK>::Words& gs,
+                                           typename R3Shape<P, LPK>::Words& vm,
+                                           typename R3Shape<P, LPK>::Words& vs, int h) {
+    using S = R3Shape<P, LPK>;
+    constexpr int W2 = S::W2;
+    uint32_t fm[W2], fs[W2], rm[W2], rs[W2];
+    // f = reversal of x^p - x - 1 = 1 - x^(p-1) - x^p; r = 1; v = 0.
+#pragma unroll
+    for (int k = 0; k < W2; k++) {
+        const int base = 32 * (h * W2 + k);
+        uint32_t m = 0, s = 0;
+        if (base == 0) m |= 1u;
+#pragma unroll
+        for (int e = P - 1; e <= P; e++)
+            if (e >= base && e < base + 32) { m |= 1u << (e - base); s |= 1u << (e - base); }
+        fm[k] = m;
+        fs[k] = s;
+        rm[k] = (base == 0) ? 1u : 0u;
+        rs[k] = 0;
+        vm[k] = 0;
+        vs[k] = 0;
+    }
+    int delta = 1;
+    const uint32_t hmask = (LPK == 2 && h == 1) ? 0xFFFFFFFFu : 0u;  // odd lane of a pair
+#pragma unroll 1
+    for (int step = 0; step < 2 * P - 1; step++) {
+        // coefficient 0 of f and g lives in bit 0 of word 0 of the even lane
+        uint32_t c0 = (fm[0] & 1u) | ((fs[0] & 1u) << 1) | ((gm[0] & 1u) << 2) | ((gs[0] & 1u) << 3);
+        if (LPK == 2) c0 = pair_even(c0);
+        const uint32_t f0s = (c0 >> 1) & 1u, g0m = (c0 >> 2) & 1u, g0s = (c0 >> 3) & 1u;
+        const uint32_t SW = 0u - ((uint32_t)(delta > 0) & g0m);  // swap mask
+        const uint32_t NZ = 0u - g0m;                             // s != 0
+        const uint32_t NEG = NZ & (0u - (1u ^ g0s ^ f0s));        // s == -1
+        delta = (int)((((uint32_t)(-delta)) & SW) | (((uint32_t)delta) & ~SW)) + 1;
+#pragma unroll
+        for (int k = 0; k < W2; k++) {
+            // g' = s*g + (s != 0 ? f : 0); r' = s*r + (s != 0 ? v : 0)   (F_3 adds)
+            const uint32_t mbf = fm[k] & NZ, mbv = vm[k] & NZ;
+            const uint32_t xg = gs[k] ^ NEG ^ fs[k], xr = rs[k] ^ NEG ^ vs[k];
+            const uint32_t ug = gs[k] ^ NEG ^ mbf, ur = rs[k] ^ NEG ^ mbv;
+            const uint32_t ngm = (gm[k] ^ mbf) | (gm[k] & mbf & ~xg);
+            const uint32_t ngs = sel(gm[k], ug, fs[k]);
+            const uint32_t nrm = (rm[k] ^ mbv) | (rm[k] & mbv & ~xr);
+            const uint32_t nrs = sel(rm[k], ur, vs[k]);
+            // (f, v) <- swap ? (g, r) : (f, v), from the values before the update
+            fm[k] = sel(SW, gm[k], fm[k]);
+            fs[k] = sel(SW, gs[k], fs[k]);
+            const uint32_t nvm = sel(SW, rm[k], vm[k]);
+            const uint32_t nvs = sel(SW, rs[k], vs[k]);
+            gm[k] = ngm; gs[k] = ngs; rm[k] = nrm; rs[k] = nrs;
+            vm[k] = nvm; vs[k] = nvs;
+        }
+        // g <- g / x (one bit down), v <- x v (one bit up)
+        uint32_t gin_m = 0, gin_s = 0, vin_m = 0, vin_s = 0;
+        if (LPK == 2) {
+            // next lane's word 0 feeds the even lane's top word; the odd lane gets 0
+            gin_m = __shfl_down(gm[0], 1) & ~hmask;
+            gin_s = __shfl_down(gs[0], 1) & ~hmask;
+            // previous lane's top word feeds the odd lane's word 0; the even lane gets 0
+            vin_m = __shfl_up(vm[W2 - 1], 1) & hmask;
+            vin_s = __shfl_up(vs[W2 - 1], 1) & hmask;
+        }
+#pragma unroll
+        for (int k = 0; k < W2 - 1; k++) {
+            gm[k] = __builtin_amdgcn_alignbit(gm[k + 1], gm[k], 1);
+            gs[k] = __builtin_amdgcn_alignbit(gs[k + 1], gs[k], 1);
+        }
+        gm[W2 - 1] = __builtin_amdgcn_alignbit(gin_m, gm[W2 - 1], 1);
+        gs[W2 - 1] = __builtin_amdgcn_alignbit(gin_s, gs[W2 - 1], 1);
+#pragma unroll
+        for (int k = W2 - 1; k > 0; k--) {
+            vm[k] = __builtin_amdgcn_alignbit(vm[k], vm[k - 1], 31);
+            vs[k] = __builtin_amdgcn_alignbit(vs[k], vs[k - 1], 31);
+        }
+        vm[0] = __builtin_amdgcn_alignbit(vm[0], vin_m, 31);
+        vs[0] = __builtin_amdgcn_alignbit(vs[0], vin_s, 31);
+    }
+    // scale v by f(0)^-1 = f(0) (f(0) = -1 flips the sign plane); canonical s
+    uint32_t f0 = (fs[0] & 1u);
+    if (LPK == 2) f0 = pair_even(f0);
+    const uint32_t FLIP = 0u - f0;
+#pragma unroll
+    for (int k = 0; k < W2; k++) vs[k] = (vs[k] ^ FLIP) & vm[k];
+    return delta;
+}
+
+}  // namespace ntrup

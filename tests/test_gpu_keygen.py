@@ -1,0 +1,128 @@
+"""End-to-end parity of batched KeyGen (Section 3.1, Algorithm 1) against the
+oracle: encoded pk and sk bytes must be identical key by key.
+
+Configurations: sntrup761 one key at a time (32 keys), batched N=1024 with
+groups of 32 (every key compared), the full N=65536 launch (sampled keys plus
+a property of every key), mixed parameter sets, and invariance of each key
+under group size, launch form and graph replay.
+"""
+import numpy as np
+import pytest
+
+from paper_2106_08759_amd import workloads as wl
+import oracle_pool
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_2106_08759_amd as nk
+    c = nk.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def ref761():
+    return oracle_pool.oracle_keys(wl.SEED, 761, range(1024))
+
+
+def host(t):
+    return t.cpu().numpy()
+
+
+def test_plain_32_keys_bit_exact(ctx, ref761):
+    pk, sk = ctx.keygen_plain(761, wl.SEED, 0, 32)
+    rpk, rsk = oracle_pool.pk_sk_arrays(ref761, range(32))
+    assert np.array_equal(host(pk), rpk)
+    assert np.array_equal(host(sk), rsk)
+
+
+def test_batched_1024_group32_bit_exact(ctx, ref761):
+    ctx.set_config(761, group_size=32)
+    pk, sk = ctx.batch_keygen(761, wl.SEED, 0, 1024)
+    rpk, rsk = oracle_pool.pk_sk_arrays(ref761, range(1024))
+    gpk, gsk = host(pk), host(sk)
+    bad = [i for i in range(1024) if not (np.array_equal(gpk[i], rpk[i]) and np.array_equal(gsk[i], rsk[i]))]
+    assert not bad, bad[:10]
+
+
+@pytest.mark.parametrize("G", [1, 16, 64, 128, 256, 1000])
+def test_group_size_invariance(ctx, ref761, G):
+    ctx.set_config(761, group_size=G)
+    try:
+        pk, sk = ctx.batch_keygen(761, wl.SEED, 0, 300)
+        rpk, rsk = oracle_pool.pk_sk_arrays(ref761, range(300))
+        assert np.array_equal(host(pk), rpk) and np.array_equal(host(sk), rsk)
+    finally:
+        ctx.set_config(761, group_size=32)
+
+
+def test_offset_and_graph_replay(ctx, ref761):
+    """Keys 500..755 alone equal the same keys inside the 1024 batch; a graph
+    replayed several times (with eager work between) gives the same bytes."""
+    import torch
+    rpk, rsk = oracle_pool.pk_sk_arrays(ref761, range(500, 756))
+    ctx.set_config(761, use_graph=1)
+    for rep in range(3):
+        pk, sk = ctx.batch_keygen(761, wl.SEED, 500, 256)
+        torch.cuda.synchronize()
+        assert np.array_equal(host(pk), rpk) and np.array_equal(host(sk), rsk), rep
+    ctx.set_config(761, use_graph=0)
+    pk, sk = ctx.batch_keygen(761, wl.SEED, 500, 256)
+    assert np.array_equal(host(pk), rpk) and np.array_equal(host(sk), rsk)
+    ctx.set_config(761, use_graph=1)
+
+
+@pytest.mark.parametrize("p", [653, 857, 1277])
+def test_other_params_bit_exact(ctx, p):
+    """Every key of a 200-key batch; 653 and 1277 exercise the resample path
+    (about 4-5% of g are not units in R/3 for these p)."""
+    n = 200
+    ref = oracle_pool.oracle_keys(wl.SEED, p, range(n))
+    pk, sk = ctx.batch_keygen(p, wl.SEED, 0, n)
+    rpk, rsk = oracle_pool.pk_sk_arrays(ref, range(n))
+    assert np.array_equal(host(pk), rpk) and np.array_equal(host(sk), rsk)
+    if p in (653, 1277):
+        assert any(ref[i][5] > 1 for i in range(n))  # the resample path ran
+
+
+def test_mixed_parameter_sets(ctx):
+    jobs = [(653, 100, 40), (761, 7, 33), (857, 0, 17), (1277, 3, 21)]
+    outs = ctx.batch_keygen_mixed(wl.SEED, jobs)
+    for (p, first, n), (pk, sk) in zip(jobs, outs):
+        ref = oracle_pool.oracle_keys(wl.SEED, p, range(first, first + n))
+        rpk, rsk = oracle_pool.pk_sk_arrays(ref, range(first, first + n))
+        assert np.array_equal(host(pk), rpk) and np.array_equal(host(sk), rsk), p
+
+
+def test_full_size_65536_sampled_and_property(ctx):
+    """The benchmark launch: N=65536 sntrup761 keys.  256 keys spread over the
+    range are compared with the oracle; for every key, ginv * (h * 3f) = 1 in
+    R/3 and h * 3f has coefficients in {-1, 0, 1} (h*3f = g is small), checked
+    with the library's product (itself pinned by the op tests)."""
+    import torch
+    import paper_2106_08759_amd as nk
+    n = 65536
+    pk, sk = ctx.batch_keygen(761, wl.SEED, 0, n)
+    idx = list(np.linspace(0, n - 1, 256).astype(int))
+    ref = oracle_pool.oracle_keys(wl.SEED, 761, idx)
+    rpk, rsk = oracle_pool.pk_sk_arrays(ref, idx)
+    gpk, gsk = host(pk), host(sk)
+    assert np.array_equal(gpk[idx], rpk) and np.array_equal(gsk[idx], rsk)
+    h = nk.decode_pk(gpk, 761)
+    f, ginv = nk.decode_sk(gsk, 761)
+    assert (np.count_nonzero(f, axis=1) == 286).all()
+    chunk = 8192
+    for s in range(0, n, chunk):
+        hh = torch.from_numpy(h[s:s + chunk]).cuda()
+        f3 = torch.from_numpy(3 * f[s:s + chunk].astype(np.int16)).cuda()
+        g = ctx.mul_rq(761, f3, hh, small_a=True)
+        gh = host(g)
+        assert np.abs(gh).max() <= 1
+        one = ctx.mul_rq(761, g, torch.from_numpy(ginv[s:s + chunk].astype(np.int16)).cuda(), small_a=True)
+        one = host(one) % 3
+        e = np.zeros(761, dtype=one.dtype)
+        e[0] = 1
+        assert (one == e).all()
