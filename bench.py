@@ -1,0 +1,217 @@
+#!/usr/bin/env python3
+"""Benchmark: batched sntrup761 KeyGen on one MI355X.
+
+One step = one pass of the whole hot path over one batch: N = 65536
+sntrup761 keys (Short sampling, R/3 reciprocals with resampling, Montgomery
+groups in R/q, encoded pk/sk written to HBM).  Prints ONE JSON line.
+
+value     keys/s over the timed steps (inputs: a 32-byte seed; outputs stay in
+          HBM; no host copies inside the timed region)
+roofline  the dominant kernel's algorithmic integer ops per launch divided by
+          its average launch time, measured with HIP events recorded on the
+          launch stream during the timed steps, against the int32 VALU peak
+          256 CU x 64 lanes x 2.4 GHz = 39.3 T lane-ops/s
+cpu_baseline  the CPU oracle (plain C, -O2) on the host cores, bounded sample
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import multiprocessing as mp
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+VALU_PEAK = 256 * 64 * 2.4e9  # int32 lane-ops per second
+
+
+def ceil_div(a, b):
+    return -(-a // b)
+
+
+def group_kernel_ops(p: int, n: int, G: int) -> float:
+    """Algorithmic int32 multiply-adds of the Montgomery group kernel for n keys:
+    per group of g keys, 4g-3 ring products of p*p schoolbook MACs (g-1 prefix,
+    g-1 c_i, g-1 t_i, g products h_i) plus one divstep reciprocal of (2p-1)
+    steps x (p+1) coefficients x 4 MACs (f0*g, g0*f, f0*r, g0*v)."""
+    ops = 0.0
+    for start in range(0, n, G):
+        g = min(G, n - start)
+        ops += (4 * g - 3) * p * p + (2 * p - 1) * (p + 1) * 4
+    return ops
+
+
+def r3_kernel_ops(p: int, keys: int) -> float:
+    """Algorithmic 32-bit lane-ops of the bitsliced R/3 divsteps: per key,
+    2p-1 divsteps x ceil((p+1)/32) words x 18 ops (two F_3 scalar
+    multiply-adds at 5 ops, two 2-plane selects, two 2-plane shifts)."""
+    return float(keys) * (2 * p - 1) * ceil_div(p + 1, 32) * 18
+
+
+def short_kernel_ops(p: int, keys: int) -> float:
+    """ChaCha20 blocks (20 rounds x 4 quarter-rounds x 12 ops + 32) for the f
+    stream plus the bitonic network's compare-exchanges (2 ops each)."""
+    ns = 1024 if p <= 1024 else 2048
+    lg = ns.bit_length() - 1
+    ce = ns // 2 * lg * (lg + 1) // 2
+    blocks = ns // 16
+    return float(keys) * (blocks * (20 * 4 * 12 + 32) + 2 * ce)
+
+
+def _cpu_worker(args):
+    p, start, seconds = args
+    import oracle
+    t0 = time.perf_counter()
+    done, idx = 0, start
+    while time.perf_counter() - t0 < seconds:
+        oracle.keygen_range(bytes(range(32)), p, idx, 4)
+        idx += 4
+        done += 4
+    return done, time.perf_counter() - t0
+
+
+def cpu_baseline(p: int, seconds: float) -> dict:
+    import oracle
+    oracle.build()
+    cores = max(1, min(16, os.cpu_count() or 1))
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(cores) as pool:
+        res = pool.map(_cpu_worker, [(p, 10_000_000 * i, seconds) for i in range(cores)])
+    wall = time.perf_counter() - t0
+    keys = sum(r[0] for r in res)
+    return {"value": round(keys / wall, 1), "unit": "keys/s", "cores": cores, "kind": "oracle",
+            "sample": "sntrup%d KeyGen, %d keys over %d processes (disjoint index ranges), %.1f s wall"
+                      % (p, keys, cores, wall)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--p", type=int, default=761)
+    ap.add_argument("--n", type=int, default=65536)
+    ap.add_argument("--group-size", type=int, default=0, help="0: the context's tuned/default value")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the plain-form and N=1024 side measurements")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(keys shard with no exchange step; see the design notes)", file=sys.stderr)
+        sys.exit(2)
+
+    # the CPU oracle runs first, in forked workers, before this process touches the GPU
+    cb = None if args.no_cpu_baseline else cpu_baseline(args.p, args.cpu_seconds)
+
+    import torch
+    import paper_2106_08759_amd as nk
+    from paper_2106_08759_amd import workloads as wl
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    p, n, K, W = args.p, args.n, args.steps, args.warmup
+    ctx = nk.Context(0)
+    if args.group_size:
+        ctx.set_config(p, group_size=args.group_size)
+    cfg = ctx.get_config(p)
+    prm = nk.params(p)
+    ctx.reserve(p, n)
+    pk = torch.empty((n, prm.pk_bytes), dtype=torch.uint8, device="cuda")
+    sk = torch.empty((n, prm.sk_bytes), dtype=torch.uint8, device="cuda")
+
+    for _ in range(W):
+        ctx.batch_keygen(p, wl.SEED, 0, n, pk, sk, check=False)
+    torch.cuda.synchronize()
+    assert ctx.status() == 0
+
+    # timed region: K steps, stage events recorded on the launch stream
+    ctx.timing_begin(K)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record()
+    for _ in range(K):
+        ctx.batch_keygen(p, wl.SEED, 0, n, pk, sk, check=False)
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = ev0.elapsed_time(ev1)
+    stage_ms, timed = ctx.timing_end()
+    assert timed == K
+    rc = ctx.status()
+    assert rc == 0, "keygen status %d" % rc
+    ms_per_step = ms / K
+    keys_per_s = n * K / (ms / 1e3)
+
+    avg = {k: v / K for k, v in stage_ms.items()}
+    ops = {"group": group_kernel_ops(p, n, cfg["group_size"]), "r3_main": r3_kernel_ops(p, n),
+           "sample_short": short_kernel_ops(p, n)}
+    dom = max(ops, key=lambda k: avg[k])
+    achieved = ops[dom] / (avg[dom] / 1e3)
+    kernel_names = {"group": "group_kernel<%d,true>" % p,
+                    "r3_main": "r3_kernel<%d,%d>" % (p, cfg["lanes_per_key"]),
+                    "sample_short": "sample_short_kernel<%d>" % p}
+    roofline = {"bound": "alu", "kernel": kernel_names[dom], "achieved": round(achieved / 1e12, 3),
+                "peak": round(VALU_PEAK / 1e12, 2), "unit": "TOP/s", "frac": round(achieved / VALU_PEAK, 4),
+                "traffic": None,
+                "ops_per_launch": ops[dom], "avg_launch_ms": round(avg[dom], 4)}
+    stage_fracs = {k: {"ms": round(avg[k], 4),
+                       "frac": (round(ops[k] / (avg[k] / 1e3) / VALU_PEAK, 4) if k in ops and avg[k] > 0 else None)}
+                   for k in avg}
+
+    extras = {}
+    if not args.no_extras:
+        # the plain form (one key per launch sequence, Section 3.1) and N=1024 batches
+        m = 32
+        ctx.keygen_plain(p, wl.SEED, 0, m, check=True)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        ctx.keygen_plain(p, wl.SEED, 0, m, check=False)
+        e1.record()
+        torch.cuda.synchronize()
+        plain = m / (e0.elapsed_time(e1) / 1e3)
+        ctx.batch_keygen(p, wl.SEED, 0, 1024, check=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(10):
+            ctx.batch_keygen(p, wl.SEED, 0, 1024, check=False)
+        e1.record()
+        torch.cuda.synchronize()
+        b1024 = 1024 * 10 / (e0.elapsed_time(e1) / 1e3)
+        extras = {"plain32_keys_per_s": round(plain, 1), "batched1024_keys_per_s": round(b1024, 1),
+                  "speedup_batched65536_over_plain": round(keys_per_s / plain, 1)}
+
+    out = {
+        "metric": "sntrup761 keys/sec on 1 MI355X (bit-exact)",
+        "value": round(keys_per_s, 1),
+        "unit": "keys/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic (seeded ChaCha20 keys; seed bytes 0x00..0x1f)",
+        "config": {"workload": "sntrup%d batched KeyGen, N=%d keys, Montgomery group size %d" % (p, n, cfg["group_size"]),
+                   "p": p, "q": prm.q, "w": prm.w, "n_keys": n, "group_size": cfg["group_size"],
+                   "lanes_per_key": cfg["lanes_per_key"], "launch": "stream (events between stages)"},
+        "roofline": roofline,
+        "stages": stage_fracs,
+        "wall_s": round(wall, 3),
+    }
+    out.update(extras)
+    if cb is not None:
+        out["cpu_baseline"] = cb
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -124,6 +124,16 @@ int ntrup_batch_keygen_mixed(ntrup_ctx *ctx, const uint8_t *seed, const ntrup_jo
  * 0, NTRUP_EAGAIN, NTRUP_EFAULT or NTRUP_EIO. */
 int ntrup_ctx_status(ntrup_ctx *ctx, void *stream);
 
+/* Stage timing with HIP events recorded on the launch stream.  After
+ * ntrup_ctx_timing_begin(ctx, m) the next m pipelines (one per job of a keygen
+ * call; graph replay is bypassed meanwhile) record 5 events each, bounding
+ * 4 stages: [0] Short sampler, [1] R/3 main pass, [2] R/3 retry and final
+ * passes, [3] Montgomery group kernel.  ntrup_ctx_timing_end waits for them,
+ * writes the summed milliseconds per stage to ms[0..3] (nstages >= 4), the
+ * number of pipelines timed to *npipelines, and switches timing off. */
+int ntrup_ctx_timing_begin(ntrup_ctx *ctx, int max_pipelines);
+int ntrup_ctx_timing_end(ntrup_ctx *ctx, double *ms, int nstages, int *npipelines);
+
 /* ---- single operations (kernel-level access, used by the tests) ----------
  * All arrays are device pointers, row-major [n][p], centered coefficients.
  * Each runs the same device code as the keygen pipeline.                   */

@@ -73,6 +73,8 @@ def lib() -> ctypes.CDLL:
         "ntrup_keygen_plain": (i32, [vp, i32, ctypes.c_char_p, u64, sz, vp, vp, vp]),
         "ntrup_batch_keygen_mixed": (i32, [vp, ctypes.c_char_p, ctypes.POINTER(_Job), sz, vp]),
         "ntrup_ctx_status": (i32, [vp, vp]),
+        "ntrup_ctx_timing_begin": (i32, [vp, i32]),
+        "ntrup_ctx_timing_end": (i32, [vp, ctypes.POINTER(ctypes.c_double), i32, ctypes.POINTER(i32)]),
         "ntrup_op_mul_rq": (i32, [vp, i32, vp, vp, vp, sz, i32, vp]),
         "ntrup_op_recip_rq": (i32, [vp, i32, vp, vp, vp, sz, vp]),
         "ntrup_op_recip_r3": (i32, [vp, i32, vp, vp, vp, sz, vp]),
@@ -179,6 +181,18 @@ class Context:
 
     def workspace_bytes(self) -> int:
         return lib().ntrup_ctx_workspace_bytes(self._h)
+
+    STAGES = ("sample_short", "r3_main", "r3_retry", "group")
+
+    def timing_begin(self, max_pipelines: int):
+        self._check(lib().ntrup_ctx_timing_begin(self._h, max_pipelines), "timing_begin")
+
+    def timing_end(self):
+        """-> (dict stage -> summed ms, number of pipelines timed)"""
+        ms = (ctypes.c_double * 4)()
+        cnt = ctypes.c_int()
+        self._check(lib().ntrup_ctx_timing_end(self._h, ms, 4, ctypes.byref(cnt)), "timing_end")
+        return dict(zip(self.STAGES, list(ms))), cnt.value
 
     def status(self, stream=None) -> int:
         return lib().ntrup_ctx_status(self._h, _stream(stream))

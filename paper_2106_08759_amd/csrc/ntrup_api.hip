@@ -83,7 +83,14 @@ struct ntrup_ctx {
     GraphKey gkey;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    // stage timing: kStages+1 events per recorded pipeline
+    std::vector<hipEvent_t> tev;
+    int t_max = 0, t_used = 0;
 };
+
+namespace {
+constexpr int kStages = 4;  // sample_short, r3 main pass, r3 retry/final passes, group
+}
 
 namespace {
 
@@ -133,14 +140,25 @@ Seed make_seed(const uint8_t* s) {
 
 unsigned grid_for(size_t items, size_t per_block) { return (unsigned)((items + per_block - 1) / per_block); }
 
+// Event slot of stage boundary b of the current timed pipeline, or null.
+hipEvent_t stage_event(ntrup_ctx* ctx, int b) {
+    if (ctx->t_used >= ctx->t_max) return nullptr;
+    return ctx->tev[(size_t)ctx->t_used * (kStages + 1) + b];
+}
+
 // Enqueue the whole KeyGen pipeline of one job on `st`.  zero_err: also clear
 // the error word (once per API call).
 template <int P>
 int enqueue_keygen(ntrup_ctx* ctx, const ntrup_config& cfg, const Seed& seed, uint64_t first_index,
                    size_t n, uint8_t* pk, uint8_t* sk, const Ws& w, hipStream_t st, bool zero_err) {
     hipLaunchKernelGGL(zero_ints_kernel, dim3(1), dim3(64), 0, st, w.counters, zero_err ? kCounterInts : 16);
+    auto mark = [&](int b) {
+        if (hipEvent_t ev = stage_event(ctx, b)) (void)hipEventRecord(ev, st);
+    };
+    mark(0);
     hipLaunchKernelGGL(sample_short_kernel<P>, dim3(grid_for(n, 4)), dim3(256), 0, st, seed, first_index, (int)n,
                        w.f_rows);
+    mark(1);
     R3Args a;
     a.seed = seed;
     a.first_index = first_index;
@@ -162,7 +180,9 @@ int enqueue_keygen(ntrup_ctx* ctx, const ntrup_config& cfg, const Seed& seed, ui
             hipLaunchKernelGGL((r3_kernel<P, 2>), dim3(grid_for(n, 32)), dim3(64), 0, st, a);
         else
             hipLaunchKernelGGL((r3_kernel<P, 1>), dim3(grid_for(n, 64)), dim3(64), 0, st, a);
+        if (pass == 0) mark(2);
     }
+    mark(3);
     GroupArgs g;
     g.n = (int)n;
     g.G = cfg.group_size;
@@ -176,6 +196,8 @@ int enqueue_keygen(ntrup_ctx* ctx, const ntrup_config& cfg, const Seed& seed, ui
     g.a_in = nullptr;
     g.c_out = nullptr;
     hipLaunchKernelGGL((group_kernel<P, true>), dim3(grid_for(n, cfg.group_size)), dim3(64), 0, st, g);
+    mark(4);
+    if (ctx->t_used < ctx->t_max) ctx->t_used++;
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(ctx, e);
     return 0;
@@ -280,6 +302,7 @@ int ntrup_ctx_destroy(ntrup_ctx* ctx) {
     if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     if (ctx->ws) (void)hipFree(ctx->ws);
+    for (hipEvent_t e : ctx->tev) (void)hipEventDestroy(e);
     delete ctx;
     return 0;
 }
@@ -319,7 +342,8 @@ int ntrup_batch_keygen(ntrup_ctx* ctx, int p, const uint8_t* seed, uint64_t firs
     const Ws w = carve(ctx->ws, p, n);
     hipStream_t st = (hipStream_t)stream;
     ctx->last_err.assign(1, w.counters + 32);
-    if (!cfg.use_graph) return enqueue_dispatch(ctx, p, cfg, sd, first_index, n, pk, sk, w, st, true);
+    if (!cfg.use_graph || ctx->t_max > 0)
+        return enqueue_dispatch(ctx, p, cfg, sd, first_index, n, pk, sk, w, st, true);
 
     GraphKey key;
     memset(&key, 0, sizeof key);
@@ -392,6 +416,39 @@ int ntrup_batch_keygen_mixed(ntrup_ctx* ctx, const uint8_t* seed, const ntrup_jo
                                  jobs[j].n, jobs[j].pk, jobs[j].sk, w, (hipStream_t)stream, true);
         if (r) return r;
     }
+    return 0;
+}
+
+int ntrup_ctx_timing_begin(ntrup_ctx* ctx, int max_pipelines) {
+    if (!ctx || max_pipelines < 0 || max_pipelines > 100000) return NTRUP_EINVAL;
+    if (int r = set_device(ctx)) return r;
+    const size_t need = (size_t)max_pipelines * (kStages + 1);
+    while (ctx->tev.size() < need) {
+        hipEvent_t e;
+        NTRUP_HIP(ctx, hipEventCreate(&e));
+        ctx->tev.push_back(e);
+    }
+    ctx->t_max = max_pipelines;
+    ctx->t_used = 0;
+    return 0;
+}
+
+int ntrup_ctx_timing_end(ntrup_ctx* ctx, double* ms, int nstages, int* npipelines) {
+    if (!ctx || !ms || nstages < kStages) return NTRUP_EINVAL;
+    if (int r = set_device(ctx)) return r;
+    for (int s = 0; s < nstages; s++) ms[s] = 0.0;
+    for (int c = 0; c < ctx->t_used; c++) {
+        hipEvent_t* ev = &ctx->tev[(size_t)c * (kStages + 1)];
+        NTRUP_HIP(ctx, hipEventSynchronize(ev[kStages]));
+        for (int s = 0; s < kStages; s++) {
+            float t = 0.f;
+            NTRUP_HIP(ctx, hipEventElapsedTime(&t, ev[s], ev[s + 1]));
+            ms[s] += t;
+        }
+    }
+    if (npipelines) *npipelines = ctx->t_used;
+    ctx->t_max = 0;
+    ctx->t_used = 0;
     return 0;
 }
 
