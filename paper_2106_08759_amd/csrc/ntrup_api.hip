@@ -285,7 +285,7 @@ int ntrup_ctx_create(ntrup_ctx** out, int device) {
     ntrup_ctx* ctx = new (std::nothrow) ntrup_ctx();
     if (!ctx) return NTRUP_ENOMEM;
     ctx->device = device;
-    for (int i = 0; i < 4; i++) ctx->cfg[i] = ntrup_config{32, kParams[i] > 800 ? 2 : 1, 1, 1};
+    for (int i = 0; i < 4; i++) ctx->cfg[i] = ntrup_config{32, 2, 1, 1};
     if (set_device(ctx) != 0 || hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking) != hipSuccess) {
         delete ctx;
         return NTRUP_EIO;

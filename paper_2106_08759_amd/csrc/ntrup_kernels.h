@@ -272,20 +272,21 @@ struct GroupArgs {
 template <int P>
 struct GroupLds {
     using S = RqShape<P>;
-    int32_t A[S::JP];
-    int32_t A2[S::JP];
-    int32_t Bb[S::JP];
-    int32_t Cb[S::JP];
-    int32_t E[S::ELEN];
+    __attribute__((aligned(16))) int16_t A0[S::JPA];  // broadcast operands
+    __attribute__((aligned(16))) int16_t A1[S::JPA];
+    __attribute__((aligned(16))) int16_t Bb[S::JP];   // big operands (natural order)
+    __attribute__((aligned(16))) int16_t Cb[S::JP];
+    __attribute__((aligned(16))) int32_t Pk[S::PLEN]; // packed Toeplitz window / staging
+    __attribute__((aligned(16))) int16_t Et[S::PLEN + 2];  // window build scratch
 };
 
 template <int P>
-__device__ __forceinline__ void store_lds(const int32_t (&acc)[RqShape<P>::R], int32_t* dst) {
+__device__ __forceinline__ void store_lds(const int32_t (&acc)[RqShape<P>::R], int16_t* dst) {
     constexpr int R = RqShape<P>::R;
     const int lane = lane_id();
 #pragma unroll
     for (int t = 0; t < R; t++)
-        if (R * lane + t < P) dst[R * lane + t] = acc[t];
+        if (R * lane + t < P) dst[R * lane + t] = (int16_t)acc[t];
 }
 
 template <int P>
@@ -299,18 +300,18 @@ __device__ __forceinline__ void store_row(const int32_t (&acc)[RqShape<P>::R], i
 
 // dst[j] = 3 f_j (j < p), 0 up to JP
 template <int P>
-__device__ __forceinline__ void load_3f(const int8_t* row, int32_t* dst) {
-    for (int j = lane_id(); j < RqShape<P>::JP; j += 64) dst[j] = (j < P) ? 3 * (int32_t)row[j] : 0;
+__device__ __forceinline__ void load_3f(const int8_t* row, int16_t* dst) {
+    for (int j = lane_id(); j < RqShape<P>::JP; j += 64) dst[j] = (j < P) ? (int16_t)(3 * (int32_t)row[j]) : 0;
 }
 
 template <int P>
-__device__ __forceinline__ void load_row16(const int16_t* row, int32_t* dst) {
-    for (int j = lane_id(); j < RqShape<P>::JP; j += 64) dst[j] = (j < P) ? (int32_t)row[j] : 0;
+__device__ __forceinline__ void load_row16(const int16_t* row, int16_t* dst) {
+    for (int j = lane_id(); j < RqShape<P>::JP; j += 64) dst[j] = (j < P) ? row[j] : 0;
 }
 
 // dst[j] = g_j from the bitsliced words of key `key`
 template <int P>
-__device__ __forceinline__ void load_g(const uint32_t* gbits, int n, int key, int32_t* dst) {
+__device__ __forceinline__ void load_g(const uint32_t* gbits, int n, int key, int16_t* dst) {
     constexpr int WN = ceil_div(P, 32);
     constexpr int JP = RqShape<P>::JP;
     const int lane = lane_id();
@@ -321,7 +322,7 @@ __device__ __forceinline__ void load_g(const uint32_t* gbits, int n, int key, in
 #pragma unroll 8
         for (int e = 0; e < 32; e++) {
             const int j = 32 * lane + e;
-            if (j < P) dst[j] = (int32_t)((m >> e) & 1u) * (1 - 2 * (int32_t)((s >> e) & 1u));
+            if (j < P) dst[j] = (int16_t)((int32_t)((m >> e) & 1u) * (1 - 2 * (int32_t)((s >> e) & 1u)));
         }
     }
 }
@@ -329,24 +330,25 @@ __device__ __forceinline__ void load_g(const uint32_t* gbits, int n, int key, in
 // pk: h_i + (q-1)/2 as 13-bit little-endian fields; sk: f then 1/g as 2-bit
 // fields c + 1, four per byte, least significant first.
 template <int P>
-__device__ __forceinline__ void encode_key(const GroupArgs& a, int key, const int32_t* H) {
+__device__ __forceinline__ void encode_key(int key, const int16_t* H, uint8_t* pk_out, uint8_t* sk_out,
+                                           const int8_t* f_rows, const uint32_t* ibits, int n) {
     constexpr int Q = Param<P>::q;
     constexpr int PKB = pk_bytes(P), SKH = sk_half_bytes(P);
     const int lane = lane_id();
-    uint8_t* pk = a.pk + (size_t)key * PKB;
+    uint8_t* pk = pk_out + (size_t)key * PKB;
     for (int b = lane; b < PKB; b += 64) {
         const int bit = 8 * b, i0 = bit / 13, o = bit - 13 * i0;
         const uint32_t v0 = (uint32_t)(H[i0] + (Q - 1) / 2);
         const uint32_t v1 = (i0 + 1 < P) ? (uint32_t)(H[i0 + 1] + (Q - 1) / 2) : 0u;
         pk[b] = (uint8_t)((v0 | (v1 << 13)) >> o);
     }
-    uint8_t* sk = a.sk + (size_t)key * 2 * SKH;
-    const int8_t* f = a.f_rows + (size_t)key * P;
+    uint8_t* sk = sk_out + (size_t)key * 2 * SKH;
+    const int8_t* f = f_rows + (size_t)key * P;
     for (int b = lane; b < SKH; b += 64) {
         uint32_t bf = 0, bi = 0;
         const int w = b >> 3, sh = (4 * b) & 31;
-        const uint32_t m = a.ibits[(size_t)(2 * w) * a.n + key] >> sh;
-        const uint32_t s = a.ibits[(size_t)(2 * w + 1) * a.n + key] >> sh;
+        const uint32_t m = ibits[(size_t)(2 * w) * n + key] >> sh;
+        const uint32_t s = ibits[(size_t)(2 * w + 1) * n + key] >> sh;
 #pragma unroll
         for (int e = 0; e < 4; e++) {
             const int i = 4 * b + e;
@@ -365,70 +367,70 @@ __device__ __forceinline__ void encode_key(const GroupArgs& a, int key, const in
 // KEYGEN = false: a_i = a_in rows (big), outputs c_i = 1/a_i to c_out.
 template <int P, bool KEYGEN>
 __global__ __launch_bounds__(64) void group_kernel(GroupArgs args) {
-    using S = RqShape<P>;
-    constexpr int R = S::R;
+    constexpr int R = RqShape<P>::R;
     __shared__ GroupLds<P> L;
     const int lane = lane_id();
+    const int n = args.n;
     const int k0 = blockIdx.x * args.G;
-    const int gsz = min(args.G, args.n - k0);
+    const int gsz = min(args.G, n - k0);
     if (gsz <= 0) return;
-    int32_t acc[R], acc2[R];
-
-    auto load_a = [&](int key, int32_t* dst) {
-        if (KEYGEN) load_3f<P>(args.f_rows + (size_t)key * P, dst);
-        else load_row16<P>(args.a_in + (size_t)key * P, dst);
-    };
+    const int8_t* f_rows = args.f_rows;
+    const int16_t* a_in = args.a_in;
+    int16_t* bscr = args.bscr;
+    int32_t acc1[1][R], acc2[2][R];
 
     // prefix products: b_1 = a_1, b_i = a_i b_{i-1}
-    load_a(k0, L.Bb);
+    if (KEYGEN) load_3f<P>(f_rows + (size_t)k0 * P, L.Bb);
+    else load_row16<P>(a_in + (size_t)k0 * P, L.Bb);
     __syncthreads();
-    for (int j = lane; j < P; j += 64) args.bscr[(size_t)k0 * P + j] = (int16_t)L.Bb[j];
+    for (int j = lane; j < P; j += 64) bscr[(size_t)k0 * P + j] = L.Bb[j];
     for (int i = 1; i < gsz; i++) {
-        load_a(k0 + i, L.A);
-        build_E<P>(L.Bb, L.E);
+        if (KEYGEN) load_3f<P>(f_rows + (size_t)(k0 + i) * P, L.A0);
+        else load_row16<P>(a_in + (size_t)(k0 + i) * P, L.A0);
+        build_window<P>(L.Bb, L.Et, L.Pk);
         __syncthreads();
-        mul_wave<P, !KEYGEN>(L.A, L.Bb, L.E, acc);
+        mul_wave<P, 1, !KEYGEN, false>(L.A0, nullptr, L.Bb, L.Pk, acc1);
         __syncthreads();
-        store_lds<P>(acc, L.Bb);
-        store_row<P>(acc, args.bscr + (size_t)(k0 + i) * P);
+        store_lds<P>(acc1[0], L.Bb);
+        store_row<P>(acc1[0], bscr + (size_t)(k0 + i) * P);
         __syncthreads();
     }
     // one reciprocal per group: t = 1/b_gsz
-    const int ok = recip_wave<P>(L.Bb, L.Bb, L.E);
+    const int ok = recip_wave<P>(L.Bb, L.Bb, L.Pk);
     if (!ok && lane == 0) atomicOr(args.err, 2);
 
-    auto finish = [&](int key, const int32_t* C) {
-        // C holds c = 1/a of this key
+    // back-substitution: c_i = t_i b_{i-1} and t_{i-1} = t_i a_i share the
+    // window of t_i (in Bb); then c_i is consumed (h_i = g_i c_i or output)
+    for (int i = gsz; i >= 1; i--) {
+        const int16_t* C = L.Bb;  // i == 1: c_1 = t_1
+        if (i > 1) {
+            load_row16<P>(bscr + (size_t)(k0 + i - 2) * P, L.A0);
+            if (KEYGEN) load_3f<P>(f_rows + (size_t)(k0 + i - 1) * P, L.A1);
+            else load_row16<P>(a_in + (size_t)(k0 + i - 1) * P, L.A1);
+            build_window<P>(L.Bb, L.Et, L.Pk);
+            __syncthreads();
+            mul_wave<P, 2, true, !KEYGEN>(L.A0, L.A1, L.Bb, L.Pk, acc2);
+            __syncthreads();
+            store_lds<P>(acc2[0], L.Cb);
+            store_lds<P>(acc2[1], L.Bb);
+            __syncthreads();
+            C = L.Cb;
+        }
+        const int key = k0 + i - 1;
         if (KEYGEN) {
-            load_g<P>(args.gbits, args.n, key, L.A);
-            build_E<P>(C, L.E);
+            load_g<P>(args.gbits, n, key, L.A0);
+            build_window<P>(C, L.Et, L.Pk);
             __syncthreads();
-            mul_wave<P, false>(L.A, C, L.E, acc);   // h = g c
+            mul_wave<P, 1, false, false>(L.A0, nullptr, C, L.Pk, acc1);   // h = g c
             __syncthreads();
-            store_lds<P>(acc, L.A2);
+            store_lds<P>(acc1[0], L.A1);
             __syncthreads();
-            encode_key<P>(args, key, L.A2);
+            encode_key<P>(key, L.A1, args.pk, args.sk, f_rows, args.ibits, n);
         } else {
-            for (int j = lane; j < P; j += 64) args.c_out[(size_t)key * P + j] = (int16_t)C[j];
+            for (int j = lane; j < P; j += 64) args.c_out[(size_t)key * P + j] = C[j];
         }
         __syncthreads();
-    };
-
-    // back-substitution: c_i = t_i b_{i-1}, t_{i-1} = t_i a_i (t_i in Bb)
-    for (int i = gsz - 1; i >= 1; i--) {
-        load_row16<P>(args.bscr + (size_t)(k0 + i - 1) * P, L.A);
-        load_a(k0 + i, L.A2);
-        build_E<P>(L.Bb, L.E);
-        __syncthreads();
-        mul_wave<P, true>(L.A, L.Bb, L.E, acc);          // c_i
-        mul_wave<P, !KEYGEN>(L.A2, L.Bb, L.E, acc2);     // t_{i-1}
-        __syncthreads();
-        store_lds<P>(acc, L.Cb);
-        store_lds<P>(acc2, L.Bb);
-        __syncthreads();
-        finish(k0 + i, L.Cb);
     }
-    finish(k0, L.Bb);  // c_1 = t_1
 }
 
 // ----------------------------------------------------------------------------
@@ -439,14 +441,14 @@ __global__ __launch_bounds__(64) void mul_kernel(int n, const int16_t* a, const 
     __shared__ GroupLds<P> L;
     const int e = blockIdx.x;
     if (e >= n) return;
-    int32_t acc[RqShape<P>::R];
-    load_row16<P>(a + (size_t)e * P, L.A);
+    int32_t acc[1][RqShape<P>::R];
+    load_row16<P>(a + (size_t)e * P, L.A0);
     load_row16<P>(b + (size_t)e * P, L.Bb);
     __syncthreads();
-    build_E<P>(L.Bb, L.E);
+    build_window<P>(L.Bb, L.Et, L.Pk);
     __syncthreads();
-    mul_wave<P, BIG>(L.A, L.Bb, L.E, acc);
-    store_row<P>(acc, c + (size_t)e * P);
+    mul_wave<P, 1, BIG, false>(L.A0, nullptr, L.Bb, L.Pk, acc);
+    store_row<P>(acc[0], c + (size_t)e * P);
 }
 
 template <int P>
@@ -456,8 +458,8 @@ __global__ __launch_bounds__(64) void recip_q_kernel(int n, const int16_t* a, in
     if (e >= n) return;
     load_row16<P>(a + (size_t)e * P, L.Bb);
     __syncthreads();
-    const int r = recip_wave<P>(L.Bb, L.Bb, L.E);
-    for (int j = lane_id(); j < P; j += 64) out[(size_t)e * P + j] = (int16_t)L.Bb[j];
+    const int r = recip_wave<P>(L.Bb, L.Bb, L.Pk);
+    for (int j = lane_id(); j < P; j += 64) out[(size_t)e * P + j] = L.Bb[j];
     if (lane_id() == 0) ok[e] = r;
 }
 

@@ -31,14 +31,26 @@ constexpr int sk_bytes(int p) { return 2 * sk_half_bytes(p); }
 // Barrett constant floor(2^32 / q).
 constexpr int32_t barrett_m(int q) { return (int32_t)(((uint64_t)1 << 32) / (uint64_t)q); }
 
+// Signed 24-bit multiply (the low 24 bits of each operand, sign-extended),
+// the semantics of v_mul_i32_i24; exact whenever |a|, |b| < 2^23.
+NTRUP_HD int32_t mul24(int32_t a, int32_t b) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __mul24(a, b);
+#else
+    const int32_t a24 = (int32_t)((uint32_t)a << 8) >> 8, b24 = (int32_t)((uint32_t)b << 8) >> 8;
+    return (int32_t)((int64_t)a24 * b24);
+#endif
+}
+
 // x - q * floor(x * m / 2^32) with m = floor(2^32/q).  For |x| < 2^31 the
-// result lies in (-q/2, 3q/2); for |x| < 2^28 in (-q/16, 17q/16).  Checked
-// exhaustively over all int32 inputs by the host test of this header.
+// result lies in (-q/2, 3q/2); for |x| < 2^28 in (-q/16, 17q/16).  The
+// quotient estimate is below 2^23 in magnitude, so q * t is a 24-bit multiply.
+// Checked exhaustively over all int32 inputs by the host test of this header.
 template <int Q>
 NTRUP_HD int32_t reduce_rough(int32_t x) {
     constexpr int32_t m = barrett_m(Q);
     int32_t t = (int32_t)(((int64_t)x * (int64_t)m) >> 32);
-    return x - t * Q;
+    return x - mul24(t, Q);
 }
 
 // Centered representative in [-(q-1)/2, (q-1)/2] of any |x| < 2^31.

@@ -120,7 +120,7 @@ def test_recip_r3_matches_oracle(ctx, p, lpk):
             if ref is not None:
                 assert np.array_equal(out[i], centered(ref, 3)), (p, lpk, i)
     finally:
-        ctx.set_config(p, lanes_per_key=2 if p > 800 else 1)
+        ctx.set_config(p, lanes_per_key=2)
 
 
 @pytest.mark.parametrize("p,G,n", [(761, 1, 3), (761, 5, 23), (761, 32, 70), (653, 7, 15),
