@@ -55,10 +55,32 @@ __device__ __forceinline__ uint32_t pair_even(uint32_t x) {
     // quad_perm [0,0,2,2]: both lanes of the pair read the even lane
     return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0xA0, 0xF, 0xF, true);
 }
+// lane i reads lane i+1 / lane i-1 within its row of 16 (row_shl:1 / row_shr:1);
+// a pair never straddles a row, and the caller masks the lane that must read 0
+__device__ __forceinline__ uint32_t row_next(uint32_t x) {
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x101, 0xF, 0xF, true);
+}
+__device__ __forceinline__ uint32_t row_prev(uint32_t x) {
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x111, 0xF, 0xF, true);
+}
 
-// 1 + 2 + 3 input boolean helpers; hipcc turns these into v_bitop3/v_bfi.
+// Three-input boolean functions on gfx950 (v_bitop3_b32): the 8-bit table is
+// the function evaluated on the operand patterns 0xF0, 0xCC, 0xAA.
+constexpr uint32_t kSel = (0xF0u & 0xCCu) | (~0xF0u & 0xAAu) & 0xFFu;   // x ? y : z  (0xCA)
+constexpr uint32_t kXor3 = (0xF0u ^ 0xCCu ^ 0xAAu) & 0xFFu;              // x ^ y ^ z  (0x96)
+constexpr uint32_t kAddM = ((0xF0u ^ 0xCCu) | (0xF0u & 0xCCu & ~0xAAu)) & 0xFFu;  // (0x7C)
+static_assert(kSel == 0xCA && kXor3 == 0x96 && kAddM == 0x7C, "bitop3 tables");
+
 __device__ __forceinline__ uint32_t sel(uint32_t mask, uint32_t a, uint32_t b) {
-    return (a & mask) | (b & ~mask);
+    return __builtin_amdgcn_bitop3_b32(mask, a, b, kSel);
+}
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+    return __builtin_amdgcn_bitop3_b32(a, b, c, kXor3);
+}
+// nonzero plane of a + b in F_3 from the nonzero planes x, y and the sign
+// difference z: (x ^ y) | (x & y & ~z)
+__device__ __forceinline__ uint32_t addm(uint32_t x, uint32_t y, uint32_t z) {
+    return __builtin_amdgcn_bitop3_b32(x, y, z, kAddM);
 }
 
 // Natural-order bitsliced words of a small polynomial c_0..c_{p-1} staged in
@@ -134,11 +156,11 @@ __device__ __forceinline__ int r3_divsteps(typename R3Shape<P, LPK>::Words& gm,
         for (int k = 0; k < W2; k++) {
             // g' = s*g + (s != 0 ? f : 0); r' = s*r + (s != 0 ? v : 0)   (F_3 adds)
             const uint32_t mbf = fm[k] & NZ, mbv = vm[k] & NZ;
-            const uint32_t xg = gs[k] ^ NEG ^ fs[k], xr = rs[k] ^ NEG ^ vs[k];
-            const uint32_t ug = gs[k] ^ NEG ^ mbf, ur = rs[k] ^ NEG ^ mbv;
-            const uint32_t ngm = (gm[k] ^ mbf) | (gm[k] & mbf & ~xg);
+            const uint32_t xg = xor3(gs[k], NEG, fs[k]), xr = xor3(rs[k], NEG, vs[k]);
+            const uint32_t ug = xor3(gs[k], NEG, mbf), ur = xor3(rs[k], NEG, mbv);
+            const uint32_t ngm = addm(gm[k], mbf, xg);
             const uint32_t ngs = sel(gm[k], ug, fs[k]);
-            const uint32_t nrm = (rm[k] ^ mbv) | (rm[k] & mbv & ~xr);
+            const uint32_t nrm = addm(rm[k], mbv, xr);
             const uint32_t nrs = sel(rm[k], ur, vs[k]);
             // (f, v) <- swap ? (g, r) : (f, v), from the values before the update
             fm[k] = sel(SW, gm[k], fm[k]);
@@ -152,11 +174,11 @@ __device__ __forceinline__ int r3_divsteps(typename R3Shape<P, LPK>::Words& gm,
         uint32_t gin_m = 0, gin_s = 0, vin_m = 0, vin_s = 0;
         if (LPK == 2) {
             // next lane's word 0 feeds the even lane's top word; the odd lane gets 0
-            gin_m = __shfl_down(gm[0], 1) & ~hmask;
-            gin_s = __shfl_down(gs[0], 1) & ~hmask;
+            gin_m = row_next(gm[0]) & ~hmask;
+            gin_s = row_next(gs[0]) & ~hmask;
             // previous lane's top word feeds the odd lane's word 0; the even lane gets 0
-            vin_m = __shfl_up(vm[W2 - 1], 1) & hmask;
-            vin_s = __shfl_up(vs[W2 - 1], 1) & hmask;
+            vin_m = row_prev(vm[W2 - 1]) & hmask;
+            vin_s = row_prev(vs[W2 - 1]) & hmask;
         }
 #pragma unroll
         for (int k = 0; k < W2 - 1; k++) {
