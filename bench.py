@@ -102,6 +102,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the plain-form and N=1024 side measurements")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="run one device-to-device copy of this many MiB first (HBM counter calibration)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -127,6 +129,13 @@ def main():
     pk = torch.empty((n, prm.pk_bytes), dtype=torch.uint8, device="cuda")
     sk = torch.empty((n, prm.sk_bytes), dtype=torch.uint8, device="cuda")
 
+    if args.calib_copy_mib:
+        src = torch.ones(args.calib_copy_mib << 20, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     for _ in range(W):
         ctx.batch_keygen(p, wl.SEED, 0, n, pk, sk, check=False)
     torch.cuda.synchronize()
