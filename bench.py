@@ -98,7 +98,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--p", type=int, default=761)
     ap.add_argument("--n", type=int, default=65536)
-    ap.add_argument("--group-size", type=int, default=0, help="0: the context's tuned/default value")
+    ap.add_argument("--group-size", type=int, default=0, help="0: autotuned (see --no-autotune)")
+    ap.add_argument("--no-autotune", action="store_true", help="use the library defaults instead of tuning")
+    ap.add_argument("--serve-seconds", type=float, default=3.0)
+    ap.add_argument("--serve-rate", type=float, default=3e5)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the plain-form and N=1024 side measurements")
@@ -121,8 +124,12 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     p, n, K, W = args.p, args.n, args.steps, args.warmup
     ctx = nk.Context(0)
+    tuned = None
     if args.group_size:
         ctx.set_config(p, group_size=args.group_size)
+    elif not args.no_autotune:
+        from paper_2106_08759_amd import autotune
+        tuned = autotune.tune(ctx, p, n, reps=2)
     cfg = ctx.get_config(p)
     prm = nk.params(p)
     ctx.reserve(p, n)
@@ -200,6 +207,31 @@ def main():
         b1024 = 1024 * 10 / (e0.elapsed_time(e1) / 1e3)
         extras = {"plain32_keys_per_s": round(plain, 1), "batched1024_keys_per_s": round(b1024, 1),
                   "speedup_batched65536_over_plain": round(keys_per_s / plain, 1)}
+        # mixed parameter sets in one graph launch: 16384 keys each of 653/761/857/1277
+        jobs = [(653, 0, 16384), (761, 0, 16384), (857, 0, 16384), (1277, 0, 16384)]
+        if not args.no_autotune:
+            from paper_2106_08759_amd import autotune
+            for q_ in (653, 857, 1277):
+                autotune.tune(ctx, q_, 16384, reps=2)
+        ctx.batch_keygen_mixed(wl.SEED, jobs, check=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(5):
+            ctx.batch_keygen_mixed(wl.SEED, jobs, check=False)
+        e1.record()
+        torch.cuda.synchronize()
+        assert ctx.status() == 0
+        mixed_ms = e0.elapsed_time(e1) / 5
+        extras["mixed_4x16384"] = {"keys_per_s": round(4 * 16384 / mixed_ms * 1e3, 1), "ms": round(mixed_ms, 3),
+                                   "launch": "one hipGraph, four concurrent branches"}
+        # serving: Poisson arrivals, 70/20/10 % sntrup761/857/1277, device pools
+        if args.serve_seconds > 0:
+            from paper_2106_08759_amd import serve
+            rep = serve.serve(serve.GpuBackend(0), args.serve_rate, args.serve_seconds,
+                              {761: 0.7, 857: 0.2, 1277: 0.1}, wl.SEED,
+                              refill={761: 16384, 857: 8192, 1277: 4096}, blocks=4)
+            extras["serving"] = {k: rep[k] for k in ("rate_req_per_s", "seconds", "requests", "served",
+                                                     "keys_per_s", "latency_ms", "workspaces", "hbm_used_bytes")}
 
     out = {
         "metric": "sntrup761 keys/sec on 1 MI355X (bit-exact)",
@@ -222,6 +254,10 @@ def main():
         "wall_s": round(wall, 3),
     }
     out.update(extras)
+    if tuned is not None:
+        out["autotune"] = {"config": tuned["config"], "cached": tuned["cached"],
+                           "table_ms": {"G%d/L%d/R%d" % (r["group_size"], r["lanes_per_key"], r["retry_passes"]): r["ms"]
+                                        for r in tuned.get("table", [])}}
     if cb is not None:
         out["cpu_baseline"] = cb
     print(json.dumps(out), flush=True)

@@ -1,0 +1,143 @@
+"""Autotuner for the batched KeyGen pipeline.
+
+Knobs (see ``ntrup_config`` in include/ntrupkg.h):
+  group_size     Montgomery group size G (Section 2.2's n): larger groups
+                 share one R/q reciprocal among more keys but leave fewer
+                 independent groups to fill the GPU;
+  lanes_per_key  one or two lanes per key for the bitsliced R/3 divsteps;
+  retry_passes   compacted passes over keys whose g was not invertible
+                 before the final looping pass (matters for p = 653, 1277).
+
+The product tile (R = ceil(p/64) outputs per lane) and the reduction chunk
+are fixed by p and need no tuning.  Every candidate is timed on the real
+pipeline with HIP events on the launch stream; the winner per
+(device, p, N rounded up to a power of two) is cached as JSON.
+"""
+from __future__ import annotations
+
+import json
+import os
+import time
+
+GROUP_SIZES = (16, 32, 64, 128, 256)
+
+
+def cache_path() -> str:
+    return os.environ.get("NTRUPKG_TUNE_CACHE",
+                          os.path.join(os.path.expanduser("~"), ".cache", "ntrupkg", "autotune.json"))
+
+
+def bucket(n: int) -> int:
+    b = 1
+    while b < n:
+        b <<= 1
+    return b
+
+
+def candidates(p: int, n: int):
+    """Configurations worth timing for n keys of degree p."""
+    out = []
+    gs = [g for g in GROUP_SIZES if g <= max(16, n)]
+    lpks = (2,) if p > 800 else (1, 2)          # one lane per key spills for large p
+    retries = (0, 1, 2) if p in (653, 1277) else (1,)
+    for g in gs:
+        for l in lpks:
+            for r in retries:
+                out.append({"group_size": g, "lanes_per_key": l, "retry_passes": r})
+    return out
+
+
+def _key(device_name: str, p: int, n: int) -> str:
+    return "%s|p=%d|n<=%d" % (device_name, p, bucket(n))
+
+
+def load_cache(path: str | None = None) -> dict:
+    path = path or cache_path()
+    try:
+        with open(path) as fh:
+            return json.load(fh)
+    except (OSError, ValueError):
+        return {}
+
+
+def save_cache(data: dict, path: str | None = None) -> None:
+    path = path or cache_path()
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    tmp = path + ".tmp%d" % os.getpid()
+    with open(tmp, "w") as fh:
+        json.dump(data, fh, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def lookup(device_name: str, p: int, n: int, path: str | None = None):
+    return load_cache(path).get(_key(device_name, p, n))
+
+
+def time_config(ctx, p: int, n: int, cfg: dict, seed: bytes, reps: int, pk, sk) -> float:
+    """Mean milliseconds per call of the pipeline under cfg (eager launches)."""
+    import torch
+    ctx.set_config(p, use_graph=0, **cfg)
+    ctx.batch_keygen(p, seed, 0, n, pk, sk, check=True)  # warm
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        ctx.batch_keygen(p, seed, 0, n, pk, sk, check=False)
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def tune(ctx, p: int, n: int, seed: bytes | None = None, reps: int = 3, force: bool = False,
+         path: str | None = None, use_graph: int = 1) -> dict:
+    """Pick and apply the fastest configuration for (p, n); returns the cache entry
+    {"config": ..., "ms": ..., "keys_per_s": ..., "table": [...], "cached": bool}."""
+    import torch
+    from . import params
+    from .workloads import SEED
+
+    seed = seed or SEED
+    dev = torch.cuda.get_device_name(ctx.device)
+    key = _key(dev, p, n)
+    data = load_cache(path)
+    if not force and key in data:
+        entry = dict(data[key])
+        ctx.set_config(p, use_graph=use_graph, **entry["config"])
+        entry["cached"] = True
+        return entry
+    prm = params(p)
+    pk = torch.empty((n, prm.pk_bytes), dtype=torch.uint8, device="cuda:%d" % ctx.device)
+    sk = torch.empty((n, prm.sk_bytes), dtype=torch.uint8, device="cuda:%d" % ctx.device)
+    ctx.reserve(p, n)
+    table = []
+    for cfg in candidates(p, n):
+        ms = time_config(ctx, p, n, cfg, seed, reps, pk, sk)
+        table.append(dict(cfg, ms=round(ms, 4)))
+    best = min(table, key=lambda r: r["ms"])
+    cfg = {k: best[k] for k in ("group_size", "lanes_per_key", "retry_passes")}
+    entry = {"config": cfg, "ms": best["ms"], "keys_per_s": round(n / best["ms"] * 1e3, 1),
+             "n": n, "table": table, "tuned_at": time.strftime("%Y-%m-%dT%H:%M:%S")}
+    data[key] = entry
+    save_cache(data, path)
+    ctx.set_config(p, use_graph=use_graph, **cfg)
+    return dict(entry, cached=False)
+
+
+def main(argv=None):
+    import argparse
+    ap = argparse.ArgumentParser(description="tune the batched KeyGen pipeline")
+    ap.add_argument("--p", type=int, nargs="+", default=[761])
+    ap.add_argument("--n", type=int, default=65536)
+    ap.add_argument("--reps", type=int, default=3)
+    ap.add_argument("--force", action="store_true")
+    args = ap.parse_args(argv)
+    from . import Context
+    ctx = Context(0)
+    for p in args.p:
+        e = tune(ctx, p, args.n, reps=args.reps, force=args.force)
+        print(json.dumps({"p": p, "n": args.n, "config": e["config"], "ms": e["ms"],
+                          "keys_per_s": e["keys_per_s"], "cached": e["cached"]}))
+
+
+if __name__ == "__main__":
+    main()

@@ -57,17 +57,33 @@ Ws carve(void* base, int p, size_t n) {
     return w;
 }
 
-struct GraphKey {
+// One keygen job as enqueued: parameter set, key range, outputs, the config
+// in force and the job's offset in the context workspace.
+struct JobDesc {
     int p;
-    size_t n;
     uint64_t first_index;
-    uint32_t seed[8];
-    void* pk;
-    void* sk;
-    void* ws;
+    size_t n;
+    uint8_t* pk;
+    uint8_t* sk;
     ntrup_config cfg;
-    bool operator==(const GraphKey& o) const { return memcmp(this, &o, sizeof(*this)) == 0; }
+    size_t ws_off;
+    bool operator==(const JobDesc& o) const {
+        return p == o.p && first_index == o.first_index && n == o.n && pk == o.pk && sk == o.sk &&
+               memcmp(&cfg, &o.cfg, sizeof cfg) == 0 && ws_off == o.ws_off;
+    }
 };
+
+// What a captured graph was built from; a call replays it when all match.
+struct GraphKey {
+    uint32_t seed[8];
+    void* ws;
+    std::vector<JobDesc> jobs;
+    bool operator==(const GraphKey& o) const {
+        return memcmp(seed, o.seed, sizeof seed) == 0 && ws == o.ws && jobs == o.jobs;
+    }
+};
+
+constexpr int kJobStreams = 4;  // concurrent branches of a mixed call
 
 }  // namespace
 
@@ -79,6 +95,9 @@ struct ntrup_ctx {
     ntrup_config cfg[4];
     std::vector<int*> last_err;     // error words of the last keygen call
     hipStream_t cap_stream = nullptr;
+    hipStream_t job_streams[kJobStreams] = {};
+    hipEvent_t fork_event = nullptr;
+    std::vector<hipEvent_t> join_events;
     bool have_graph = false;
     GraphKey gkey;
     hipGraph_t graph = nullptr;
@@ -286,8 +305,11 @@ int ntrup_ctx_create(ntrup_ctx** out, int device) {
     if (!ctx) return NTRUP_ENOMEM;
     ctx->device = device;
     for (int i = 0; i < 4; i++) ctx->cfg[i] = ntrup_config{32, 2, 1, 1};
-    if (set_device(ctx) != 0 || hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking) != hipSuccess) {
-        delete ctx;
+    bool ok = set_device(ctx) == 0 && hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking) == hipSuccess;
+    for (int i = 0; ok && i < kJobStreams; i++)
+        ok = hipStreamCreateWithFlags(&ctx->job_streams[i], hipStreamNonBlocking) == hipSuccess;
+    if (!ok) {
+        ntrup_ctx_destroy(ctx);
         return NTRUP_EIO;
     }
     *out = ctx;
@@ -301,6 +323,10 @@ int ntrup_ctx_destroy(ntrup_ctx* ctx) {
     if (ctx->exec) (void)hipGraphExecDestroy(ctx->exec);
     if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+    for (hipStream_t js : ctx->job_streams)
+        if (js) (void)hipStreamDestroy(js);
+    if (ctx->fork_event) (void)hipEventDestroy(ctx->fork_event);
+    for (hipEvent_t e : ctx->join_events) (void)hipEventDestroy(e);
     if (ctx->ws) (void)hipFree(ctx->ws);
     for (hipEvent_t e : ctx->tev) (void)hipEventDestroy(e);
     delete ctx;
@@ -333,45 +359,13 @@ int ntrup_set_config(ntrup_ctx* ctx, int p, const ntrup_config* cfg) {
 
 int ntrup_batch_keygen(ntrup_ctx* ctx, int p, const uint8_t* seed, uint64_t first_index, size_t n, uint8_t* pk,
                        uint8_t* sk, void* stream) {
-    if (!ctx || !seed) return NTRUP_EINVAL;
-    if (int r = check_job(p, n, pk, sk)) return r;
-    if (int r = set_device(ctx)) return r;
-    if (int r = ensure_ws(ctx, ws_bytes(p, n))) return r;
-    const ntrup_config& cfg = ctx->cfg[param_slot(p)];
-    const Seed sd = make_seed(seed);
-    const Ws w = carve(ctx->ws, p, n);
-    hipStream_t st = (hipStream_t)stream;
-    ctx->last_err.assign(1, w.counters + 32);
-    if (!cfg.use_graph || ctx->t_max > 0)
-        return enqueue_dispatch(ctx, p, cfg, sd, first_index, n, pk, sk, w, st, true);
-
-    GraphKey key;
-    memset(&key, 0, sizeof key);
-    key.p = p;
-    key.n = n;
-    key.first_index = first_index;
-    memcpy(key.seed, sd.k, sizeof key.seed);
-    key.pk = pk;
-    key.sk = sk;
-    key.ws = ctx->ws;
-    key.cfg = cfg;
-    if (!ctx->have_graph || !(ctx->gkey == key)) {
-        if (ctx->exec) { (void)hipGraphExecDestroy(ctx->exec); ctx->exec = nullptr; }
-        if (ctx->graph) { (void)hipGraphDestroy(ctx->graph); ctx->graph = nullptr; }
-        ctx->have_graph = false;
-        NTRUP_HIP(ctx, hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
-        int r = enqueue_dispatch(ctx, p, cfg, sd, first_index, n, pk, sk, w, ctx->cap_stream, true);
-        hipGraph_t g = nullptr;
-        hipError_t e = hipStreamEndCapture(ctx->cap_stream, &g);
-        if (r) { if (g) (void)hipGraphDestroy(g); return r; }
-        if (e != hipSuccess) return hip_fail(ctx, e);
-        ctx->graph = g;
-        NTRUP_HIP(ctx, hipGraphInstantiate(&ctx->exec, g, nullptr, nullptr, 0));
-        ctx->gkey = key;
-        ctx->have_graph = true;
-    }
-    NTRUP_HIP(ctx, hipGraphLaunch(ctx->exec, st));
-    return 0;
+    ntrup_job job;
+    job.p = p;
+    job.first_index = first_index;
+    job.n = n;
+    job.pk = pk;
+    job.sk = sk;
+    return ntrup_batch_keygen_mixed(ctx, seed, &job, 1, stream);
 }
 
 int ntrup_keygen_plain(ntrup_ctx* ctx, int p, const uint8_t* seed, uint64_t first_index, size_t n, uint8_t* pk,
@@ -395,27 +389,80 @@ int ntrup_keygen_plain(ntrup_ctx* ctx, int p, const uint8_t* seed, uint64_t firs
     return 0;
 }
 
+namespace {
+
+// Enqueue every job on `st`: one job directly; several jobs on the context's
+// job streams between a fork and a join on `st`, so that they run
+// concurrently (and form parallel branches when captured).
+int enqueue_jobs(ntrup_ctx* ctx, const Seed& sd, const std::vector<JobDesc>& jobs, hipStream_t st) {
+    if (jobs.size() == 1) {
+        const JobDesc& j = jobs[0];
+        return enqueue_dispatch(ctx, j.p, j.cfg, sd, j.first_index, j.n, j.pk, j.sk,
+                                carve((char*)ctx->ws + j.ws_off, j.p, j.n), st, true);
+    }
+    if (!ctx->fork_event) NTRUP_HIP(ctx, hipEventCreateWithFlags(&ctx->fork_event, hipEventDisableTiming));
+    while (ctx->join_events.size() < jobs.size()) {
+        hipEvent_t e;
+        NTRUP_HIP(ctx, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        ctx->join_events.push_back(e);
+    }
+    NTRUP_HIP(ctx, hipEventRecord(ctx->fork_event, st));
+    for (size_t i = 0; i < jobs.size(); i++) {
+        const JobDesc& j = jobs[i];
+        hipStream_t js = ctx->job_streams[i % kJobStreams];
+        NTRUP_HIP(ctx, hipStreamWaitEvent(js, ctx->fork_event, 0));
+        int r = enqueue_dispatch(ctx, j.p, j.cfg, sd, j.first_index, j.n, j.pk, j.sk,
+                                 carve((char*)ctx->ws + j.ws_off, j.p, j.n), js, true);
+        if (r) return r;
+        NTRUP_HIP(ctx, hipEventRecord(ctx->join_events[i], js));
+    }
+    for (size_t i = 0; i < jobs.size(); i++) NTRUP_HIP(ctx, hipStreamWaitEvent(st, ctx->join_events[i], 0));
+    return 0;
+}
+
+}  // namespace
+
 int ntrup_batch_keygen_mixed(ntrup_ctx* ctx, const uint8_t* seed, const ntrup_job* jobs, size_t njobs,
                              void* stream) {
-    if (!ctx || !seed || !jobs || njobs == 0) return NTRUP_EINVAL;
+    if (!ctx || !seed || !jobs || njobs == 0 || njobs > 4096) return NTRUP_EINVAL;
+    std::vector<JobDesc> jd(njobs);
     size_t total = 0;
+    bool graph = ctx->t_max == 0;
     for (size_t j = 0; j < njobs; j++) {
         if (int r = check_job(jobs[j].p, jobs[j].n, jobs[j].pk, jobs[j].sk)) return r;
+        jd[j] = JobDesc{jobs[j].p, jobs[j].first_index, jobs[j].n, jobs[j].pk, jobs[j].sk,
+                        ctx->cfg[param_slot(jobs[j].p)], total};
+        graph = graph && jd[j].cfg.use_graph;
         total += ws_bytes(jobs[j].p, jobs[j].n);
     }
     if (int r = set_device(ctx)) return r;
     if (int r = ensure_ws(ctx, total)) return r;
     const Seed sd = make_seed(seed);
     ctx->last_err.clear();
-    char* base = (char*)ctx->ws;
-    for (size_t j = 0; j < njobs; j++) {
-        const Ws w = carve(base, jobs[j].p, jobs[j].n);
-        base += ws_bytes(jobs[j].p, jobs[j].n);
-        ctx->last_err.push_back(w.counters + 32);
-        int r = enqueue_dispatch(ctx, jobs[j].p, ctx->cfg[param_slot(jobs[j].p)], sd, jobs[j].first_index,
-                                 jobs[j].n, jobs[j].pk, jobs[j].sk, w, (hipStream_t)stream, true);
-        if (r) return r;
+    for (const JobDesc& j : jd) ctx->last_err.push_back(carve((char*)ctx->ws + j.ws_off, j.p, j.n).counters + 32);
+    hipStream_t st = (hipStream_t)stream;
+    if (!graph) return enqueue_jobs(ctx, sd, jd, st);
+
+    GraphKey key;
+    memcpy(key.seed, sd.k, sizeof key.seed);
+    key.ws = ctx->ws;
+    key.jobs = jd;
+    if (!ctx->have_graph || !(ctx->gkey == key)) {
+        if (ctx->exec) { (void)hipGraphExecDestroy(ctx->exec); ctx->exec = nullptr; }
+        if (ctx->graph) { (void)hipGraphDestroy(ctx->graph); ctx->graph = nullptr; }
+        ctx->have_graph = false;
+        NTRUP_HIP(ctx, hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
+        int r = enqueue_jobs(ctx, sd, jd, ctx->cap_stream);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(ctx->cap_stream, &g);
+        if (r) { if (g) (void)hipGraphDestroy(g); return r; }
+        if (e != hipSuccess) return hip_fail(ctx, e);
+        ctx->graph = g;
+        NTRUP_HIP(ctx, hipGraphInstantiate(&ctx->exec, g, nullptr, nullptr, 0));
+        ctx->gkey = key;
+        ctx->have_graph = true;
     }
+    NTRUP_HIP(ctx, hipGraphLaunch(ctx->exec, st));
     return 0;
 }
 

@@ -1,0 +1,31 @@
+"""Autotuner host logic (no GPU): candidate sets, size buckets, JSON cache."""
+import json
+
+from paper_2106_08759_amd import autotune
+
+
+def test_candidates_cover_the_knobs():
+    c761 = autotune.candidates(761, 65536)
+    assert {c["group_size"] for c in c761} == set(autotune.GROUP_SIZES)
+    assert {c["lanes_per_key"] for c in c761} == {1, 2}
+    assert {c["retry_passes"] for c in c761} == {1}
+    c1277 = autotune.candidates(1277, 65536)
+    assert {c["lanes_per_key"] for c in c1277} == {2}
+    assert {c["retry_passes"] for c in c1277} == {0, 1, 2}
+    assert all(c["group_size"] <= 16 for c in autotune.candidates(761, 10))
+
+
+def test_bucket():
+    assert [autotune.bucket(n) for n in (1, 2, 3, 1000, 1024, 1025, 65536)] == [1, 2, 4, 1024, 1024, 2048, 65536]
+
+
+def test_cache_roundtrip(tmp_path):
+    path = str(tmp_path / "tune.json")
+    assert autotune.load_cache(path) == {}
+    entry = {"config": {"group_size": 32, "lanes_per_key": 2, "retry_passes": 1}, "ms": 5.6}
+    data = {autotune._key("dev", 761, 60000): entry}
+    autotune.save_cache(data, path)
+    assert json.load(open(path)) == data
+    assert autotune.lookup("dev", 761, 65536, path) == entry      # same bucket
+    assert autotune.lookup("dev", 761, 70000, path) is None       # next bucket
+    assert autotune.lookup("other", 761, 65536, path) is None
