@@ -256,7 +256,7 @@ def main():
     out.update(extras)
     if tuned is not None:
         out["autotune"] = {"config": tuned["config"], "cached": tuned["cached"],
-                           "table_ms": {"G%d/L%d/R%d" % (r["group_size"], r["lanes_per_key"], r["retry_passes"]): r["ms"]
+                           "table_ms": {"G%d/L%d/R%dx%dx%d" % (r["group_size"], r["lanes_per_key"], r["retry_passes"], r["retry_lanes_per_key"], r["retry_parallel_attempts"]): r["ms"]
                                         for r in tuned.get("table", [])}}
     if cb is not None:
         out["cpu_baseline"] = cb

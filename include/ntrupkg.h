@@ -76,15 +76,26 @@ int ntrup_last_hip_error(const ntrup_ctx *ctx);
 const char *ntrup_strerror(int code);
 
 /* Tuning knobs per parameter set (chosen by the autotuner or the caller).
- *   group_size     Montgomery group size G, 1..1024 (Section 2.2's n)
- *   lanes_per_key  1 or 2 lanes per key for the R/3 divsteps
- *   retry_passes   0..8 compacted passes over keys whose g was not a unit,
- *                  before a final pass that loops up to 64 draws
- *   use_graph      replay the pipeline from a captured hipGraph when the
- *                  call's arguments repeat                                   */
+ *   group_size           Montgomery group size G, 1..1024 (Section 2.2's n)
+ *   lanes_per_key        1, 2, 4 or 8 lanes per key for the main R/3 pass
+ *                        (more lanes: fewer registers and lower latency per
+ *                        key, more cross-lane overhead)
+ *   retry_lanes_per_key  1, 2, 4 or 8 lanes per key for the retry passes,
+ *                        which are latency-bound (few keys, a full divstep
+ *                        run each)
+ *   retry_parallel_attempts  1, 2, 4 or 8 consecutive g draws tried side by
+ *                        side per key in the retry passes (the lowest unit
+ *                        wins, so outputs do not change); retry lanes per
+ *                        key times this is at most 64
+ *   retry_passes         0..8 compacted passes over keys whose g was not a
+ *                        unit, before a final pass that loops up to 64 draws
+ *   use_graph            replay the pipeline from a captured hipGraph when
+ *                        the call's arguments repeat                        */
 typedef struct {
     int group_size;
     int lanes_per_key;
+    int retry_lanes_per_key;
+    int retry_parallel_attempts;
     int retry_passes;
     int use_graph;
 } ntrup_config;

@@ -4,9 +4,13 @@ Knobs (see ``ntrup_config`` in include/ntrupkg.h):
   group_size     Montgomery group size G (Section 2.2's n): larger groups
                  share one R/q reciprocal among more keys but leave fewer
                  independent groups to fill the GPU;
-  lanes_per_key  one or two lanes per key for the bitsliced R/3 divsteps;
-  retry_passes   compacted passes over keys whose g was not invertible
-                 before the final looping pass (matters for p = 653, 1277).
+  lanes_per_key  1, 2, 4 or 8 lanes per key for the bitsliced R/3 divsteps
+                 of the main pass;
+  retry_lanes_per_key, retry_parallel_attempts, retry_passes
+                 lanes per key, g draws tried side by side per key, and the
+                 number of compacted passes for the keys whose g was not
+                 invertible (matters for p = 653, 1277, where the retry
+                 passes are latency-bound).
 
 The product tile (R = ceil(p/64) outputs per lane) and the reduction chunk
 are fixed by p and need no tuning.  Every candidate is timed on the real
@@ -38,12 +42,14 @@ def candidates(p: int, n: int):
     """Configurations worth timing for n keys of degree p."""
     out = []
     gs = [g for g in GROUP_SIZES if g <= max(16, n)]
-    lpks = (2,) if p > 800 else (1, 2)          # one lane per key spills for large p
-    retries = (0, 1, 2) if p in (653, 1277) else (1,)
+    lpks = (2, 4) if p > 800 else (1, 2, 4)      # one lane per key spills for large p
+    # (retry passes, retry lanes per key, attempts side by side)
+    retry = [(1, 8, 4)] if p not in (653, 1277) else [(1, 8, 2), (1, 8, 4), (1, 8, 8), (0, 8, 4), (1, 4, 4)]
     for g in gs:
         for l in lpks:
-            for r in retries:
-                out.append({"group_size": g, "lanes_per_key": l, "retry_passes": r})
+            for r, rl, ra in retry:
+                out.append({"group_size": g, "lanes_per_key": l, "retry_passes": r, "retry_lanes_per_key": rl,
+                            "retry_parallel_attempts": ra})
     return out
 
 
@@ -114,7 +120,8 @@ def tune(ctx, p: int, n: int, seed: bytes | None = None, reps: int = 3, force: b
         ms = time_config(ctx, p, n, cfg, seed, reps, pk, sk)
         table.append(dict(cfg, ms=round(ms, 4)))
     best = min(table, key=lambda r: r["ms"])
-    cfg = {k: best[k] for k in ("group_size", "lanes_per_key", "retry_passes")}
+    cfg = {k: best[k] for k in ("group_size", "lanes_per_key", "retry_passes", "retry_lanes_per_key",
+                                "retry_parallel_attempts")}
     entry = {"config": cfg, "ms": best["ms"], "keys_per_s": round(n / best["ms"] * 1e3, 1),
              "n": n, "table": table, "tuned_at": time.strftime("%Y-%m-%dT%H:%M:%S")}
     data[key] = entry

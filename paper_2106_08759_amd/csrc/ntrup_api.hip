@@ -159,6 +159,20 @@ Seed make_seed(const uint8_t* s) {
 
 unsigned grid_for(size_t items, size_t per_block) { return (unsigned)((items + per_block - 1) / per_block); }
 
+// R/3 pass over up to n keys with lpk lanes per key and a.spec attempts per
+// key side by side: 64 / (lpk * spec) keys per one-wave block.
+template <int P>
+void launch_r3(int lpk, size_t n, const R3Args& a, hipStream_t st) {
+    const size_t kpb = (size_t)(64 / lpk / a.spec);
+    const dim3 grid(grid_for(n, kpb)), blk(64);
+    switch (lpk) {
+        case 1: hipLaunchKernelGGL((r3_kernel<P, 1>), grid, blk, 0, st, a); break;
+        case 2: hipLaunchKernelGGL((r3_kernel<P, 2>), grid, blk, 0, st, a); break;
+        case 4: hipLaunchKernelGGL((r3_kernel<P, 4>), grid, blk, 0, st, a); break;
+        default: hipLaunchKernelGGL((r3_kernel<P, 8>), grid, blk, 0, st, a); break;
+    }
+}
+
 // Event slot of stage boundary b of the current timed pipeline, or null.
 hipEvent_t stage_event(ntrup_ctx* ctx, int b) {
     if (ctx->t_used >= ctx->t_max) return nullptr;
@@ -194,11 +208,9 @@ int enqueue_keygen(ntrup_ctx* ctx, const ntrup_config& cfg, const Seed& seed, ui
         a.count_in = pass == 0 ? nullptr : w.counters + (pass - 1);
         a.list_out = last ? nullptr : w.lists[pass & 1];
         a.count_out = last ? nullptr : w.counters + pass;
-        a.max_rounds = last ? kMaxAttempts : 1;
-        if (cfg.lanes_per_key == 2)
-            hipLaunchKernelGGL((r3_kernel<P, 2>), dim3(grid_for(n, 32)), dim3(64), 0, st, a);
-        else
-            hipLaunchKernelGGL((r3_kernel<P, 1>), dim3(grid_for(n, 64)), dim3(64), 0, st, a);
+        a.spec = pass == 0 ? 1 : cfg.retry_parallel_attempts;
+        a.max_rounds = last ? ceil_div(kMaxAttempts, a.spec) : 1;
+        launch_r3<P>(pass == 0 ? cfg.lanes_per_key : cfg.retry_lanes_per_key, n, a, st);
         if (pass == 0) mark(2);
     }
     mark(3);
@@ -234,8 +246,11 @@ int enqueue_dispatch(ntrup_ctx* ctx, int p, const ntrup_config& cfg, const Seed&
 }
 
 bool valid_config(const ntrup_config& c) {
-    return c.group_size >= 1 && c.group_size <= 1024 && (c.lanes_per_key == 1 || c.lanes_per_key == 2) &&
-           c.retry_passes >= 0 && c.retry_passes <= 8 && (c.use_graph == 0 || c.use_graph == 1);
+    auto lpk_ok = [](int l) { return l == 1 || l == 2 || l == 4 || l == 8; };
+    return c.group_size >= 1 && c.group_size <= 1024 && lpk_ok(c.lanes_per_key) &&
+           lpk_ok(c.retry_lanes_per_key) && lpk_ok(c.retry_parallel_attempts) &&
+           c.retry_lanes_per_key * c.retry_parallel_attempts <= 64 && c.retry_passes >= 0 &&
+           c.retry_passes <= 8 && (c.use_graph == 0 || c.use_graph == 1);
 }
 
 int check_job(int p, size_t n, const void* pk, const void* sk) {
@@ -251,13 +266,13 @@ int op_recip_r3(ntrup_ctx* ctx, int lpk, const int8_t* a, int8_t* out, int32_t* 
     memset(&ar, 0, sizeof ar);
     ar.n = (int)n;
     ar.max_rounds = 1;
+    ar.spec = 1;
     ar.attempts = w.attempts;
     ar.gbits = w.gbits;
     ar.ibits = w.ibits;
     ar.err = w.counters + 32;
     ar.g_in = a;
-    if (lpk == 2) hipLaunchKernelGGL((r3_kernel<P, 2>), dim3(grid_for(n, 32)), dim3(64), 0, st, ar);
-    else hipLaunchKernelGGL((r3_kernel<P, 1>), dim3(grid_for(n, 64)), dim3(64), 0, st, ar);
+    launch_r3<P>(lpk, n, ar, st);
     hipLaunchKernelGGL(unpack_bits_kernel<P>, dim3(grid_for(n, 256)), dim3(256), 0, st, (int)n, w.ibits, out);
     hipLaunchKernelGGL(copy_flags_kernel, dim3(grid_for(n, 256)), dim3(256), 0, st, (int)n, w.attempts, ok);
     NTRUP_HIP(ctx, hipGetLastError());
@@ -304,7 +319,7 @@ int ntrup_ctx_create(ntrup_ctx** out, int device) {
     ntrup_ctx* ctx = new (std::nothrow) ntrup_ctx();
     if (!ctx) return NTRUP_ENOMEM;
     ctx->device = device;
-    for (int i = 0; i < 4; i++) ctx->cfg[i] = ntrup_config{32, 2, 1, 1};
+    for (int i = 0; i < 4; i++) ctx->cfg[i] = ntrup_config{32, 2, 8, 4, 1, 1};
     bool ok = set_device(ctx) == 0 && hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking) == hipSuccess;
     for (int i = 0; ok && i < kJobStreams; i++)
         ok = hipStreamCreateWithFlags(&ctx->job_streams[i], hipStreamNonBlocking) == hipSuccess;

@@ -145,6 +145,7 @@ struct R3Args {
     uint64_t first_index;
     int n;
     int max_rounds;
+    int spec;               // attempts tried side by side per key (1, 2, 4 or 8)
     const int* list_in;     // null in the main pass
     const int* count_in;
     int* list_out;          // null: no further pass
@@ -156,6 +157,11 @@ struct R3Args {
     const int8_t* g_in;     // test entry: explicit g rows [n][p], one round, no sampling
 };
 
+// A wave holds 64/LPK lane groups; with spec = A, consecutive runs of A
+// groups work on one key and try attempts base, base+1, ..., base+A-1 at
+// once.  The key takes the lowest attempt whose g is a unit -- exactly the
+// g a one-at-a-time resampling loop would accept -- so the outputs do not
+// depend on A.  Keys whose A attempts all fail move on by A attempts.
 template <int P, int LPK>
 __global__ __launch_bounds__(64) void r3_kernel(R3Args args) {
     using S = R3Shape<P, LPK>;
@@ -163,14 +169,17 @@ __global__ __launch_bounds__(64) void r3_kernel(R3Args args) {
     __shared__ uint32_t nat[S::KPW][2][S::WT];
     __shared__ uint32_t vst[S::KPW][2][S::WT];
     const int lane = lane_id();
-    const int kl = lane / LPK;
-    const int h = (LPK == 2) ? (lane & 1) : 0;
-    const int slot = blockIdx.x * S::KPW + kl;
-    int key = -1, attempt = 0;
+    const int A = args.spec;
+    const int gi = lane / LPK;            // lane group
+    const int a = gi % A;                 // which of the key's side-by-side attempts
+    const int h = lane & (LPK - 1);
+    const int kw = gi / A;                // key slot in the wave
+    const int slot = blockIdx.x * (S::KPW / A) + kw;
+    int key = -1, base = 0;
     if (args.list_in) {
         if (slot < *args.count_in) {
             key = args.list_in[slot];
-            attempt = args.attempts[key];
+            base = args.attempts[key];
         }
     } else if (slot < args.n) {
         key = slot;
@@ -178,10 +187,11 @@ __global__ __launch_bounds__(64) void r3_kernel(R3Args args) {
     if (__ballot(key >= 0) == 0) return;  // whole wave idle
     const uint64_t index = args.first_index + (uint64_t)(key < 0 ? 0 : key);
     bool done = key < 0;
-    uint32_t* nm = nat[kl][0];
-    uint32_t* ns = nat[kl][1];
+    uint32_t* nm = nat[gi][0];
+    uint32_t* ns = nat[gi][1];
     for (int round = 0; round < args.max_rounds; round++) {
         if (__all(done)) break;
+        const int attempt = base + a;
         for (int k = h; k < S::WT; k += LPK) {
             uint32_t mw = 0, sw = 0;
             if (k < S::WN) {
@@ -195,7 +205,7 @@ __global__ __launch_bounds__(64) void r3_kernel(R3Args args) {
                         sw |= (uint32_t)(c < 0) << e;
                     }
                 } else {
-                    sample_small_word<P>(args.seed, index, attempt, k, mw, sw);
+                    sample_small_word<P>(args.seed, index, attempt < kMaxAttempts ? attempt : 0, k, mw, sw);
                 }
             }
             nm[k] = mw;
@@ -211,25 +221,32 @@ __global__ __launch_bounds__(64) void r3_kernel(R3Args args) {
         const int delta = r3_divsteps<P, LPK>(gm, gs, vm, vs, h);
 #pragma unroll
         for (int k = 0; k < W2; k++) {
-            vst[kl][0][h * W2 + k] = vm[k];
-            vst[kl][1][h * W2 + k] = vs[k];
+            vst[gi][0][h * W2 + k] = vm[k];
+            vst[gi][1][h * W2 + k] = vs[k];
         }
         __syncthreads();
-        if (!done && delta == 0) {
-            for (int k = h; k < S::WN; k += LPK) {
-                const size_t n = (size_t)args.n;
-                args.gbits[(size_t)(2 * k) * n + key] = nm[k];
-                args.gbits[(size_t)(2 * k + 1) * n + key] = ns[k] & nm[k];
-                args.ibits[(size_t)(2 * k) * n + key] = load_output<P, LPK>(vst[kl][0], k);
-                args.ibits[(size_t)(2 * k + 1) * n + key] = load_output<P, LPK>(vst[kl][1], k);
+        // lowest successful attempt of each key, from the group leaders' votes
+        const unsigned long long votes = __ballot(h == 0 && !done && delta == 0 && attempt < kMaxAttempts);
+        uint32_t mine = 0;
+        for (int b = 0; b < A; b++) mine |= (uint32_t)((votes >> ((kw * A + b) * LPK)) & 1ull) << b;
+        if (!done && mine) {
+            const int win = __builtin_ctz(mine);
+            if (a == win) {
+                for (int k = h; k < S::WN; k += LPK) {
+                    const size_t n = (size_t)args.n;
+                    args.gbits[(size_t)(2 * k) * n + key] = nm[k];
+                    args.gbits[(size_t)(2 * k + 1) * n + key] = ns[k] & nm[k];
+                    args.ibits[(size_t)(2 * k) * n + key] = load_output<P, LPK>(vst[gi][0], k);
+                    args.ibits[(size_t)(2 * k + 1) * n + key] = load_output<P, LPK>(vst[gi][1], k);
+                }
+                if (h == 0) args.attempts[key] = (uint8_t)(base + win + 1);
             }
-            if (h == 0) args.attempts[key] = (uint8_t)(attempt + 1);
             done = true;
         } else if (!done) {
-            attempt++;
-            if (attempt >= kMaxAttempts || args.g_in) {
-                if (h == 0) {
-                    args.attempts[key] = args.g_in ? (uint8_t)0 : (uint8_t)attempt;
+            base += A;
+            if (base >= kMaxAttempts || args.g_in) {
+                if (h == 0 && a == 0) {
+                    args.attempts[key] = args.g_in ? (uint8_t)0 : (uint8_t)kMaxAttempts;
                     if (!args.g_in) atomicOr(args.err, 1);
                 }
                 done = true;
@@ -237,15 +254,15 @@ __global__ __launch_bounds__(64) void r3_kernel(R3Args args) {
         }
         __syncthreads();
     }
-    const bool pend = !done && h == 0;
+    const bool pend = !done && h == 0 && a == 0;
     if (args.list_out) {
-        if (pend) args.attempts[key] = (uint8_t)attempt;
+        if (pend) args.attempts[key] = (uint8_t)base;
         const unsigned long long m = __ballot(pend);
         if (m) {
-            int base = 0;
-            if (lane == 0) base = atomicAdd(args.count_out, __popcll(m));
-            base = __shfl(base, 0);
-            if (pend) args.list_out[base + __popcll(m & ((1ull << lane) - 1ull))] = key;
+            int b0 = 0;
+            if (lane == 0) b0 = atomicAdd(args.count_out, __popcll(m));
+            b0 = __shfl(b0, 0);
+            if (pend) args.list_out[b0 + __popcll(m & ((1ull << lane) - 1ull))] = key;
         }
     } else if (pend) {
         atomicOr(args.err, 1);

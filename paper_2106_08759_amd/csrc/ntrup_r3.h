@@ -32,7 +32,7 @@ namespace ntrup {
 
 template <int P, int LPK>
 struct R3Shape {
-    static_assert(LPK == 1 || LPK == 2, "one or two lanes per key");
+    static_assert(LPK == 1 || LPK == 2 || LPK == 4 || LPK == 8, "1, 2, 4 or 8 lanes per key");
     static constexpr int W = ceil_div(P + 1, 32);   // words holding p+1 coefficients
     static constexpr int W2 = ceil_div(W, LPK);     // words per lane
     static constexpr int WT = W2 * LPK;             // padded words per polynomial
@@ -44,16 +44,15 @@ struct R3Shape {
     static_assert(D >= 1, "room for x^p");
 };
 
-// Pair-lane helpers: value of the other lane of the pair, of the next lane
-// (lane+1) and of the previous lane (lane-1).  DPP quad permutes stay inside
-// groups of four lanes, so pairs (2k, 2k+1) never see a foreign key.
-__device__ __forceinline__ uint32_t pair_swap(uint32_t x) {
-    // quad_perm [1,0,3,2]
-    return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0xB1, 0xF, 0xF, true);
-}
-__device__ __forceinline__ uint32_t pair_even(uint32_t x) {
-    // quad_perm [0,0,2,2]: both lanes of the pair read the even lane
-    return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0xA0, 0xF, 0xF, true);
+// Lane-group helpers.  A key owns LPK consecutive lanes (LPK divides 16, so a
+// group never straddles a DPP row); group_first broadcasts the value of the
+// group's first lane: DPP quad permutes for LPK <= 4, ds_bpermute beyond.
+template <int LPK>
+__device__ __forceinline__ uint32_t group_first(uint32_t x) {
+    if (LPK == 1) return x;
+    if (LPK == 2) return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0xA0, 0xF, 0xF, true);  // [0,0,2,2]
+    if (LPK == 4) return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x00, 0xF, 0xF, true);  // [0,0,0,0]
+    return (uint32_t)__shfl((int)x, (int)(threadIdx.x & 63) & ~(LPK - 1));
 }
 // lane i reads lane i+1 / lane i-1 within its row of 16 (row_shl:1 / row_shr:1);
 // a pair never straddles a row, and the caller masks the lane that must read 0
@@ -141,12 +140,13 @@ __device__ __forceinline__ int r3_divsteps(typename R3Shape<P, LPK>::Words& gm,
         vs[k] = 0;
     }
     int delta = 1;
-    const uint32_t hmask = (LPK == 2 && h == 1) ? 0xFFFFFFFFu : 0u;  // odd lane of a pair
+    const uint32_t last = (h == LPK - 1) ? 0xFFFFFFFFu : 0u;   // top lane of the key's group
+    const uint32_t first = (h == 0) ? 0xFFFFFFFFu : 0u;        // bottom lane
 #pragma unroll 1
     for (int step = 0; step < 2 * P - 1; step++) {
         // coefficient 0 of f and g lives in bit 0 of word 0 of the even lane
         uint32_t c0 = (fm[0] & 1u) | ((fs[0] & 1u) << 1) | ((gm[0] & 1u) << 2) | ((gs[0] & 1u) << 3);
-        if (LPK == 2) c0 = pair_even(c0);
+        c0 = group_first<LPK>(c0);
         const uint32_t f0s = (c0 >> 1) & 1u, g0m = (c0 >> 2) & 1u, g0s = (c0 >> 3) & 1u;
         const uint32_t SW = 0u - ((uint32_t)(delta > 0) & g0m);  // swap mask
         const uint32_t NZ = 0u - g0m;                             // s != 0
@@ -172,13 +172,13 @@ __device__ __forceinline__ int r3_divsteps(typename R3Shape<P, LPK>::Words& gm,
         }
         // g <- g / x (one bit down), v <- x v (one bit up)
         uint32_t gin_m = 0, gin_s = 0, vin_m = 0, vin_s = 0;
-        if (LPK == 2) {
-            // next lane's word 0 feeds the even lane's top word; the odd lane gets 0
-            gin_m = row_next(gm[0]) & ~hmask;
-            gin_s = row_next(gs[0]) & ~hmask;
-            // previous lane's top word feeds the odd lane's word 0; the even lane gets 0
-            vin_m = row_prev(vm[W2 - 1]) & hmask;
-            vin_s = row_prev(vs[W2 - 1]) & hmask;
+        if (LPK > 1) {
+            // the next lane's word 0 feeds this lane's top word (0 for the top lane)
+            gin_m = row_next(gm[0]) & ~last;
+            gin_s = row_next(gs[0]) & ~last;
+            // the previous lane's top word feeds this lane's word 0 (0 for the bottom lane)
+            vin_m = row_prev(vm[W2 - 1]) & ~first;
+            vin_s = row_prev(vs[W2 - 1]) & ~first;
         }
 #pragma unroll
         for (int k = 0; k < W2 - 1; k++) {
@@ -197,7 +197,7 @@ __device__ __forceinline__ int r3_divsteps(typename R3Shape<P, LPK>::Words& gm,
     }
     // scale v by f(0)^-1 = f(0) (f(0) = -1 flips the sign plane); canonical s
     uint32_t f0 = (fs[0] & 1u);
-    if (LPK == 2) f0 = pair_even(f0);
+    f0 = group_first<LPK>(f0);
     const uint32_t FLIP = 0u - f0;
 #pragma unroll
     for (int k = 0; k < W2; k++) vs[k] = (vs[k] ^ FLIP) & vm[k];

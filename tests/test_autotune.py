@@ -7,11 +7,14 @@ from paper_2106_08759_amd import autotune
 def test_candidates_cover_the_knobs():
     c761 = autotune.candidates(761, 65536)
     assert {c["group_size"] for c in c761} == set(autotune.GROUP_SIZES)
-    assert {c["lanes_per_key"] for c in c761} == {1, 2}
+    assert {c["lanes_per_key"] for c in c761} == {1, 2, 4}
     assert {c["retry_passes"] for c in c761} == {1}
     c1277 = autotune.candidates(1277, 65536)
-    assert {c["lanes_per_key"] for c in c1277} == {2}
-    assert {c["retry_passes"] for c in c1277} == {0, 1, 2}
+    assert {c["lanes_per_key"] for c in c1277} == {2, 4}
+    assert {c["retry_passes"] for c in c1277} == {0, 1}
+    assert {c["retry_lanes_per_key"] for c in c1277} == {4, 8}
+    assert {c["retry_parallel_attempts"] for c in c1277} == {2, 4, 8}
+    assert all(c["retry_lanes_per_key"] * c["retry_parallel_attempts"] <= 64 for c in c1277)
     assert all(c["group_size"] <= 16 for c in autotune.candidates(761, 10))
 
 
@@ -22,7 +25,7 @@ def test_bucket():
 def test_cache_roundtrip(tmp_path):
     path = str(tmp_path / "tune.json")
     assert autotune.load_cache(path) == {}
-    entry = {"config": {"group_size": 32, "lanes_per_key": 2, "retry_passes": 1}, "ms": 5.6}
+    entry = {"config": {"group_size": 32, "lanes_per_key": 2, "retry_passes": 1, "retry_lanes_per_key": 8}, "ms": 5.6}
     data = {autotune._key("dev", 761, 60000): entry}
     autotune.save_cache(data, path)
     assert json.load(open(path)) == data

@@ -88,6 +88,26 @@ def test_other_params_bit_exact(ctx, p):
         assert any(ref[i][5] > 1 for i in range(n))  # the resample path ran
 
 
+@pytest.mark.parametrize("p", [653, 1277])
+def test_resampling_invariance(ctx, p):
+    """The retry passes may try several g draws of a key side by side and may
+    use any lane layout; the accepted g is always the first unit, so the keys
+    are the oracle's whatever the retry configuration."""
+    n = 300
+    ref = oracle_pool.oracle_keys(wl.SEED, p, range(n))
+    rpk, rsk = oracle_pool.pk_sk_arrays(ref, range(n))
+    assert sum(ref[i][5] > 1 for i in range(n)) >= 5
+    base = ctx.get_config(p)
+    try:
+        for lpk, rl, ra, rp in [(2, 2, 1, 0), (4, 8, 2, 1), (8, 8, 8, 2), (1, 4, 4, 0), (2, 8, 4, 3)]:
+            ctx.set_config(p, lanes_per_key=lpk, retry_lanes_per_key=rl, retry_parallel_attempts=ra,
+                           retry_passes=rp)
+            pk, sk = ctx.batch_keygen(p, wl.SEED, 0, n)
+            assert np.array_equal(host(pk), rpk) and np.array_equal(host(sk), rsk), (lpk, rl, ra, rp)
+    finally:
+        ctx.set_config(p, **{k: v for k, v in base.items()})
+
+
 def test_mixed_parameter_sets(ctx):
     jobs = [(653, 100, 40), (761, 7, 33), (857, 0, 17), (1277, 3, 21)]
     outs = ctx.batch_keygen_mixed(wl.SEED, jobs)
