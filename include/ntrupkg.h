@@ -90,7 +90,10 @@ const char *ntrup_strerror(int code);
  *   retry_passes         0..8 compacted passes over keys whose g was not a
  *                        unit, before a final pass that loops up to 64 draws
  *   use_graph            replay the pipeline from a captured hipGraph when
- *                        the call's arguments repeat                        */
+ *                        the call's arguments repeat
+ *   product_engine       R/q products on the vector units (0: v_dot2 Toeplitz
+ *                        dot products) or on the int8 matrix cores (1: block
+ *                        Toeplitz MFMA with two 7-bit limbs); both exact    */
 typedef struct {
     int group_size;
     int lanes_per_key;
@@ -98,6 +101,7 @@ typedef struct {
     int retry_parallel_attempts;
     int retry_passes;
     int use_graph;
+    int product_engine;
 } ntrup_config;
 
 int ntrup_get_config(const ntrup_ctx *ctx, int p, ntrup_config *cfg);
@@ -150,7 +154,8 @@ int ntrup_ctx_timing_end(ntrup_ctx *ctx, double *ms, int nstages, int *npipeline
  * Each runs the same device code as the keygen pipeline.                   */
 
 /* c = a * b in R/q (Section 2.1).  |a|,|b| <= (q-1)/2.  small_a != 0 selects
- * the small-operand path, which requires |a_j| <= 3. */
+ * the small-operand path, which requires |a_j| <= 3.  The product engine is
+ * the context's product_engine for p. */
 int ntrup_op_mul_rq(ntrup_ctx *ctx, int p, const int16_t *a, const int16_t *b, int16_t *c, size_t n,
                     int small_a, void *stream);
 

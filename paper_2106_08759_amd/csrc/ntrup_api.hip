@@ -226,7 +226,10 @@ int enqueue_keygen(ntrup_ctx* ctx, const ntrup_config& cfg, const Seed& seed, ui
     g.err = w.counters + 32;
     g.a_in = nullptr;
     g.c_out = nullptr;
-    hipLaunchKernelGGL((group_kernel<P, true>), dim3(grid_for(n, cfg.group_size)), dim3(64), 0, st, g);
+    if (cfg.product_engine == 1)
+        hipLaunchKernelGGL((group_mfma_kernel<P, true>), dim3(grid_for(n, cfg.group_size)), dim3(64), 0, st, g);
+    else
+        hipLaunchKernelGGL((group_kernel<P, true>), dim3(grid_for(n, cfg.group_size)), dim3(64), 0, st, g);
     mark(4);
     if (ctx->t_used < ctx->t_max) ctx->t_used++;
     hipError_t e = hipGetLastError();
@@ -250,7 +253,8 @@ bool valid_config(const ntrup_config& c) {
     return c.group_size >= 1 && c.group_size <= 1024 && lpk_ok(c.lanes_per_key) &&
            lpk_ok(c.retry_lanes_per_key) && lpk_ok(c.retry_parallel_attempts) &&
            c.retry_lanes_per_key * c.retry_parallel_attempts <= 64 && c.retry_passes >= 0 &&
-           c.retry_passes <= 8 && (c.use_graph == 0 || c.use_graph == 1);
+           c.retry_passes <= 8 && (c.use_graph == 0 || c.use_graph == 1) &&
+           (c.product_engine == 0 || c.product_engine == 1);
 }
 
 int check_job(int p, size_t n, const void* pk, const void* sk) {
@@ -319,7 +323,7 @@ int ntrup_ctx_create(ntrup_ctx** out, int device) {
     ntrup_ctx* ctx = new (std::nothrow) ntrup_ctx();
     if (!ctx) return NTRUP_ENOMEM;
     ctx->device = device;
-    for (int i = 0; i < 4; i++) ctx->cfg[i] = ntrup_config{32, 2, 8, 4, 1, 1};
+    for (int i = 0; i < 4; i++) ctx->cfg[i] = ntrup_config{32, 2, 8, 4, 1, 1, 1};
     bool ok = set_device(ctx) == 0 && hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking) == hipSuccess;
     for (int i = 0; ok && i < kJobStreams; i++)
         ok = hipStreamCreateWithFlags(&ctx->job_streams[i], hipStreamNonBlocking) == hipSuccess;
@@ -537,10 +541,13 @@ int ntrup_op_mul_rq(ntrup_ctx* ctx, int p, const int16_t* a, const int16_t* b, i
     if (int r = set_device(ctx)) return r;
     hipStream_t st = (hipStream_t)stream;
     const dim3 grid((unsigned)n), blk(64);
+    const bool mfma = ctx->cfg[param_slot(p)].product_engine == 1;
 #define NTRUP_MUL(PP)                                                                              \
     case PP:                                                                                       \
-        if (small_a) hipLaunchKernelGGL((mul_kernel<PP, false>), grid, blk, 0, st, (int)n, a, b, c); \
-        else hipLaunchKernelGGL((mul_kernel<PP, true>), grid, blk, 0, st, (int)n, a, b, c);          \
+        if (mfma && small_a) hipLaunchKernelGGL((mulm_kernel<PP, false>), grid, blk, 0, st, (int)n, a, b, c); \
+        else if (mfma) hipLaunchKernelGGL((mulm_kernel<PP, true>), grid, blk, 0, st, (int)n, a, b, c);    \
+        else if (small_a) hipLaunchKernelGGL((mul_kernel<PP, false>), grid, blk, 0, st, (int)n, a, b, c); \
+        else hipLaunchKernelGGL((mul_kernel<PP, true>), grid, blk, 0, st, (int)n, a, b, c);               \
         break;
     switch (p) { NTRUP_MUL(653) NTRUP_MUL(761) NTRUP_MUL(857) NTRUP_MUL(1277) }
 #undef NTRUP_MUL
@@ -598,12 +605,14 @@ int ntrup_op_batch_inv_rq(ntrup_ctx* ctx, int p, const int16_t* a, int16_t* out,
     ctx->last_err.assign(1, w.counters + 32);
     hipLaunchKernelGGL(zero_ints_kernel, dim3(1), dim3(64), 0, st, w.counters, kCounterInts);
     const dim3 grid(grid_for(n, group_size)), blk(64);
-    switch (p) {
-        case 653: hipLaunchKernelGGL((group_kernel<653, false>), grid, blk, 0, st, g); break;
-        case 761: hipLaunchKernelGGL((group_kernel<761, false>), grid, blk, 0, st, g); break;
-        case 857: hipLaunchKernelGGL((group_kernel<857, false>), grid, blk, 0, st, g); break;
-        case 1277: hipLaunchKernelGGL((group_kernel<1277, false>), grid, blk, 0, st, g); break;
-    }
+    const bool mfma = ctx->cfg[param_slot(p)].product_engine == 1;
+#define NTRUP_INV(PP)                                                                      \
+    case PP:                                                                               \
+        if (mfma) hipLaunchKernelGGL((group_mfma_kernel<PP, false>), grid, blk, 0, st, g); \
+        else hipLaunchKernelGGL((group_kernel<PP, false>), grid, blk, 0, st, g);           \
+        break;
+    switch (p) { NTRUP_INV(653) NTRUP_INV(761) NTRUP_INV(857) NTRUP_INV(1277) }
+#undef NTRUP_INV
     NTRUP_HIP(ctx, hipGetLastError());
     return 0;
 }

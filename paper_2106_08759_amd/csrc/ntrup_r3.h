@@ -65,7 +65,7 @@ __device__ __forceinline__ uint32_t row_prev(uint32_t x) {
 
 // Three-input boolean functions on gfx950 (v_bitop3_b32): the 8-bit table is
 // the function evaluated on the operand patterns 0xF0, 0xCC, 0xAA.
-constexpr uint32_t kSel = (0xF0u & 0xCCu) | (~0xF0u & 0xAAu) & 0xFFu;   // x ? y : z  (0xCA)
+constexpr uint32_t kSel = ((0xF0u & 0xCCu) | (~0xF0u & 0xAAu)) & 0xFFu;   // x ? y : z  (0xCA)
 constexpr uint32_t kXor3 = (0xF0u ^ 0xCCu ^ 0xAAu) & 0xFFu;              // x ^ y ^ z  (0x96)
 constexpr uint32_t kAddM = ((0xF0u ^ 0xCCu) | (0xF0u & 0xCCu & ~0xAAu)) & 0xFFu;  // (0x7C)
 static_assert(kSel == 0xCA && kXor3 == 0x96 && kAddM == 0x7C, "bitop3 tables");

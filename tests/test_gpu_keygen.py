@@ -108,6 +108,25 @@ def test_resampling_invariance(ctx, p):
         ctx.set_config(p, **{k: v for k, v in base.items()})
 
 
+@pytest.mark.parametrize("engine", [0, 1])
+@pytest.mark.parametrize("p", [653, 761, 857, 1277])
+def test_product_engine_bit_exact(ctx, p, engine):
+    """The group kernel with its products on the vector units (0) or on the
+    int8 matrix cores (1) gives the oracle's keys, for several group sizes
+    including ragged last groups."""
+    n = 200
+    ref = oracle_pool.oracle_keys(wl.SEED, p, range(n))
+    rpk, rsk = oracle_pool.pk_sk_arrays(ref, range(n))
+    base = ctx.get_config(p)
+    try:
+        for G in (1, 7, 32, 64):
+            ctx.set_config(p, product_engine=engine, group_size=G)
+            pk, sk = ctx.batch_keygen(p, wl.SEED, 0, n)
+            assert np.array_equal(host(pk), rpk) and np.array_equal(host(sk), rsk), (p, engine, G)
+    finally:
+        ctx.set_config(p, **base)
+
+
 def test_mixed_parameter_sets(ctx):
     jobs = [(653, 100, 40), (761, 7, 33), (857, 0, 17), (1277, 3, 21)]
     outs = ctx.batch_keygen_mixed(wl.SEED, jobs)

@@ -49,27 +49,66 @@ def test_sample_matches_oracle(ctx, p):
             assert np.array_equal(g[i], oracle.sample_small(wl.SEED, 1000 + i, p, attempt)), (p, i, attempt)
 
 
+ENGINES = [0, 1]  # vector dot2 Toeplitz, int8 matrix cores
+
+
+def _with_engine(ctx, p, engine):
+    ctx.set_config(p, product_engine=engine)
+
+
+DEFAULT_ENGINE = 1
+
+
+@pytest.mark.parametrize("engine", ENGINES)
 @pytest.mark.parametrize("p", P_ALL)
-def test_mul_big_matches_oracle(ctx, p):
+def test_mul_big_matches_oracle(ctx, p, engine):
     _, q, _ = wl.PQW[p]
     a = np.concatenate([wl.random_rq(p, 6, tag=1), wl.extreme_rq(p)])
     b = np.concatenate([wl.random_rq(p, 6, tag=2), wl.extreme_rq(p)[::-1]])
-    c = host(ctx.mul_rq(p, dev(a), dev(b)))
+    _with_engine(ctx, p, engine)
+    try:
+        c = host(ctx.mul_rq(p, dev(a), dev(b)))
+    finally:
+        _with_engine(ctx, p, DEFAULT_ENGINE)
     for i in range(len(a)):
         ref = centered(oracle.mul_mod(a[i], b[i], p, q), q)
-        assert np.array_equal(c[i], ref), (p, i)
+        assert np.array_equal(c[i], ref), (p, engine, i)
 
 
+@pytest.mark.parametrize("engine", ENGINES)
 @pytest.mark.parametrize("p", P_ALL)
-def test_mul_small_matches_oracle(ctx, p):
+def test_mul_small_matches_oracle(ctx, p, engine):
     _, q, _ = wl.PQW[p]
     a = wl.random_small(p, 6, tag=3, bound=3).astype(np.int16)
     a[0] = 3
     a[1] = -3
     b = np.concatenate([wl.random_rq(p, 4, tag=4), wl.extreme_rq(p)[:2]])
-    c = host(ctx.mul_rq(p, dev(a), dev(b), small_a=True))
+    _with_engine(ctx, p, engine)
+    try:
+        c = host(ctx.mul_rq(p, dev(a), dev(b), small_a=True))
+    finally:
+        _with_engine(ctx, p, DEFAULT_ENGINE)
     for i in range(len(a)):
-        assert np.array_equal(c[i], centered(oracle.mul_mod(a[i], b[i], p, q), q)), (p, i)
+        assert np.array_equal(c[i], centered(oracle.mul_mod(a[i], b[i], p, q), q)), (p, engine, i)
+
+
+@pytest.mark.parametrize("p", P_ALL)
+def test_mul_engines_agree_on_many(ctx, p):
+    """2048 random products per engine (several thousand MFMA tiles, every
+    lane position): the matrix-core product equals the vector product, which
+    the tests above pin to the oracle."""
+    import torch
+    _, q, _ = wl.PQW[p]
+    a = dev(wl.random_rq(p, 2048, tag=11))
+    s = dev(wl.random_small(p, 2048, tag=12, bound=3).astype(np.int16))
+    b = dev(wl.random_rq(p, 2048, tag=13))
+    outs = []
+    for engine in ENGINES:
+        _with_engine(ctx, p, engine)
+        outs.append((host(ctx.mul_rq(p, a, b)), host(ctx.mul_rq(p, s, b, small_a=True))))
+    _with_engine(ctx, p, DEFAULT_ENGINE)
+    torch.cuda.synchronize()
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
 
 
 @pytest.mark.parametrize("p", P_ALL)
@@ -123,14 +162,19 @@ def test_recip_r3_matches_oracle(ctx, p, lpk):
         ctx.set_config(p, lanes_per_key=2)
 
 
+@pytest.mark.parametrize("engine", ENGINES)
 @pytest.mark.parametrize("p,G,n", [(761, 1, 3), (761, 5, 23), (761, 32, 70), (653, 7, 15),
                                    (857, 4, 9), (1277, 3, 7)])
-def test_batch_inverse_matches_oracle(ctx, p, G, n):
+def test_batch_inverse_matches_oracle(ctx, p, G, n, engine):
     """Montgomery's trick (Section 2.2) over groups of G: every output is the
     unique inverse, whatever the grouping and the ragged last group."""
     _, q, _ = wl.PQW[p]
     a = wl.random_rq(p, n, tag=7 + G)
-    out = host(ctx.batch_inv_rq(p, dev(a), G))
+    _with_engine(ctx, p, engine)
+    try:
+        out = host(ctx.batch_inv_rq(p, dev(a), G))
+    finally:
+        _with_engine(ctx, p, DEFAULT_ENGINE)
     assert ctx.status() == 0
     for i in range(n):
         assert np.array_equal(out[i], centered(oracle.inv_mod(a[i], p, q), q)), (p, G, i)
