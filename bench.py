@@ -9,11 +9,10 @@ value     keys/s over the timed steps (inputs: a 32-byte seed; outputs stay in
           HBM; no host copies inside the timed region)
 roofline  the dominant kernel's algorithmic integer ops per launch divided by
           its average launch time, measured with HIP events recorded on the
-          launch stream during the timed steps.  Peaks (256 CU x 64 lanes x
-          2.4 GHz): 39.3 T int32 lane-ops/s for bit-op kernels; 78.6 T
-          multiply-adds/s for the Montgomery group kernel, whose products run
-          on v_dot2_i32_i16 (two 16-bit multiply-adds into int32 per lane per
-          clock)
+          launch stream during the timed steps.  Peaks: 39.3 T int32
+          lane-ops/s for the vector-ALU kernels (256 CU x 64 lanes x 2.4 GHz;
+          R/3 divsteps, Short sampling); 5.0 P int8 ops/s for the Montgomery
+          group kernel, whose R/q products run on the int8 matrix cores
 cpu_baseline  the CPU oracle (plain C, -O2) on the host cores, bounded sample
 """
 from __future__ import annotations
@@ -29,23 +28,32 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 VALU_PEAK = 256 * 64 * 2.4e9  # int32 lane-ops per second
-DOT2_PEAK = 2 * VALU_PEAK     # int16 x int16 -> int32 multiply-adds per second (v_dot2_i32_i16)
+I8_MFMA_PEAK = 5.0e15          # dense int8 matrix-core ops per second (2 per multiply-add)
 
 
 def ceil_div(a, b):
     return -(-a // b)
 
 
-def group_kernel_ops(p: int, n: int, G: int) -> float:
-    """Algorithmic int32 multiply-adds of the Montgomery group kernel for n keys:
-    per group of g keys, 4g-3 ring products of p*p schoolbook MACs (g-1 prefix,
-    g-1 c_i, g-1 t_i, g products h_i) plus one divstep reciprocal of (2p-1)
-    steps x (p+1) coefficients x 4 MACs (f0*g, g0*f, f0*r, g0*v)."""
-    ops = 0.0
+def group_kernel_ops(p: int, n: int, G: int, W: int) -> float:
+    """Algorithmic int8 matrix-core operations (2 per multiply-add) of the
+    Montgomery group kernel for n keys.  A ring product is p*p schoolbook
+    multiply-adds per pair of int8 limbs: 2 limb pairs when one operand is
+    small (3f_i, g_i), 4 when both are residues.  Per group of g keys: g-1
+    prefix products and g-1 t_i updates (small), g-1 products c_i (big) and g
+    products h_i (small); per W groups: 3(W-1) big products of the shared
+    reciprocal.  The divstep reciprocal itself runs on the vector ALUs and is
+    not counted."""
+    macs = 0.0
+    groups = 0
     for start in range(0, n, G):
         g = min(G, n - start)
-        ops += (4 * g - 3) * p * p + (2 * p - 1) * (p + 1) * 4
-    return ops
+        macs += ((g - 1) * 2 + (g - 1) * 2 + (g - 1) * 4 + g * 2) * p * p
+        groups += 1
+    for start in range(0, groups, W):
+        w = min(W, groups - start)
+        macs += 3 * (w - 1) * 4 * p * p
+    return 2 * macs
 
 
 def r3_kernel_ops(p: int, keys: int) -> float:
@@ -168,16 +176,18 @@ def main():
     keys_per_s = n * K / (ms / 1e3)
 
     avg = {k: v / K for k, v in stage_ms.items()}
-    ops = {"group": group_kernel_ops(p, n, cfg["group_size"]), "r3_main": r3_kernel_ops(p, n),
-           "sample_short": short_kernel_ops(p, n)}
-    peaks = {"group": DOT2_PEAK, "r3_main": VALU_PEAK, "sample_short": VALU_PEAK}
-    units = {"group": "T MAC/s", "r3_main": "T lane-op/s", "sample_short": "T lane-op/s"}
+    assert cfg["product_engine"] == 1, "the roofline below prices the matrix-core group kernel"
+    ops = {"group": group_kernel_ops(p, n, cfg["group_size"], cfg["inverse_share"]),
+           "r3_main": r3_kernel_ops(p, n), "sample_short": short_kernel_ops(p, n)}
+    peaks = {"group": I8_MFMA_PEAK, "r3_main": VALU_PEAK, "sample_short": VALU_PEAK}
+    units = {"group": "T int8-op/s", "r3_main": "T lane-op/s", "sample_short": "T lane-op/s"}
     dom = max(ops, key=lambda k: avg[k])
     achieved = ops[dom] / (avg[dom] / 1e3)
-    kernel_names = {"group": "group_kernel<%d,true>" % p,
+    kernel_names = {"group": "keygen_group_kernel<%d,%d>" % (p, cfg["inverse_share"]),
                     "r3_main": "r3_kernel<%d,%d>" % (p, cfg["lanes_per_key"]),
                     "sample_short": "sample_short_kernel<%d>" % p}
-    roofline = {"bound": "alu", "kernel": kernel_names[dom], "achieved": round(achieved / 1e12, 3),
+    roofline = {"bound": "mfma" if dom == "group" else "alu", "kernel": kernel_names[dom],
+                "achieved": round(achieved / 1e12, 3),
                 "peak": round(peaks[dom] / 1e12, 2), "unit": units[dom], "frac": round(achieved / peaks[dom], 4),
                 "traffic": None,
                 "ops_per_launch": ops[dom], "avg_launch_ms": round(avg[dom], 4)}
@@ -248,7 +258,9 @@ def main():
         "data": "synthetic (seeded ChaCha20 keys; seed bytes 0x00..0x1f)",
         "config": {"workload": "sntrup%d batched KeyGen, N=%d keys, Montgomery group size %d" % (p, n, cfg["group_size"]),
                    "p": p, "q": prm.q, "w": prm.w, "n_keys": n, "group_size": cfg["group_size"],
-                   "lanes_per_key": cfg["lanes_per_key"], "launch": "stream (events between stages)"},
+                   "inverse_share": cfg["inverse_share"], "lanes_per_key": cfg["lanes_per_key"],
+                   "product_engine": "int8 matrix cores" if cfg["product_engine"] == 1 else "v_dot2",
+                   "launch": "stream (events between stages)"},
         "roofline": roofline,
         "stages": stage_fracs,
         "wall_s": round(wall, 3),
@@ -256,7 +268,9 @@ def main():
     out.update(extras)
     if tuned is not None:
         out["autotune"] = {"config": tuned["config"], "cached": tuned["cached"],
-                           "table_ms": {"G%d/L%d/R%dx%dx%d" % (r["group_size"], r["lanes_per_key"], r["retry_passes"], r["retry_lanes_per_key"], r["retry_parallel_attempts"]): r["ms"]
+                           "table_ms": {"G%d/W%d/L%d/R%dx%dx%d" % (r["group_size"], r["inverse_share"], r["lanes_per_key"],
+                                                                   r["retry_passes"], r["retry_lanes_per_key"],
+                                                                   r["retry_parallel_attempts"]): r["ms"]
                                         for r in tuned.get("table", [])}}
     if cb is not None:
         out["cpu_baseline"] = cb

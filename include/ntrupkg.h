@@ -93,7 +93,10 @@ const char *ntrup_strerror(int code);
  *                        the call's arguments repeat
  *   product_engine       R/q products on the vector units (0: v_dot2 Toeplitz
  *                        dot products) or on the int8 matrix cores (1: block
- *                        Toeplitz MFMA with two 7-bit limbs); both exact    */
+ *                        Toeplitz MFMA with two 7-bit limbs); both exact
+ *   inverse_share        1, 2, 4 or 8 Montgomery groups (one wave each) that
+ *                        share one R/q reciprocal (product_engine 1 only;
+ *                        at most 4 for p = 1277)                            */
 typedef struct {
     int group_size;
     int lanes_per_key;
@@ -102,6 +105,7 @@ typedef struct {
     int retry_passes;
     int use_graph;
     int product_engine;
+    int inverse_share;
 } ntrup_config;
 
 int ntrup_get_config(const ntrup_ctx *ctx, int p, ntrup_config *cfg);

@@ -44,7 +44,7 @@ class _Config(ctypes.Structure):
     _fields_ = [("group_size", ctypes.c_int), ("lanes_per_key", ctypes.c_int),
                 ("retry_lanes_per_key", ctypes.c_int), ("retry_parallel_attempts", ctypes.c_int),
                 ("retry_passes", ctypes.c_int), ("use_graph", ctypes.c_int),
-                ("product_engine", ctypes.c_int)]
+                ("product_engine", ctypes.c_int), ("inverse_share", ctypes.c_int)]
 
 
 _lib = None
@@ -172,14 +172,15 @@ class Context:
         return {"group_size": c.group_size, "lanes_per_key": c.lanes_per_key,
                 "retry_lanes_per_key": c.retry_lanes_per_key,
                 "retry_parallel_attempts": c.retry_parallel_attempts, "retry_passes": c.retry_passes,
-                "use_graph": c.use_graph, "product_engine": c.product_engine}
+                "use_graph": c.use_graph, "product_engine": c.product_engine,
+                "inverse_share": c.inverse_share}
 
     def set_config(self, p: int, **kw):
         cur = self.get_config(p)
         cur.update(kw)
         c = _Config(cur["group_size"], cur["lanes_per_key"], cur["retry_lanes_per_key"],
                     cur["retry_parallel_attempts"], cur["retry_passes"], cur["use_graph"],
-                    cur["product_engine"])
+                    cur["product_engine"], cur["inverse_share"])
         self._check(lib().ntrup_set_config(self._h, p, ctypes.byref(c)), "ntrup_set_config")
 
     def reserve(self, p: int, n: int):

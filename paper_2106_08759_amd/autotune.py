@@ -4,6 +4,8 @@ Knobs (see ``ntrup_config`` in include/ntrupkg.h):
   group_size     Montgomery group size G (Section 2.2's n): larger groups
                  share one R/q reciprocal among more keys but leave fewer
                  independent groups to fill the GPU;
+  inverse_share  W groups (one wave each) sharing one reciprocal through a
+                 second level of the same trick;
   lanes_per_key  1, 2, 4 or 8 lanes per key for the bitsliced R/3 divsteps
                  of the main pass;
   retry_lanes_per_key, retry_parallel_attempts, retry_passes
@@ -12,10 +14,12 @@ Knobs (see ``ntrup_config`` in include/ntrupkg.h):
                  invertible (matters for p = 653, 1277, where the retry
                  passes are latency-bound).
 
-The product tile (R = ceil(p/64) outputs per lane) and the reduction chunk
-are fixed by p and need no tuning.  Every candidate is timed on the real
-pipeline with HIP events on the launch stream; the winner per
-(device, p, N rounded up to a power of two) is cached as JSON.
+The group knobs (G, W) and the R/3 knobs act on different kernels, so they
+are tuned one after the other: first (G, W) with the default R/3 knobs, then
+the R/3 knobs with the chosen (G, W).  The product tiles are fixed by p.
+Every candidate is timed on the real pipeline with HIP events on the launch
+stream; the winner per (device, p, N rounded up to a power of two) is cached
+as JSON.
 """
 from __future__ import annotations
 
@@ -23,7 +27,10 @@ import json
 import os
 import time
 
-GROUP_SIZES = (16, 32, 64, 128, 256)
+GROUP_SIZES = (16, 32, 64, 128)
+SHARES = (1, 2, 4, 8)
+KNOBS = ("group_size", "inverse_share", "lanes_per_key", "retry_passes", "retry_lanes_per_key",
+         "retry_parallel_attempts")
 
 
 def cache_path() -> str:
@@ -38,23 +45,38 @@ def bucket(n: int) -> int:
     return b
 
 
-def candidates(p: int, n: int):
-    """Configurations worth timing for n keys of degree p."""
+def group_candidates(p: int, n: int):
+    """(G, W) pairs worth timing for n keys of degree p."""
     out = []
-    gs = [g for g in GROUP_SIZES if g <= max(16, n)]
-    lpks = (2, 4) if p > 800 else (1, 2, 4)      # one lane per key spills for large p
-    # (retry passes, retry lanes per key, attempts side by side)
-    retry = [(1, 8, 4)] if p not in (653, 1277) else [(1, 8, 2), (1, 8, 4), (1, 8, 8), (0, 8, 4), (1, 4, 4)]
-    for g in gs:
-        for l in lpks:
-            for r, rl, ra in retry:
-                out.append({"group_size": g, "lanes_per_key": l, "retry_passes": r, "retry_lanes_per_key": rl,
-                            "retry_parallel_attempts": ra})
+    for g in GROUP_SIZES:
+        if g > max(16, n):
+            continue
+        for w in SHARES:
+            if p == 1277 and w > 4:   # 8 waves of p = 1277 exceed the LDS
+                continue
+            if g * w > max(16, 2 * n):
+                continue
+            out.append({"group_size": g, "inverse_share": w})
     return out
 
 
+def r3_candidates(p: int):
+    """R/3 knob settings worth timing for degree p."""
+    lpks = (2, 4) if p > 800 else (1, 2, 4)      # one lane per key spills for large p
+    # (retry passes, retry lanes per key, attempts side by side)
+    retry = [(1, 8, 4)] if p not in (653, 1277) else [(1, 8, 2), (1, 8, 4), (1, 8, 8), (0, 8, 4), (1, 4, 4)]
+    return [{"lanes_per_key": l, "retry_passes": r, "retry_lanes_per_key": rl, "retry_parallel_attempts": ra}
+            for l in lpks for r, rl, ra in retry]
+
+
+def candidates(p: int, n: int):
+    """All configurations the two tuning phases may time (for reference)."""
+    return [dict(g, **r) for g in group_candidates(p, n) for r in r3_candidates(p)]
+
+
 def _key(device_name: str, p: int, n: int) -> str:
-    return "%s|p=%d|n<=%d" % (device_name, p, bucket(n))
+    # v2: entries carry inverse_share and the matrix-core product engine
+    return "%s|p=%d|n<=%d|v2" % (device_name, p, bucket(n))
 
 
 def load_cache(path: str | None = None) -> dict:
@@ -115,13 +137,22 @@ def tune(ctx, p: int, n: int, seed: bytes | None = None, reps: int = 3, force: b
     pk = torch.empty((n, prm.pk_bytes), dtype=torch.uint8, device="cuda:%d" % ctx.device)
     sk = torch.empty((n, prm.sk_bytes), dtype=torch.uint8, device="cuda:%d" % ctx.device)
     ctx.reserve(p, n)
+    base = ctx.get_config(p)
+    cur = {k: base[k] for k in KNOBS}
+    ctx.set_config(p, product_engine=1)
     table = []
-    for cfg in candidates(p, n):
-        ms = time_config(ctx, p, n, cfg, seed, reps, pk, sk)
-        table.append(dict(cfg, ms=round(ms, 4)))
+    # phase 1: the group stage
+    for gc in group_candidates(p, n):
+        cfg = dict(cur, **gc)
+        table.append(dict(cfg, ms=round(time_config(ctx, p, n, cfg, seed, reps, pk, sk), 4)))
     best = min(table, key=lambda r: r["ms"])
-    cfg = {k: best[k] for k in ("group_size", "lanes_per_key", "retry_passes", "retry_lanes_per_key",
-                                "retry_parallel_attempts")}
+    cur.update({k: best[k] for k in ("group_size", "inverse_share")})
+    # phase 2: the R/3 stage
+    for rc in r3_candidates(p):
+        cfg = dict(cur, **rc)
+        table.append(dict(cfg, ms=round(time_config(ctx, p, n, cfg, seed, reps, pk, sk), 4)))
+    best = min(table, key=lambda r: r["ms"])
+    cfg = {k: best[k] for k in KNOBS}
     entry = {"config": cfg, "ms": best["ms"], "keys_per_s": round(n / best["ms"] * 1e3, 1),
              "n": n, "table": table, "tuned_at": time.strftime("%Y-%m-%dT%H:%M:%S")}
     data[key] = entry

@@ -9,6 +9,7 @@
 
 #include "../../include/ntrupkg.h"
 #include "ntrup_kernels.h"
+#include "ntrup_keygen.h"
 
 using namespace ntrup;
 
@@ -226,10 +227,20 @@ int enqueue_keygen(ntrup_ctx* ctx, const ntrup_config& cfg, const Seed& seed, ui
     g.err = w.counters + 32;
     g.a_in = nullptr;
     g.c_out = nullptr;
-    if (cfg.product_engine == 1)
-        hipLaunchKernelGGL((group_mfma_kernel<P, true>), dim3(grid_for(n, cfg.group_size)), dim3(64), 0, st, g);
-    else
+    if (cfg.product_engine == 1) {
+        const int W = cfg.inverse_share;
+        const dim3 grid(grid_for(n, (size_t)cfg.group_size * W)), blk(64 * W);
+        switch (W) {
+            case 1: hipLaunchKernelGGL((keygen_group_kernel<P, 1>), grid, blk, 0, st, g); break;
+            case 2: hipLaunchKernelGGL((keygen_group_kernel<P, 2>), grid, blk, 0, st, g); break;
+            case 4: hipLaunchKernelGGL((keygen_group_kernel<P, 4>), grid, blk, 0, st, g); break;
+            default:
+                if constexpr (P != 1277) hipLaunchKernelGGL((keygen_group_kernel<P, 8>), grid, blk, 0, st, g);
+                break;
+        }
+    } else {
         hipLaunchKernelGGL((group_kernel<P, true>), dim3(grid_for(n, cfg.group_size)), dim3(64), 0, st, g);
+    }
     mark(4);
     if (ctx->t_used < ctx->t_max) ctx->t_used++;
     hipError_t e = hipGetLastError();
@@ -254,7 +265,8 @@ bool valid_config(const ntrup_config& c) {
            lpk_ok(c.retry_lanes_per_key) && lpk_ok(c.retry_parallel_attempts) &&
            c.retry_lanes_per_key * c.retry_parallel_attempts <= 64 && c.retry_passes >= 0 &&
            c.retry_passes <= 8 && (c.use_graph == 0 || c.use_graph == 1) &&
-           (c.product_engine == 0 || c.product_engine == 1);
+           (c.product_engine == 0 || c.product_engine == 1) &&
+           (c.inverse_share == 1 || c.inverse_share == 2 || c.inverse_share == 4 || c.inverse_share == 8);
 }
 
 int check_job(int p, size_t n, const void* pk, const void* sk) {
@@ -323,7 +335,7 @@ int ntrup_ctx_create(ntrup_ctx** out, int device) {
     ntrup_ctx* ctx = new (std::nothrow) ntrup_ctx();
     if (!ctx) return NTRUP_ENOMEM;
     ctx->device = device;
-    for (int i = 0; i < 4; i++) ctx->cfg[i] = ntrup_config{32, 2, 8, 4, 1, 1, 1};
+    for (int i = 0; i < 4; i++) ctx->cfg[i] = ntrup_config{32, 2, 8, 4, 1, 1, 1, 4};
     bool ok = set_device(ctx) == 0 && hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking) == hipSuccess;
     for (int i = 0; ok && i < kJobStreams; i++)
         ok = hipStreamCreateWithFlags(&ctx->job_streams[i], hipStreamNonBlocking) == hipSuccess;
@@ -372,6 +384,7 @@ int ntrup_get_config(const ntrup_ctx* ctx, int p, ntrup_config* cfg) {
 int ntrup_set_config(ntrup_ctx* ctx, int p, const ntrup_config* cfg) {
     const int s = param_slot(p);
     if (!ctx || s < 0 || !cfg || !valid_config(*cfg)) return NTRUP_EINVAL;
+    if (p == 1277 && cfg->inverse_share > 4) return NTRUP_EINVAL;  // 8 waves of p = 1277 exceed LDS/VGPRs
     ctx->cfg[s] = *cfg;
     return 0;
 }

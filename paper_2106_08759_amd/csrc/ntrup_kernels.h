@@ -539,8 +539,8 @@ __global__ __launch_bounds__(64, NTRUP_GM_WAVES) void group_mfma_kernel(GroupArg
         if (KEYGEN) hankel_3f<P>(f_rows + (size_t)(k0 + i) * P, L.HS);
         else hankel_row<P>(a_in + (size_t)(k0 + i) * P, L.HL, L.HH);
         __syncthreads();
-        if (KEYGEN) mfma_mul<P, false>(L.TL, L.TH, L.HS, nullptr, CS, L.Bb, bscr + (size_t)(k0 + i) * P);
-        else mfma_mul<P, true>(L.TL, L.TH, L.HL, L.HH, CS, L.Bb, bscr + (size_t)(k0 + i) * P);
+        if (KEYGEN) mfma_mul<P, false>(L.TL, L.TH, L.HS, nullptr, CS, L.Bb, nullptr, nullptr, bscr + (size_t)(k0 + i) * P);
+        else mfma_mul<P, true>(L.TL, L.TH, L.HL, L.HH, CS, L.Bb, nullptr, nullptr, bscr + (size_t)(k0 + i) * P);
         __syncthreads();
     }
     // one reciprocal per group: t = 1/b_gsz
@@ -556,11 +556,11 @@ __global__ __launch_bounds__(64, NTRUP_GM_WAVES) void group_mfma_kernel(GroupArg
             hankel_row<P>(bscr + (size_t)(k0 + i - 2) * P, L.HL, L.HH);
             if (KEYGEN) hankel_3f<P>(f_rows + (size_t)(k0 + i - 1) * P, L.HS);
             __syncthreads();
-            mfma_mul<P, true>(L.TL, L.TH, L.HL, L.HH, CS, L.Cb, nullptr);
+            mfma_mul<P, true>(L.TL, L.TH, L.HL, L.HH, CS, L.Cb, nullptr, nullptr, nullptr);
             if (!KEYGEN) hankel_row<P>(a_in + (size_t)(k0 + i - 1) * P, L.HL, L.HH);
             __syncthreads();
-            if (KEYGEN) mfma_mul<P, false>(L.TL, L.TH, L.HS, nullptr, CS, L.Bb, nullptr);
-            else mfma_mul<P, true>(L.TL, L.TH, L.HL, L.HH, CS, L.Bb, nullptr);
+            if (KEYGEN) mfma_mul<P, false>(L.TL, L.TH, L.HS, nullptr, CS, L.Bb, nullptr, nullptr, nullptr);
+            else mfma_mul<P, true>(L.TL, L.TH, L.HL, L.HH, CS, L.Bb, nullptr, nullptr, nullptr);
             __syncthreads();
             C = L.Cb;
         }
@@ -570,7 +570,7 @@ __global__ __launch_bounds__(64, NTRUP_GM_WAVES) void group_mfma_kernel(GroupArg
             build_toeplitz<P>(C, L.TL, L.TH);
             hankel_g<P>(args.gbits, n, key, L.HS);
             __syncthreads();
-            mfma_mul<P, false>(L.TL, L.TH, L.HS, nullptr, CS, L.Cb, nullptr);
+            mfma_mul<P, false>(L.TL, L.TH, L.HS, nullptr, CS, L.Cb, nullptr, nullptr, nullptr);
             __syncthreads();
             encode_key<P>(key, L.Cb, args.pk, args.sk, f_rows, args.ibits, n);
         } else {
@@ -624,7 +624,7 @@ __global__ __launch_bounds__(64) void mulm_kernel(int n, const int16_t* a, const
     build_toeplitz<P>(L.Y, L.TL, L.TH);
     build_hankel<P>(L.X, L.HL, BIG ? L.HH : nullptr);
     __syncthreads();
-    mfma_mul<P, BIG>(L.TL, L.TH, L.HL, L.HH, L.CS, nullptr, c + (size_t)e * P);
+    mfma_mul<P, BIG>(L.TL, L.TH, L.HL, L.HH, L.CS, nullptr, nullptr, nullptr, c + (size_t)e * P);
 }
 
 template <int P>

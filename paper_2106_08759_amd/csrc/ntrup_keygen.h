@@ -1,0 +1,386 @@
+// Batched KeyGen group stage on the matrix cores (Section 3.1 KeyGen with the
+// batch inversion of Section 2.2): for each key h = g / (3f) in R/q, encoded
+// with f and 1/g into (pk, sk).
+//
+// One workgroup = W waves; wave w owns a Montgomery group of G keys.
+//   1. prefix (every wave): b_1 = 3f_1, b_i = 3f_i b_{i-1}; rows b_i kept in
+//      HBM, P_w = b_G stays in the wave's LDS;
+//   2. shared reciprocal (wave 0): Q_0 = P_0, Q_w = Q_{w-1} P_w, one
+//      constant-time divstep reciprocal T = 1/Q_{W-1}, then for w = W-1..1
+//      1/P_w = T Q_{w-1} and T <- T P_w; 1/P_0 = T.  W groups share one
+//      reciprocal (the same trick as inside a group, one level up);
+//   3. back-substitution (every wave), from t = 1/P_w: c_i = t b_{i-1}
+//      (= 1/(3f_i)), t <- t 3f_i, h_i = g_i c_i, then encoding.
+// Every product is mfma_mul with the running value as Toeplitz operand.
+//
+// Latency: the next key's operands (the f row, the stored prefix row, the
+// bitsliced g and 1/g words) are loaded into registers one step ahead and
+// written to LDS at the start of the step; waves synchronise their own LDS
+// traffic with wave_sync and meet at workgroup barriers only around step 2.
+//
+// Register layout of the per-key operands: lane l holds coefficients
+// m = 4l + 256u + t (t = 0..3, u < NU), four per 32-bit word, which is also the
+// layout of sk (byte 4l+... covers coefficients 4b..4b+3 with b = l + 64u).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ntrup_kernels.h"
+#include "ntrup_mfma.h"
+#include "ntrup_params.h"
+#include "ntrup_rq.h"
+
+namespace ntrup {
+
+template <int P>
+struct KgShape {
+    static constexpr int NU = ceil_div(P, 256);   // 4-coefficient words per lane
+    static constexpr int WN = ceil_div(P, 32);    // bitsliced words per plane
+};
+
+// Per-wave LDS of the KeyGen group kernel.
+template <int P>
+struct KgWave {
+    using S = MfShape<P>;
+    static constexpr int STG = (64 * RqShape<P>::RI > S::CLEN / 2) ? 64 * RqShape<P>::RI : S::CLEN / 2;
+    __attribute__((aligned(16))) uint8_t TL[S::TLEN];   // Toeplitz limbs of the running value
+    __attribute__((aligned(16))) uint8_t TH[S::TLEN];
+    __attribute__((aligned(16))) uint8_t UL[S::TLEN];   // Toeplitz limbs of c_i
+    __attribute__((aligned(16))) uint8_t UH[S::TLEN];
+    __attribute__((aligned(16))) uint8_t HL[S::HLEN];   // Hankel limbs of a big operand
+    __attribute__((aligned(16))) uint8_t HH[S::HLEN];
+    __attribute__((aligned(16))) uint8_t HS[S::HLEN];   // 3 f of the current key
+    __attribute__((aligned(16))) uint8_t HG[S::HLEN];   // g of the current key
+    __attribute__((aligned(16))) int32_t ST[STG];       // conv / divstep staging
+    __attribute__((aligned(16))) int16_t Bb[RqShape<P>::JP];  // running value
+    __attribute__((aligned(16))) int16_t Cb[RqShape<P>::JP];  // c_i, h_i, chain values
+};
+
+// Operands of one key, in registers.
+template <int P>
+struct KgRegs {
+    static constexpr int NU = KgShape<P>::NU;
+    uint32_t f[NU];       // f bytes (int8), four coefficients per word
+    uint32_t b[NU][2];    // stored prefix row b_{i-1}: four int16
+    uint32_t gm[NU], gs[NU];   // g: nonzero / negative bits (4 per word, low bits)
+    uint32_t im[NU], is[NU];   // 1/g in R/3, same form
+};
+
+// Coefficient mask of the 4-coefficient word starting at m0.
+template <int P>
+__device__ __forceinline__ uint32_t live4(int m0) {
+    return m0 >= P ? 0u : (P - m0 >= 4 ? 0xFu : ((1u << (P - m0)) - 1u));
+}
+
+template <int P>
+__device__ __forceinline__ void kg_load_f(const int8_t* f_rows, int key, KgRegs<P>& r) {
+    const int lane = lane_id();
+    const uint8_t* row = (const uint8_t*)f_rows + (size_t)key * P;
+#pragma unroll
+    for (int u = 0; u < KgShape<P>::NU; u++) {
+        const int m0 = 4 * lane + 256 * u;
+        uint32_t w = 0;
+#pragma unroll
+        for (int t = 0; t < 4; t++)
+            if (m0 + t < P) w |= (uint32_t)row[m0 + t] << (8 * t);
+        r.f[u] = w;
+    }
+}
+
+template <int P>
+__device__ __forceinline__ void kg_load_b(const int16_t* bscr, int row_index, KgRegs<P>& r) {
+    const int lane = lane_id();
+    const uint16_t* row = (const uint16_t*)bscr + (size_t)row_index * P;
+#pragma unroll
+    for (int u = 0; u < KgShape<P>::NU; u++) {
+        const int m0 = 4 * lane + 256 * u;
+        uint32_t v[4];
+#pragma unroll
+        for (int t = 0; t < 4; t++) v[t] = (m0 + t < P) ? (uint32_t)row[m0 + t] : 0u;
+        r.b[u][0] = v[0] | (v[1] << 16);
+        r.b[u][1] = v[2] | (v[3] << 16);
+    }
+}
+
+template <int P>
+__device__ __forceinline__ void kg_load_bits(const uint32_t* gbits, const uint32_t* ibits, int n, int key,
+                                             KgRegs<P>& r) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int u = 0; u < KgShape<P>::NU; u++) {
+        const int m0 = 4 * lane + 256 * u;
+        uint32_t gm = 0, gs = 0, im = 0, is = 0;
+        if (m0 < P) {
+            const int wd = m0 >> 5, sh = m0 & 31;
+            const uint32_t live = live4<P>(m0);
+            gm = (gbits[(size_t)(2 * wd) * n + key] >> sh) & live;
+            gs = (gbits[(size_t)(2 * wd + 1) * n + key] >> sh) & live;
+            im = (ibits[(size_t)(2 * wd) * n + key] >> sh) & live;
+            is = (ibits[(size_t)(2 * wd + 1) * n + key] >> sh) & live;
+        }
+        r.gm[u] = gm;
+        r.gs[u] = gs;
+        r.im[u] = im;
+        r.is[u] = is;
+    }
+}
+
+// Four bits -> four bytes (bit t to the low bit of byte t).
+__device__ __forceinline__ uint32_t spread4(uint32_t x) { return ((x & 0xFu) * 0x00204081u) & 0x01010101u; }
+// Four bits -> four 2-bit fields (bit t to bit 2t).
+__device__ __forceinline__ uint32_t spread2(uint32_t x) {
+    return (x & 1u) | ((x & 2u) << 1) | ((x & 4u) << 2) | ((x & 8u) << 3);
+}
+
+// HS[HOFF + m] = 3 f_m: bytes 0x00, 0x01, 0xFF -> 0x00, 0x03, 0xFD.
+template <int P>
+__device__ __forceinline__ void kg_put_3f(const KgRegs<P>& r, uint8_t* HS) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int u = 0; u < KgShape<P>::NU; u++) {
+        const int m0 = 4 * lane + 256 * u;
+        if (m0 < P) *(uint32_t*)(HS + MfShape<P>::HOFF + m0) = r.f[u] ^ ((r.f[u] & 0x01010101u) << 1);
+    }
+}
+
+// HG[HOFF + m] = g_m: byte 0x01 (g = 1) or 0xFF (g = -1).
+template <int P>
+__device__ __forceinline__ void kg_put_g(const KgRegs<P>& r, uint8_t* HG) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int u = 0; u < KgShape<P>::NU; u++) {
+        const int m0 = 4 * lane + 256 * u;
+        if (m0 < P) *(uint32_t*)(HG + MfShape<P>::HOFF + m0) = spread4(r.gm[u]) | (spread4(r.gs[u]) * 0xFEu);
+    }
+}
+
+// HL/HH[HOFF + m] = limbs of the stored row b_m.
+template <int P>
+__device__ __forceinline__ void kg_put_b(const KgRegs<P>& r, uint8_t* HL, uint8_t* HH) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int u = 0; u < KgShape<P>::NU; u++) {
+        const int m0 = 4 * lane + 256 * u;
+        if (m0 < P) {
+            uint32_t lo = 0, hi = 0;
+#pragma unroll
+            for (int t = 0; t < 4; t++) {
+                const int32_t v = (int32_t)(int16_t)(r.b[u][t >> 1] >> (16 * (t & 1)));
+                uint32_t l, h;
+                split_limb(v, l, h);
+                lo |= l << (8 * t);
+                hi |= h << (8 * t);
+            }
+            *(uint32_t*)(HL + MfShape<P>::HOFF + m0) = lo;
+            *(uint32_t*)(HH + MfShape<P>::HOFF + m0) = hi;
+        }
+    }
+}
+
+// The first prefix value b_1 = 3 f: X[m] = 3 f_m (int16), the same row to
+// HBM, and its reversed Toeplitz limbs TL[Z0 - m] = 3 f_m (the high limbs of
+// |3 f_m| <= 3 are 0: TH must hold zeros).
+template <int P>
+__device__ __forceinline__ void kg_put_3f16(const KgRegs<P>& r, int16_t* X, uint8_t* TL, int16_t* row) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int u = 0; u < KgShape<P>::NU; u++) {
+        const int m0 = 4 * lane + 256 * u;
+        if (m0 >= P) continue;
+#pragma unroll
+        for (int t = 0; t < 4; t++) {
+            if (m0 + t < P) {
+                const int16_t v = (int16_t)(3 * (int32_t)(int8_t)(r.f[u] >> (8 * t)));
+                X[m0 + t] = v;
+                row[m0 + t] = v;
+            }
+        }
+        const uint32_t f3 = r.f[u] ^ ((r.f[u] & 0x01010101u) << 1);
+        *(uint32_t*)(TL + MfShape<P>::Z0 - m0 - 3) = __builtin_amdgcn_perm(0u, f3, 0x00010203u);   // byte reverse
+    }
+}
+
+// sk = (f, 1/g) as 2-bit fields c + 1, four per byte; pk = h_i + (q-1)/2 as
+// 13-bit fields (h in LDS).
+template <int P>
+__device__ __forceinline__ void kg_encode(int key, const int16_t* H, const KgRegs<P>& r, uint8_t* pk_out,
+                                          uint8_t* sk_out) {
+    constexpr int Q = Param<P>::q;
+    constexpr int PKB = pk_bytes(P), SKH = sk_half_bytes(P);
+    const int lane = lane_id();
+    uint8_t* pk = pk_out + (size_t)key * PKB;
+    for (int b = lane; b < PKB; b += 64) {
+        const int bit = 8 * b, i0 = bit / 13, o = bit - 13 * i0;
+        const uint32_t v0 = (uint32_t)(H[i0] + (Q - 1) / 2);
+        const uint32_t v1 = (i0 + 1 < P) ? (uint32_t)(H[i0 + 1] + (Q - 1) / 2) : 0u;
+        pk[b] = (uint8_t)((v0 | (v1 << 13)) >> o);
+    }
+    uint8_t* sk = sk_out + (size_t)key * 2 * SKH;
+#pragma unroll
+    for (int u = 0; u < KgShape<P>::NU; u++) {
+        const int b = lane + 64 * u;
+        if (b < SKH) {
+            const uint32_t live = live4<P>(4 * b);
+            // f + 1 per byte without carries between bytes
+            const uint32_t x = ((r.f[u] & 0x7F7F7F7Fu) + 0x01010101u) ^ (r.f[u] & 0x80808080u);
+            uint32_t bf = (x & 3u) | ((x >> 6) & 0xCu) | ((x >> 12) & 0x30u) | ((x >> 18) & 0xC0u);
+            bf &= spread2(live) * 3u;
+            const uint32_t bi = (spread2(~r.im[u] & live)) | (spread2(r.im[u] & ~r.is[u] & live) << 1);
+            sk[b] = (uint8_t)bf;
+            sk[SKH + b] = (uint8_t)bi;
+        }
+    }
+}
+
+template <int P>
+__device__ __forceinline__ void kg_zero(uint8_t* p, int bytes) {
+    for (int i = lane_id(); i < bytes / 4; i += 64) ((uint32_t*)p)[i] = 0u;
+}
+
+template <int P>
+__device__ __forceinline__ void kg_set_one(int16_t* X) {
+    for (int i = lane_id(); i < P; i += 64) X[i] = (int16_t)(i == 0);
+}
+
+template <int P>
+__device__ __forceinline__ void kg_copy(const int16_t* src, int16_t* dst) {
+    for (int i = lane_id(); i < P; i += 64) dst[i] = src[i];
+}
+
+// One back-substitution step for key kw0 + i - 1 (i >= 1): operands in cur,
+// the next step's operands loaded into nxt.  On entry TL/TH hold the limbs
+// of t = 1/b_i; on exit those of t 3f_i.
+template <int P>
+__device__ __forceinline__ void kg_back_step(const GroupArgs& args, KgWave<P>& L, int kw0, int i, KgRegs<P>& cur,
+                                             KgRegs<P>& nxt) {
+    int16_t* CS = (int16_t*)L.ST;
+    const int key = kw0 + i - 1;
+    kg_put_3f<P>(cur, L.HS);
+    kg_put_g<P>(cur, L.HG);
+    if (i > 1) {
+        kg_put_b<P>(cur, L.HL, L.HH);
+        kg_load_f<P>(args.f_rows, key - 1, nxt);
+        if (i > 2) kg_load_b<P>(args.bscr, key - 2, nxt);
+        kg_load_bits<P>(args.gbits, args.ibits, args.n, key - 1, nxt);
+    }
+    wave_sync();
+    const uint8_t* CL = L.TL;   // i == 1: c_1 = t_1
+    const uint8_t* CH = L.TH;
+    if (i > 1) {
+        mfma_mul<P, true>(L.TL, L.TH, L.HL, L.HH, CS, nullptr, L.UL, L.UH, nullptr);   // c_i = t b_{i-1}
+        wave_sync();
+        mfma_mul<P, false>(L.TL, L.TH, L.HS, nullptr, CS, nullptr, L.TL, L.TH, nullptr); // t <- t 3f_i
+        wave_sync();
+        CL = L.UL;
+        CH = L.UH;
+    }
+    mfma_mul<P, false>(CL, CH, L.HG, nullptr, CS, L.Cb, nullptr, nullptr, nullptr);     // h = g c_i
+    wave_sync();
+    kg_encode<P>(key, L.Cb, cur, args.pk, args.sk);
+}
+
+// At least two waves per SIMD (at most 256 registers per lane) where that
+// fits without spills (p < 800).
+template <int P, int W>
+__global__ __launch_bounds__(64 * W, (P < 800 ? 2 : 1)) void keygen_group_kernel(GroupArgs args) {
+    using S = MfShape<P>;
+    __shared__ KgWave<P> LW[W];
+    const int wave = (int)(threadIdx.x >> 6);
+    KgWave<P>& L = LW[wave];
+    const int n = args.n;
+    const int G = args.G;
+    const int kw0 = (blockIdx.x * W + wave) * G;
+    const int gsz = max(0, min(G, n - kw0));
+    int16_t* CS = (int16_t*)L.ST;
+    int16_t* bscr = args.bscr;
+
+    // zero padding of every limb array (only [.., p) positions are rewritten)
+    kg_zero<P>(L.TL, S::TLEN);
+    kg_zero<P>(L.TH, S::TLEN);
+    kg_zero<P>(L.UL, S::TLEN);
+    kg_zero<P>(L.UH, S::TLEN);
+    kg_zero<P>(L.HL, S::HLEN);
+    kg_zero<P>(L.HH, S::HLEN);
+    kg_zero<P>(L.HS, S::HLEN);
+    kg_zero<P>(L.HG, S::HLEN);
+    wave_sync();
+
+    // 1. prefix products; TL/TH carry the limbs of b_{i-1}
+    KgRegs<P> ra, rb;
+    if (gsz >= 1) {
+        kg_load_f<P>(args.f_rows, kw0, ra);
+        kg_put_3f16<P>(ra, L.Bb, L.TL, bscr + (size_t)kw0 * P);
+        if (gsz > 1) kg_load_f<P>(args.f_rows, kw0 + 1, ra);
+        for (int i = 1; i < gsz; i++) {
+            kg_put_3f<P>(ra, L.HS);
+            if (i + 1 < gsz) kg_load_f<P>(args.f_rows, kw0 + i + 1, ra);
+            wave_sync();
+            mfma_mul<P, false>(L.TL, L.TH, L.HS, nullptr, CS, i + 1 == gsz ? L.Bb : nullptr, L.TL, L.TH,
+                               bscr + (size_t)(kw0 + i) * P);
+            wave_sync();
+        }
+    } else {
+        kg_set_one<P>(L.Bb);
+    }
+    __syncthreads();
+    // operands of the first back-substitution step (prefix rows now visible)
+    if (gsz >= 1) {
+        kg_load_f<P>(args.f_rows, kw0 + gsz - 1, ra);
+        if (gsz >= 2) kg_load_b<P>(bscr, kw0 + gsz - 2, ra);
+        kg_load_bits<P>(args.gbits, args.ibits, n, kw0 + gsz - 1, ra);
+    }
+
+    // 2. one reciprocal for the W group products (Toeplitz limbs in wave 0's
+    // TL/TH; the Hankel arrays keep zero padding since build_hankel writes
+    // them whole)
+    if (wave == 0) {
+        if (W == 1) {
+            const int ok = recip_wave<P>(L.Bb, L.Bb, L.ST);
+            if (!ok && lane_id() == 0) atomicOr(args.err, 2);
+        } else {
+            // Q_{w-1} -> LW[w].Cb, Q_{W-1} -> LW[0].Cb
+            kg_copy<P>(LW[0].Bb, LW[1].Cb);
+            for (int w = 1; w < W; w++) {
+                wave_sync();
+                build_toeplitz<P>(LW[w].Cb, L.TL, L.TH);
+                build_hankel<P>(LW[w].Bb, L.HL, L.HH);
+                wave_sync();
+                mfma_mul<P, true>(L.TL, L.TH, L.HL, L.HH, CS, w + 1 < W ? LW[w + 1].Cb : LW[0].Cb, nullptr,
+                                  nullptr, nullptr);
+            }
+            wave_sync();
+            const int ok = recip_wave<P>(LW[0].Cb, LW[0].Cb, L.ST);
+            if (!ok && lane_id() == 0) atomicOr(args.err, 2);
+            for (int w = W - 1; w >= 1; w--) {
+                wave_sync();
+                build_toeplitz<P>(LW[0].Cb, L.TL, L.TH);   // T = 1/Q_w
+                build_hankel<P>(LW[w].Bb, L.HL, L.HH);      // P_w
+                wave_sync();
+                mfma_mul<P, true>(L.TL, L.TH, L.HL, L.HH, CS, LW[0].Cb, nullptr, nullptr, nullptr);  // T <- T P_w
+                wave_sync();
+                build_hankel<P>(LW[w].Cb, L.HL, L.HH);      // Q_{w-1}
+                wave_sync();
+                mfma_mul<P, true>(L.TL, L.TH, L.HL, L.HH, CS, LW[w].Bb, nullptr, nullptr, nullptr);  // 1/P_w
+            }
+            wave_sync();
+            kg_copy<P>(LW[0].Cb, LW[0].Bb);
+        }
+    }
+    __syncthreads();
+
+    // 3. back-substitution, h = g c and encoding (two steps per trip so that
+    // the operand register sets alternate at compile time)
+    if (gsz >= 1) build_toeplitz<P>(L.Bb, L.TL, L.TH);
+    for (int i = gsz; i >= 1; i -= 2) {
+        kg_back_step<P>(args, L, kw0, i, ra, rb);
+        if (i >= 2) kg_back_step<P>(args, L, kw0, i - 1, rb, ra);
+    }
+}
+
+// Workgroup LDS of the kernel above.
+template <int P, int W>
+constexpr size_t keygen_group_lds() {
+    return sizeof(KgWave<P>) * W;
+}
+
+}  // namespace ntrup

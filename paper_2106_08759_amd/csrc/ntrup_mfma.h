@@ -135,22 +135,10 @@ __device__ __forceinline__ void build_hankel(const int16_t* X, uint8_t* HL, uint
     }
 }
 
-// Toeplitz fragment of K-step kappa from a reversed limb array.
-template <int P>
-__device__ __forceinline__ mf_v4i toeplitz_frag(const uint8_t* T, int kappa, int base_dw, int sh) {
-    const uint32_t* D = (const uint32_t*)T + base_dw - 16 * kappa;
-    const uint32_t d0 = D[0], d1 = D[1], d2 = D[2], d3 = D[3], d4 = D[4];
-    mf_v4i f;
-    f[0] = (int)__builtin_amdgcn_alignbyte(d1, d0, sh);
-    f[1] = (int)__builtin_amdgcn_alignbyte(d2, d1, sh);
-    f[2] = (int)__builtin_amdgcn_alignbyte(d3, d2, sh);
-    f[3] = (int)__builtin_amdgcn_alignbyte(d4, d3, sh);
-    return f;
-}
-
 // conv of T-operand (limbs TL, TH) and H-operand (limbs HL, and HH when
 // H_BIG) over the tiles [T0, T1), written to CS as centered int16:
-// CS[16w + r] = conv_{16w+r} mod q.
+// CS[16w + r] = conv_{16w+r} mod q.  Software-pipelined: the fragments of
+// K-step k+1 are read from LDS while the MFMAs of K-step k run.
 template <int P, bool H_BIG, int T0, int T1>
 __device__ __forceinline__ void mfma_conv(const uint8_t* TL, const uint8_t* TH, const uint8_t* HL,
                                           const uint8_t* HH, int16_t* CS) {
@@ -162,7 +150,9 @@ __device__ __forceinline__ void mfma_conv(const uint8_t* TL, const uint8_t* TH, 
     const int rc = lane & 15, g = lane >> 4;
     // Toeplitz read position of K-step 0: bytes from Z0 - 16 g - rc
     const int s0 = S::Z0 - 16 * g - rc;
-    const int sh = s0 & 3, base_dw = s0 >> 2;
+    const int sh = s0 & 3;
+    const uint32_t* tl32 = (const uint32_t*)TL + (s0 >> 2);
+    const uint32_t* th32 = (const uint32_t*)TH + (s0 >> 2);
     // Hankel read position of tile 0, K-step 0: block rc - g
     const uint8_t* hl = HL + S::HOFF + 16 * (rc - g);
     const uint8_t* hh = H_BIG ? HH + S::HOFF + 16 * (rc - g) : hl;
@@ -173,26 +163,58 @@ __device__ __forceinline__ void mfma_conv(const uint8_t* TL, const uint8_t* TH, 
         acc1[t] = mf_v4i{0, 0, 0, 0};
         acc2[t] = mf_v4i{0, 0, 0, 0};
     }
+    // fragments of the next K-step
+    uint32_t nDL[5], nDH[5];
+    mf_v4i nBL[NTC], nBH[NTC];
+    auto load_step = [&](int k) {
 #pragma unroll
-    for (int k = KLO; k <= KHI; k++) {
-        // one K-step's fragments in flight at a time (bounds register use)
-        if (NTRUP_MF_SCHED) __builtin_amdgcn_sched_barrier(0);
-        const mf_v4i tl = toeplitz_frag<P>(TL, k, base_dw, sh);
-        const mf_v4i th = toeplitz_frag<P>(TH, k, base_dw, sh);
+        for (int j = 0; j < 5; j++) {
+            nDL[j] = tl32[j - 16 * k];
+            nDH[j] = th32[j - 16 * k];
+        }
 #pragma unroll
         for (int t = 0; t < NTC; t++) {
             if (k < S::klo(T0 + t) || k > S::khi(T0 + t)) continue;
             const int off = 16 * (16 * (T0 + t) - 4 * k);
-            const mf_v4i bl = *(const mf_v4i*)(hl + off);
+            nBL[t] = *(const mf_v4i*)(hl + off);
+            if (H_BIG) nBH[t] = *(const mf_v4i*)(hh + off);
+        }
+    };
+    load_step(KLO);
+#pragma unroll
+    for (int k = KLO; k <= KHI; k++) {
+        // one K-step of fragments in flight beyond the current one
+        if (NTRUP_MF_SCHED) __builtin_amdgcn_sched_barrier(0);
+        uint32_t DL[5], DH[5];
+        mf_v4i BL[NTC], BH[NTC];
+#pragma unroll
+        for (int j = 0; j < 5; j++) {
+            DL[j] = nDL[j];
+            DH[j] = nDH[j];
+        }
+#pragma unroll
+        for (int t = 0; t < NTC; t++) {
+            BL[t] = nBL[t];
+            BH[t] = nBH[t];
+        }
+        if (k < KHI) load_step(k + 1);
+        mf_v4i tl, th;
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            tl[j] = (int)__builtin_amdgcn_alignbyte(DL[j + 1], DL[j], sh);
+            th[j] = (int)__builtin_amdgcn_alignbyte(DH[j + 1], DH[j], sh);
+        }
+#pragma unroll
+        for (int t = 0; t < NTC; t++) {
+            if (k < S::klo(T0 + t) || k > S::khi(T0 + t)) continue;
             if (H_BIG) {
-                const mf_v4i bh = *(const mf_v4i*)(hh + off);
-                acc0[t] = __builtin_amdgcn_mfma_i32_16x16x64_i8(tl, bl, acc0[t], 0, 0, 0);
-                acc1[t] = __builtin_amdgcn_mfma_i32_16x16x64_i8(tl, bh, acc1[t], 0, 0, 0);
-                acc1[t] = __builtin_amdgcn_mfma_i32_16x16x64_i8(th, bl, acc1[t], 0, 0, 0);
-                acc2[t] = __builtin_amdgcn_mfma_i32_16x16x64_i8(th, bh, acc2[t], 0, 0, 0);
+                acc0[t] = __builtin_amdgcn_mfma_i32_16x16x64_i8(tl, BL[t], acc0[t], 0, 0, 0);
+                acc1[t] = __builtin_amdgcn_mfma_i32_16x16x64_i8(tl, BH[t], acc1[t], 0, 0, 0);
+                acc1[t] = __builtin_amdgcn_mfma_i32_16x16x64_i8(th, BL[t], acc1[t], 0, 0, 0);
+                acc2[t] = __builtin_amdgcn_mfma_i32_16x16x64_i8(th, BH[t], acc2[t], 0, 0, 0);
             } else {
-                acc0[t] = __builtin_amdgcn_mfma_i32_16x16x64_i8(tl, bl, acc0[t], 0, 0, 0);
-                acc1[t] = __builtin_amdgcn_mfma_i32_16x16x64_i8(th, bl, acc1[t], 0, 0, 0);
+                acc0[t] = __builtin_amdgcn_mfma_i32_16x16x64_i8(tl, BL[t], acc0[t], 0, 0, 0);
+                acc1[t] = __builtin_amdgcn_mfma_i32_16x16x64_i8(th, BL[t], acc1[t], 0, 0, 0);
             }
         }
     }
@@ -215,17 +237,77 @@ __device__ __forceinline__ void mfma_conv(const uint8_t* TL, const uint8_t* TH, 
     }
 }
 
-// c = a * b in R/q from the staged convolution: c_i for i = lane + 64u.
-// Writes dst[i] (LDS, int16) and, when row != nullptr, row[i] (global).
+// c = a * b in R/q from the staged convolution:
+//   c_i = conv_i + conv_{i+p} + [i >= 1] conv_{i+p-1},
+// four consecutive outputs i = 4 lane + 256 u + t per lane.  Any of
+//   dst  (LDS int16, c_i at dst[i]),
+//   TLo/THo (LDS, the reversed Toeplitz limbs of c for the next product:
+//        TLo[Z0 - i] = lo(c_i), THo[Z0 - i] = hi(c_i)),
+//   row  (global int16)
+// may be nullptr.
 template <int P>
-__device__ __forceinline__ void mfma_fold(const int16_t* CS, int16_t* dst, int16_t* row) {
-    constexpr int Q = Param<P>::q;
-    for (int i = lane_id(); i < P; i += 64) {
-        int32_t v = (int32_t)CS[i] + (int32_t)CS[i + P];
-        if (i >= 1) v += CS[i + P - 1];
-        const int16_t c = (int16_t)freeze<Q>(v);
-        if (dst) dst[i] = c;
-        if (row) row[i] = c;
+__device__ __forceinline__ void mfma_fold(const int16_t* CS, int16_t* dst, uint8_t* TLo, uint8_t* THo,
+                                          int16_t* row) {
+    using S = MfShape<P>;
+    constexpr int Q = S::Q;
+    constexpr int NU = ceil_div(P, 256);
+    static_assert(S::CLEN >= 2 * P + 4, "the last window read stays in the staging");
+    static_assert((S::Z0 - 3) % 4 == 0, "reversed limb words are aligned");
+    const int lane = lane_id();
+    uint32_t A[NU][2], E[NU][3];
+#pragma unroll
+    for (int u = 0; u < NU; u++) {
+        const int i = 4 * lane + 256 * u;
+        if (i < P) {
+            const uint2 a = *(const uint2*)(CS + i);
+            const uint32_t* e = (const uint32_t*)(CS + i + P - 1);   // i + p - 1 is even
+            A[u][0] = a.x;
+            A[u][1] = a.y;
+            E[u][0] = e[0];
+            E[u][1] = e[1];
+            E[u][2] = e[2];
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < NU; u++) {
+        const int i = 4 * lane + 256 * u;
+        if (i >= P) continue;
+        int32_t c[4];
+#pragma unroll
+        for (int t = 0; t < 4; t++) {
+            const int32_t cs = (int16_t)(A[u][t >> 1] >> (16 * (t & 1)));
+            const int32_t e0 = (int16_t)(E[u][t >> 1] >> (16 * (t & 1)));               // conv_{i+p-1+t}
+            const int32_t e1 = (int16_t)(E[u][(t + 1) >> 1] >> (16 * ((t + 1) & 1)));   // conv_{i+p+t}
+            const int32_t v = cs + e1 + ((i + t >= 1) ? e0 : 0);
+            c[t] = (i + t < P) ? freeze<Q>(v) : 0;
+        }
+        if (dst) {
+            if (i + 3 < P) {
+                *(uint2*)(dst + i) = make_uint2((uint32_t)(uint16_t)c[0] | ((uint32_t)(uint16_t)c[1] << 16),
+                                                (uint32_t)(uint16_t)c[2] | ((uint32_t)(uint16_t)c[3] << 16));
+            } else {
+#pragma unroll
+                for (int t = 0; t < 4; t++)
+                    if (i + t < P) dst[i + t] = (int16_t)c[t];
+            }
+        }
+        if (TLo) {
+            uint32_t lo = 0, hi = 0;
+#pragma unroll
+            for (int t = 0; t < 4; t++) {
+                uint32_t l, h;
+                split_limb(c[t], l, h);
+                lo |= l << (8 * (3 - t));
+                hi |= h << (8 * (3 - t));
+            }
+            *(uint32_t*)(TLo + S::Z0 - i - 3) = lo;
+            *(uint32_t*)(THo + S::Z0 - i - 3) = hi;
+        }
+        if (row) {
+#pragma unroll
+            for (int t = 0; t < 4; t++)
+                if (i + t < P) row[i + t] = (int16_t)c[t];
+        }
     }
 }
 
@@ -257,13 +339,15 @@ __device__ __forceinline__ void mfma_conv_chunks(const uint8_t* TL, const uint8_
 }
 
 // c = a * b: T-operand limbs (TL, TH) and H-operand limbs (HL, HH) already
-// built; CS = conv staging (CLEN int16).  Ends with the result in dst / row.
+// built; CS = conv staging (CLEN int16).  Ends with the result in dst, the
+// Toeplitz limbs (TLo, THo; may be TL, TH themselves) and / or row.
+// Wave-local: the caller orders the inputs (wave_sync) before the call.
 template <int P, bool H_BIG>
 __device__ __forceinline__ void mfma_mul(const uint8_t* TL, const uint8_t* TH, const uint8_t* HL, const uint8_t* HH,
-                                         int16_t* CS, int16_t* dst, int16_t* row) {
+                                         int16_t* CS, int16_t* dst, uint8_t* TLo, uint8_t* THo, int16_t* row) {
     mfma_conv_chunks<P, H_BIG, 0>(TL, TH, HL, HH, CS);
-    __syncthreads();
-    mfma_fold<P>(CS, dst, row);
+    wave_sync();
+    mfma_fold<P>(CS, dst, TLo, THo, row);
 }
 
 }  // namespace ntrup

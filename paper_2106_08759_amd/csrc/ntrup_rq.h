@@ -60,6 +60,16 @@ struct RqShape {
 
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63); }
 
+// Orders the LDS traffic of one wave (lanes exchanging data through LDS):
+// the LDS executes a wave's instructions in order, so a compiler fence and a
+// wait for the wave's own outstanding LDS operations suffice -- no workgroup
+// barrier, and global loads in flight stay in flight.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0), vmcnt and expcnt unconstrained
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Select without a branch: mask is all-ones or all-zeros.
 __device__ __forceinline__ int32_t bsel(int32_t mask, int32_t a, int32_t b) {
     return (a & mask) | (b & ~mask);
@@ -293,9 +303,9 @@ __device__ int recip_wave(const int16_t* Bin, int16_t* OUT, int32_t* STG) {
     }
 #pragma unroll
     for (int t = 0; t < RI; t++) STG[RI * lane + t] = freeze<Q>(mul24(inv, V[((t - SR) % RI + RI) % RI]));
-    __syncthreads();
+    wave_sync();
     for (int i = lane; i < P; i += 64) OUT[i] = (int16_t)STG[P - i];
-    __syncthreads();
+    wave_sync();
     return delta == 0;
 }
 

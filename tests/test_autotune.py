@@ -16,6 +16,9 @@ def test_candidates_cover_the_knobs():
     assert {c["retry_parallel_attempts"] for c in c1277} == {2, 4, 8}
     assert all(c["retry_lanes_per_key"] * c["retry_parallel_attempts"] <= 64 for c in c1277)
     assert all(c["group_size"] <= 16 for c in autotune.candidates(761, 10))
+    assert {c["inverse_share"] for c in c761} == {1, 2, 4, 8}
+    assert {c["inverse_share"] for c in c1277} == {1, 2, 4}          # LDS bound for p = 1277
+    assert {(c["group_size"], c["inverse_share"]) for c in autotune.candidates(761, 10)} == {(16, 1)}
 
 
 def test_bucket():

@@ -127,6 +127,25 @@ def test_product_engine_bit_exact(ctx, p, engine):
         ctx.set_config(p, **base)
 
 
+@pytest.mark.parametrize("p", [653, 761, 857, 1277])
+def test_inverse_share_bit_exact(ctx, p):
+    """W Montgomery groups sharing one reciprocal (a second level of the batch
+    inversion): same keys for every W and group size, including workgroups
+    whose last waves have few or no keys."""
+    n = 200
+    ref = oracle_pool.oracle_keys(wl.SEED, p, range(n))
+    rpk, rsk = oracle_pool.pk_sk_arrays(ref, range(n))
+    base = ctx.get_config(p)
+    try:
+        for W in ((1, 2, 4) if p == 1277 else (1, 2, 4, 8)):
+            for G in (1, 7, 32):
+                ctx.set_config(p, product_engine=1, inverse_share=W, group_size=G)
+                pk, sk = ctx.batch_keygen(p, wl.SEED, 0, n)
+                assert np.array_equal(host(pk), rpk) and np.array_equal(host(sk), rsk), (p, W, G)
+    finally:
+        ctx.set_config(p, **base)
+
+
 def test_mixed_parameter_sets(ctx):
     jobs = [(653, 100, 40), (761, 7, 33), (857, 0, 17), (1277, 3, 21)]
     outs = ctx.batch_keygen_mixed(wl.SEED, jobs)
