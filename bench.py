@@ -9,10 +9,13 @@ value     keys/s over the timed steps (inputs: a 32-byte seed; outputs stay in
           HBM; no host copies inside the timed region)
 roofline  the dominant kernel's algorithmic integer ops per launch divided by
           its average launch time, measured with HIP events recorded on the
-          launch stream during the timed steps.  Peaks: 39.3 T int32
-          lane-ops/s for the vector-ALU kernels (256 CU x 64 lanes x 2.4 GHz;
-          R/3 divsteps, Short sampling); 5.0 P int8 ops/s for the Montgomery
-          group kernel, whose R/q products run on the int8 matrix cores
+          launch stream during the timed steps.  Peaks: 78.6 T int32
+          lane-ops/s for the vector-ALU kernels (256 CU x 4 SIMD x 32 lanes x
+          2.4 GHz, the rate of the published fp32 vector peak; R/3 divsteps,
+          Short sampling); 5.0 P int8 ops/s for the Montgomery group kernel,
+          whose R/q products run on the int8 matrix cores.  traffic: HBM bytes
+          per launch from the committed counter summary, null once the kernel
+          sources differ from the ones it was measured on
 cpu_baseline  the CPU oracle (plain C, -O2) on the host cores, bounded sample
 """
 from __future__ import annotations
@@ -27,8 +30,39 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-VALU_PEAK = 256 * 64 * 2.4e9  # int32 lane-ops per second
-I8_MFMA_PEAK = 5.0e15          # dense int8 matrix-core ops per second (2 per multiply-add)
+# 256 CUs x 4 SIMDs x 32 lanes per clock x 2.4 GHz: the rate behind the
+# published 157.3 TFLOP/s fp32 vector peak (78.6 T FMA/s), applied to int32
+VALU_PEAK = 256 * 4 * 32 * 2.4e9   # int32 lane-ops per second
+I8_MFMA_PEAK = 5.0e15              # dense int8 matrix-core ops per second (2 per multiply-add)
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+
+
+def sources_digest() -> str:
+    """sha256 over the HIP sources, to tell whether stored counters still apply."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2106_08759_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".h", ".hip")):
+            h.update(name.encode())
+            with open(os.path.join(csrc, name), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()
+
+
+def stored_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE scaled by a plain-copy calibration), or None
+    when there is none or the kernel sources changed since it was taken."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            data = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if data.get("sources_sha256") != sources_digest():
+        return None
+    entry = data.get("kernels", {}).get(kernel)
+    return None if entry is None else entry["bytes_per_launch"]
 
 
 def ceil_div(a, b):
@@ -189,7 +223,7 @@ def main():
     roofline = {"bound": "mfma" if dom == "group" else "alu", "kernel": kernel_names[dom],
                 "achieved": round(achieved / 1e12, 3),
                 "peak": round(peaks[dom] / 1e12, 2), "unit": units[dom], "frac": round(achieved / peaks[dom], 4),
-                "traffic": None,
+                "traffic": stored_traffic(kernel_names[dom]),
                 "ops_per_launch": ops[dom], "avg_launch_ms": round(avg[dom], 4)}
     stage_fracs = {k: {"ms": round(avg[k], 4),
                        "frac": (round(ops[k] / (avg[k] / 1e3) / peaks[k], 4) if k in ops and avg[k] > 0 else None)}
@@ -239,9 +273,10 @@ def main():
             from paper_2106_08759_amd import serve
             rep = serve.serve(serve.GpuBackend(0), args.serve_rate, args.serve_seconds,
                               {761: 0.7, 857: 0.2, 1277: 0.1}, wl.SEED,
-                              refill={761: 16384, 857: 8192, 1277: 4096}, blocks=4)
+                              refill={761: 16384, 857: 8192, 1277: 4096}, blocks=4, tune=True)
             extras["serving"] = {k: rep[k] for k in ("rate_req_per_s", "seconds", "requests", "served",
-                                                     "keys_per_s", "latency_ms", "workspaces", "hbm_used_bytes")}
+                                                     "keys_per_s", "latency_ms", "latency_ms_by_p", "workspaces",
+                                                     "hbm_used_bytes")}
 
     out = {
         "metric": "sntrup761 keys/sec on 1 MI355X (bit-exact)",

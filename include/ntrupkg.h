@@ -7,7 +7,10 @@
  *   Short, h = g/(3f) in R/q, key pair (h, (f, 1/g)); batched as in
  *   Algorithm 1 (BatchKeyGen), the R/q reciprocals of a group of G keys shared
  *   by Montgomery's trick (Section 2.2: prefix products, one reciprocal,
- *   back-substitution; 3G-3 products + 1 reciprocal for G keys).  The R/3
+ *   back-substitution; 3G-3 products + 1 reciprocal for G keys), and W such
+ *   groups sharing one reciprocal through a second level of the same trick
+ *   (ntrup_config.inverse_share).  R/q products run on the int8 matrix cores
+ *   (exact: two 7-bit limbs per residue) or on the vector units.  The R/3
  *   reciprocal is computed per key by constant-time divsteps (the extended-gcd
  *   algorithm of Bernstein and Yang that Section 3.1 cites), which also
  *   decides invertibility.  R = Z[x]/(x^p - x - 1), parameter sets of

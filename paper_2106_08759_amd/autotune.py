@@ -74,6 +74,14 @@ def candidates(p: int, n: int):
     return [dict(g, **r) for g in group_candidates(p, n) for r in r3_candidates(p)]
 
 
+def device_id(device: int) -> str:
+    """Cache key of the device: its architecture (the marketing name can read
+    empty, e.g. under a profiler), else its name."""
+    import torch
+    props = torch.cuda.get_device_properties(device)
+    return getattr(props, "gcnArchName", "") or props.name or "unknown"
+
+
 def _key(device_name: str, p: int, n: int) -> str:
     # v2: entries carry inverse_share and the matrix-core product engine
     return "%s|p=%d|n<=%d|v2" % (device_name, p, bucket(n))
@@ -125,7 +133,7 @@ def tune(ctx, p: int, n: int, seed: bytes | None = None, reps: int = 3, force: b
     from .workloads import SEED
 
     seed = seed or SEED
-    dev = torch.cuda.get_device_name(ctx.device)
+    dev = device_id(ctx.device)
     key = _key(dev, p, n)
     data = load_cache(path)
     if not force and key in data:

@@ -69,6 +69,13 @@ class GpuBackend:
         ctx.reserve(p, n)
         return ctx.workspace_bytes()
 
+    def configure(self, ctx, p, n):
+        """Tuned configuration of (p, n) refills for this workspace (cached).
+        Refills never repeat their arguments (each starts at a new key index),
+        so they launch eagerly rather than through a captured graph."""
+        from . import autotune
+        autotune.tune(ctx, p, n, reps=2, use_graph=0)
+
     def keygen(self, ctx, p, seed, first_index, n, pk, sk, stream):
         ctx.batch_keygen(p, seed, first_index, n, pk, sk, stream=stream, check=False)
 
@@ -233,9 +240,10 @@ class Budget:
         if self.static > self.limit:
             raise MemoryError("pool rings need %d bytes, budget %d" % (self.static, self.limit))
 
-    def provision(self, backend, sizes, max_contexts: int):
+    def provision(self, backend, sizes, max_contexts: int, tune: bool = False):
         """Create as many workspaces as the budget pays for (at most
-        max_contexts); sizes = [(p, n)] of the refill batches."""
+        max_contexts); sizes = [(p, n)] of the refill batches.  With tune, each
+        workspace gets the autotuned configuration of every refill size."""
         probe = backend.context()
         ws = 0
         for p, n in sizes:
@@ -251,6 +259,10 @@ class Budget:
             for p, n in sizes:
                 backend.workspace_bytes(c, p, n)
             self.contexts.append(c)
+        if tune:
+            for c in self.contexts:
+                for p, n in sizes:
+                    backend.configure(c, p, n)
         self.free = list(self.contexts)
 
     def acquire(self):
@@ -277,7 +289,8 @@ def poisson_arrivals(rate: float, seconds: float, mix: dict, rng_seed: int = 5):
 
 def serve(backend, rate: float, seconds: float, mix: dict, seed: bytes, refill: dict, blocks: int = 4,
           low_water: dict | None = None, budget_bytes: int = 4 << 30, warm: bool = True,
-          sample_every: float = 0.01, record_keys: int = 0, rng_seed: int = 5, clock=time.perf_counter):
+          sample_every: float = 0.01, record_keys: int = 0, rng_seed: int = 5, clock=time.perf_counter,
+          tune: bool = False):
     """Run the request loop for `seconds` of Poisson arrivals.  Returns a report
     dict; with record_keys > 0 also the first record_keys delivered keys per p
     as (index, pk bytes, sk bytes)."""
@@ -285,7 +298,7 @@ def serve(backend, rate: float, seconds: float, mix: dict, seed: bytes, refill: 
     budget = Budget(budget_bytes)
     pools = {p: Pool(p, refill[p], blocks, (low_water or {}).get(p, 2 * refill[p]), backend, seed, budget)
              for p in mix}
-    budget.provision(backend, [(p, refill[p]) for p in mix], max_contexts=len(mix))
+    budget.provision(backend, [(p, refill[p]) for p in mix], max_contexts=len(mix), tune=tune)
     maxk = max(1024, int(rate * 0.01) + 1)
     host = {p: (backend.pinned(maxk, pools[p].pkb), backend.pinned(maxk, pools[p].skb)) for p in mix}
     if warm:  # fill the pools before the clock starts
@@ -300,6 +313,7 @@ def serve(backend, rate: float, seconds: float, mix: dict, seed: bytes, refill: 
     taken = {p: 0 for p in mix}                    # requests of p handed a key (copy issued)
     inflight_copies = []                           # (event, p, first request, count, key idx)
     lat_chunks = []
+    lat_by_p = {p: [] for p in mix}
     occupancy = []
     recorded = {p: [] for p in mix}
     t0 = clock()
@@ -321,6 +335,7 @@ def serve(backend, rate: float, seconds: float, mix: dict, seed: bytes, refill: 
             if backend.done(ev):
                 tdone = clock() - t0
                 lat_chunks.append(tdone - times[p][first:first + cnt])
+                lat_by_p[p].append(lat_chunks[-1])
                 if record_keys and len(recorded[p]) < record_keys:
                     hp, hs = host[p]
                     for r, key in enumerate(idx[: record_keys - len(recorded[p])]):
@@ -358,6 +373,9 @@ def serve(backend, rate: float, seconds: float, mix: dict, seed: bytes, refill: 
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)) * 1e3, 4),
                        "p99": round(float(np.percentile(lat, 99)) * 1e3, 4),
                        "max": round(float(lat.max()) * 1e3, 4)},
+        "latency_ms_by_p": {str(p): ({"p50": round(float(np.percentile(np.concatenate(v), 50)) * 1e3, 4),
+                                      "p99": round(float(np.percentile(np.concatenate(v), 99)) * 1e3, 4)}
+                                     if v else None) for p, v in lat_by_p.items()},
         "pools": {str(p): {"refill": pools[p].refill, "blocks": blocks, "low_water": pools[p].low_water,
                            "refills": pools[p].stats.refills, "deferred": pools[p].stats.deferred,
                            "generated": pools[p].stats.keys_generated} for p in mix},
@@ -380,6 +398,7 @@ def main(argv=None):
                     metavar=("R761", "R857", "R1277"))
     ap.add_argument("--blocks", type=int, default=4)
     ap.add_argument("--occupancy", action="store_true", help="include the occupancy time series")
+    ap.add_argument("--no-tune", action="store_true", help="refill with the library defaults")
     args = ap.parse_args(argv)
     from .workloads import SEED
     mix = {761: 0.7, 857: 0.2, 1277: 0.1}
@@ -387,7 +406,7 @@ def main(argv=None):
     be = GpuBackend(0)
     for r in args.rate:
         rep = serve(be, r, args.seconds, mix, SEED, refill, blocks=args.blocks,
-                    budget_bytes=int(args.budget_gib * (1 << 30)))
+                    budget_bytes=int(args.budget_gib * (1 << 30)), tune=not args.no_tune)
         if not args.occupancy:
             occ = rep.pop("occupancy")
             rep["occupancy_min"] = {c: min(s[i] for s in occ["samples"]) for i, c in

@@ -47,6 +47,9 @@ class FakeBackend:
         ctx.ws = max(ctx.ws, 3000 * n)
         return ctx.ws
 
+    def configure(self, ctx, p, n):
+        self.configured = getattr(self, "configured", []) + [(p, n)]
+
     def keygen(self, ctx, p, seed, first, n, pk, sk, stream):
         assert ctx.ws >= 3000 * n
         ctx.calls += 1
