@@ -93,7 +93,10 @@ const char *ntrup_strerror(int code);
  *   retry_passes         0..8 compacted passes over keys whose g was not a
  *                        unit, before a final pass that loops up to 64 draws
  *   use_graph            replay the pipeline from a captured hipGraph when
- *                        the call's arguments repeat
+ *                        the call's arguments repeat; a captured pipeline
+ *                        runs its stages on one stream, while eager launches
+ *                        of a single job overlap the prefix kernel with the
+ *                        R/3 stage on a second stream
  *   product_engine       R/q products on the vector units (0: v_dot2 Toeplitz
  *                        dot products) or on the int8 matrix cores (1: block
  *                        Toeplitz MFMA with two 7-bit limbs); both exact
@@ -146,13 +149,17 @@ int ntrup_batch_keygen_mixed(ntrup_ctx *ctx, const uint8_t *seed, const ntrup_jo
  * 0, NTRUP_EAGAIN, NTRUP_EFAULT or NTRUP_EIO. */
 int ntrup_ctx_status(ntrup_ctx *ctx, void *stream);
 
-/* Stage timing with HIP events recorded on the launch stream.  After
+/* Stage timing with HIP events recorded on the launch streams.  After
  * ntrup_ctx_timing_begin(ctx, m) the next m pipelines (one per job of a keygen
- * call; graph replay is bypassed meanwhile) record 5 events each, bounding
- * 4 stages: [0] Short sampler, [1] R/3 main pass, [2] R/3 retry and final
- * passes, [3] Montgomery group kernel.  ntrup_ctx_timing_end waits for them,
- * writes the summed milliseconds per stage to ms[0..3] (nstages >= 4), the
- * number of pipelines timed to *npipelines, and switches timing off. */
+ * call; graph replay is bypassed meanwhile) record 6 events each, bounding
+ * 5 stages: [0] Short sampler, [1] R/3 main pass, [2] R/3 retry and final
+ * passes, [3] prefix products and group reciprocals, [4] back-substitution,
+ * h = g/(3f) and encoding.  With the matrix-core engine in an eager
+ * single-job call, [3] runs on a side stream beside [1] and [4] is timed from
+ * the later of its inputs.
+ * ntrup_ctx_timing_end waits for them, writes the summed milliseconds per
+ * stage to ms[0..4] (nstages >= 5), the number of pipelines timed to
+ * *npipelines, and switches timing off. */
 int ntrup_ctx_timing_begin(ntrup_ctx *ctx, int max_pipelines);
 int ntrup_ctx_timing_end(ntrup_ctx *ctx, double *ms, int nstages, int *npipelines);
 

@@ -189,16 +189,16 @@ class Context:
     def workspace_bytes(self) -> int:
         return lib().ntrup_ctx_workspace_bytes(self._h)
 
-    STAGES = ("sample_short", "r3_main", "r3_retry", "group")
+    STAGES = ("sample_short", "r3_main", "r3_retry", "group_prefix", "group_back")
 
     def timing_begin(self, max_pipelines: int):
         self._check(lib().ntrup_ctx_timing_begin(self._h, max_pipelines), "timing_begin")
 
     def timing_end(self):
         """-> (dict stage -> summed ms, number of pipelines timed)"""
-        ms = (ctypes.c_double * 4)()
+        ms = (ctypes.c_double * len(self.STAGES))()
         cnt = ctypes.c_int()
-        self._check(lib().ntrup_ctx_timing_end(self._h, ms, 4, ctypes.byref(cnt)), "timing_end")
+        self._check(lib().ntrup_ctx_timing_end(self._h, ms, len(self.STAGES), ctypes.byref(cnt)), "timing_end")
         return dict(zip(self.STAGES, list(ms))), cnt.value
 
     def status(self, stream=None) -> int:

@@ -16,7 +16,9 @@ Knobs (see ``ntrup_config`` in include/ntrupkg.h):
 
 The group knobs (G, W) and the R/3 knobs act on different kernels, so they
 are tuned one after the other: first (G, W) with the default R/3 knobs, then
-the R/3 knobs with the chosen (G, W).  The product tiles are fixed by p.
+the R/3 knobs with the chosen (G, W), each timed in the launch form of the
+tuning mode (eager launches run the prefix kernel beside the R/3 stage; graph
+replay is one linear stream per job); mode "auto" then compares the two forms.  The product tiles are fixed by p.
 Every candidate is timed on the real pipeline with HIP events on the launch
 stream; the winner per (device, p, N rounded up to a power of two) is cached
 as JSON.
@@ -27,7 +29,7 @@ import json
 import os
 import time
 
-GROUP_SIZES = (16, 32, 64, 128)
+GROUP_SIZES = (8, 16, 32, 64, 128)
 SHARES = (1, 2, 4, 8)
 KNOBS = ("group_size", "inverse_share", "lanes_per_key", "retry_passes", "retry_lanes_per_key",
          "retry_parallel_attempts")
@@ -62,7 +64,7 @@ def group_candidates(p: int, n: int):
 
 def r3_candidates(p: int):
     """R/3 knob settings worth timing for degree p."""
-    lpks = (2, 4) if p > 800 else (1, 2, 4)      # one lane per key spills for large p
+    lpks = (2, 4, 8) if p > 800 else (1, 2, 4, 8)   # one lane per key spills for large p
     # (retry passes, retry lanes per key, attempts side by side)
     retry = [(1, 8, 4)] if p not in (653, 1277) else [(1, 8, 2), (1, 8, 4), (1, 8, 8), (0, 8, 4), (1, 4, 4)]
     return [{"lanes_per_key": l, "retry_passes": r, "retry_lanes_per_key": rl, "retry_parallel_attempts": ra}
@@ -82,9 +84,12 @@ def device_id(device: int) -> str:
     return getattr(props, "gcnArchName", "") or props.name or "unknown"
 
 
-def _key(device_name: str, p: int, n: int) -> str:
-    # v2: entries carry inverse_share and the matrix-core product engine
-    return "%s|p=%d|n<=%d|v2" % (device_name, p, bucket(n))
+MODES = ("auto", "eager", "graph")
+
+
+def _key(device_name: str, p: int, n: int, mode: str = "auto") -> str:
+    # v3: entries carry inverse_share and the launch form (eager / graph)
+    return "%s|p=%d|n<=%d|%s|v3" % (device_name, p, bucket(n), mode)
 
 
 def load_cache(path: str | None = None) -> dict:
@@ -105,14 +110,15 @@ def save_cache(data: dict, path: str | None = None) -> None:
     os.replace(tmp, path)
 
 
-def lookup(device_name: str, p: int, n: int, path: str | None = None):
-    return load_cache(path).get(_key(device_name, p, n))
+def lookup(device_name: str, p: int, n: int, path: str | None = None, mode: str = "auto"):
+    return load_cache(path).get(_key(device_name, p, n, mode))
 
 
-def time_config(ctx, p: int, n: int, cfg: dict, seed: bytes, reps: int, pk, sk) -> float:
-    """Mean milliseconds per call of the pipeline under cfg (eager launches)."""
+def time_config(ctx, p: int, n: int, cfg: dict, seed: bytes, reps: int, pk, sk, use_graph: int = 0) -> float:
+    """Mean milliseconds per call of the pipeline under cfg (eager launches,
+    which run the prefix kernel beside the R/3 stage, or graph replay)."""
     import torch
-    ctx.set_config(p, use_graph=0, **cfg)
+    ctx.set_config(p, use_graph=use_graph, **cfg)
     ctx.batch_keygen(p, seed, 0, n, pk, sk, check=True)  # warm
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -125,22 +131,29 @@ def time_config(ctx, p: int, n: int, cfg: dict, seed: bytes, reps: int, pk, sk) 
 
 
 def tune(ctx, p: int, n: int, seed: bytes | None = None, reps: int = 3, force: bool = False,
-         path: str | None = None, use_graph: int = 1) -> dict:
+         path: str | None = None, mode: str = "auto") -> dict:
     """Pick and apply the fastest configuration for (p, n); returns the cache entry
-    {"config": ..., "ms": ..., "keys_per_s": ..., "table": [...], "cached": bool}."""
+    {"config": ..., "use_graph": 0/1, "ms": ..., "keys_per_s": ..., "table": [...],
+    "cached": bool}.  mode: "eager" times and applies eager launches (the
+    prefix kernel beside the R/3 stage; for calls whose arguments never repeat,
+    or timed with stage events), "graph" times and applies graph replay (one
+    linear stream per job, as the jobs of a mixed call run), "auto" tunes the
+    knobs eagerly and then picks the faster launch form."""
+    assert mode in MODES, mode
     import torch
     from . import params
     from .workloads import SEED
 
     seed = seed or SEED
     dev = device_id(ctx.device)
-    key = _key(dev, p, n)
+    key = _key(dev, p, n, mode)
     data = load_cache(path)
     if not force and key in data:
         entry = dict(data[key])
-        ctx.set_config(p, use_graph=use_graph, **entry["config"])
+        ctx.set_config(p, use_graph=entry["use_graph"], **entry["config"])
         entry["cached"] = True
         return entry
+    ug = 1 if mode == "graph" else 0
     prm = params(p)
     pk = torch.empty((n, prm.pk_bytes), dtype=torch.uint8, device="cuda:%d" % ctx.device)
     sk = torch.empty((n, prm.sk_bytes), dtype=torch.uint8, device="cuda:%d" % ctx.device)
@@ -152,20 +165,32 @@ def tune(ctx, p: int, n: int, seed: bytes | None = None, reps: int = 3, force: b
     # phase 1: the group stage
     for gc in group_candidates(p, n):
         cfg = dict(cur, **gc)
-        table.append(dict(cfg, ms=round(time_config(ctx, p, n, cfg, seed, reps, pk, sk), 4)))
+        table.append(dict(cfg, ms=round(time_config(ctx, p, n, cfg, seed, reps, pk, sk, ug), 4)))
     best = min(table, key=lambda r: r["ms"])
     cur.update({k: best[k] for k in ("group_size", "inverse_share")})
     # phase 2: the R/3 stage
     for rc in r3_candidates(p):
         cfg = dict(cur, **rc)
-        table.append(dict(cfg, ms=round(time_config(ctx, p, n, cfg, seed, reps, pk, sk), 4)))
+        table.append(dict(cfg, ms=round(time_config(ctx, p, n, cfg, seed, reps, pk, sk, ug), 4)))
     best = min(table, key=lambda r: r["ms"])
     cfg = {k: best[k] for k in KNOBS}
-    entry = {"config": cfg, "ms": best["ms"], "keys_per_s": round(n / best["ms"] * 1e3, 1),
-             "n": n, "table": table, "tuned_at": time.strftime("%Y-%m-%dT%H:%M:%S")}
+    # phase 3 (auto): eager launches (stage overlap) or graph replay (one
+    # linear stream, no launch overhead) for the chosen knobs
+    if mode == "auto":
+        eager_ms = best["ms"]
+        graph_ms = round(time_config(ctx, p, n, cfg, seed, reps, pk, sk, use_graph=1), 4)
+        graph = 1 if graph_ms < eager_ms else 0
+        ms = min(eager_ms, graph_ms)
+    else:
+        graph, ms = ug, best["ms"]
+        eager_ms = ms if not ug else None
+        graph_ms = ms if ug else None
+    entry = {"config": cfg, "use_graph": graph, "mode": mode, "ms": ms, "eager_ms": eager_ms,
+             "graph_ms": graph_ms, "n": n, "table": table, "tuned_at": time.strftime("%Y-%m-%dT%H:%M:%S")}
+    entry["keys_per_s"] = round(n / entry["ms"] * 1e3, 1)
     data[key] = entry
     save_cache(data, path)
-    ctx.set_config(p, use_graph=use_graph, **cfg)
+    ctx.set_config(p, use_graph=graph, **cfg)
     return dict(entry, cached=False)
 
 
@@ -176,11 +201,12 @@ def main(argv=None):
     ap.add_argument("--n", type=int, default=65536)
     ap.add_argument("--reps", type=int, default=3)
     ap.add_argument("--force", action="store_true")
+    ap.add_argument("--mode", choices=MODES, default="auto")
     args = ap.parse_args(argv)
     from . import Context
     ctx = Context(0)
     for p in args.p:
-        e = tune(ctx, p, args.n, reps=args.reps, force=args.force)
+        e = tune(ctx, p, args.n, reps=args.reps, force=args.force, mode=args.mode)
         print(json.dumps({"p": p, "n": args.n, "config": e["config"], "ms": e["ms"],
                           "keys_per_s": e["keys_per_s"], "cached": e["cached"]}))
 

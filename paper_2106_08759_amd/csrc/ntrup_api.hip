@@ -32,6 +32,7 @@ struct Ws {
     uint32_t* gbits;
     uint32_t* ibits;
     int16_t* bscr;
+    int16_t* tinv;     // reciprocal of each Montgomery group's product
     uint8_t* attempts;
     int* lists[2];
     int* counters;
@@ -39,7 +40,7 @@ struct Ws {
 
 size_t ws_bytes(int p, size_t n) {
     const size_t wn = (size_t)ceil_div(p, 32);
-    return align256(n * p) + 2 * align256(wn * 2 * n * 4) + align256(n * p * 2) + align256(n) +
+    return align256(n * p) + 2 * align256(wn * 2 * n * 4) + 2 * align256(n * p * 2) + align256(n) +
            2 * align256(n * 4) + align256(kCounterInts * 4);
 }
 
@@ -51,6 +52,7 @@ Ws carve(void* base, int p, size_t n) {
     w.gbits = (uint32_t*)c;      c += align256(wn * 2 * n * 4);
     w.ibits = (uint32_t*)c;      c += align256(wn * 2 * n * 4);
     w.bscr = (int16_t*)c;        c += align256(n * p * 2);
+    w.tinv = (int16_t*)c;        c += align256(n * p * 2);   // at most n groups
     w.attempts = (uint8_t*)c;    c += align256(n);
     w.lists[0] = (int*)c;        c += align256(n * 4);
     w.lists[1] = (int*)c;        c += align256(n * 4);
@@ -97,6 +99,11 @@ struct ntrup_ctx {
     std::vector<int*> last_err;     // error words of the last keygen call
     hipStream_t cap_stream = nullptr;
     hipStream_t job_streams[kJobStreams] = {};
+    // side stream of single-job calls: Short sampling and the prefix half of
+    // the group stage run there beside the R/3 stage (they need only f)
+    hipStream_t side_stream = nullptr;
+    hipEvent_t side_fork = nullptr, side_join = nullptr;
+    hipEvent_t graph_done = nullptr;   // after the last graph launch
     hipEvent_t fork_event = nullptr;
     std::vector<hipEvent_t> join_events;
     bool have_graph = false;
@@ -105,11 +112,14 @@ struct ntrup_ctx {
     hipGraphExec_t exec = nullptr;
     // stage timing: kStages+1 events per recorded pipeline
     std::vector<hipEvent_t> tev;
+    std::vector<char> t_side;       // pipeline ran its side stream
     int t_max = 0, t_used = 0;
 };
 
 namespace {
-constexpr int kStages = 4;  // sample_short, r3 main pass, r3 retry/final passes, group
+// sample_short, r3 main pass, r3 retry/final passes, group prefix + reciprocal,
+// group back-substitution + encoding
+constexpr int kStages = 5;
 }
 
 namespace {
@@ -180,19 +190,62 @@ hipEvent_t stage_event(ntrup_ctx* ctx, int b) {
     return ctx->tev[(size_t)ctx->t_used * (kStages + 1) + b];
 }
 
-// Enqueue the whole KeyGen pipeline of one job on `st`.  zero_err: also clear
-// the error word (once per API call).
+// Enqueue the whole KeyGen pipeline of one job on `st`.  side_ok: with the
+// matrix-core engine, the prefix half of the group stage (which needs only
+// f) runs on ctx->side_stream beside the R/3 stage, forked from st after
+// Short sampling and joined before the back-substitution.  Otherwise -- graph
+// capture, the jobs of a mixed call (already concurrent branches), the plain
+// form -- every stage runs on st.  zero_err: also clear the error word (once
+// per API call).
+//
+// Stage events: 0 start; 1 end of sampling; 2 end of the prefix kernel
+// (the product engine 0 records it right after 1); 3 end of the R/3 main
+// pass; 4 end of the R/3 retry passes; 5 end.
 template <int P>
 int enqueue_keygen(ntrup_ctx* ctx, const ntrup_config& cfg, const Seed& seed, uint64_t first_index,
-                   size_t n, uint8_t* pk, uint8_t* sk, const Ws& w, hipStream_t st, bool zero_err) {
-    hipLaunchKernelGGL(zero_ints_kernel, dim3(1), dim3(64), 0, st, w.counters, zero_err ? kCounterInts : 16);
-    auto mark = [&](int b) {
-        if (hipEvent_t ev = stage_event(ctx, b)) (void)hipEventRecord(ev, st);
+                   size_t n, uint8_t* pk, uint8_t* sk, const Ws& w, hipStream_t st, bool side_ok, bool zero_err) {
+    const bool mfma = cfg.product_engine == 1;
+    const bool side = side_ok && mfma;
+    hipStream_t ss = side ? ctx->side_stream : st;
+    auto mark = [&](int b, hipStream_t on) {
+        if (hipEvent_t ev = stage_event(ctx, b)) (void)hipEventRecord(ev, on);
     };
-    mark(0);
+    GroupArgs g;
+    g.n = (int)n;
+    g.G = cfg.group_size;
+    g.f_rows = w.f_rows;
+    g.gbits = w.gbits;
+    g.ibits = w.ibits;
+    g.bscr = w.bscr;
+    g.pk = pk;
+    g.sk = sk;
+    g.err = w.counters + 32;
+    g.a_in = nullptr;
+    g.c_out = nullptr;
+    const int W = cfg.inverse_share;
+
+    hipLaunchKernelGGL(zero_ints_kernel, dim3(1), dim3(64), 0, st, w.counters, zero_err ? kCounterInts : 16);
+    mark(0, st);
     hipLaunchKernelGGL(sample_short_kernel<P>, dim3(grid_for(n, 4)), dim3(256), 0, st, seed, first_index, (int)n,
                        w.f_rows);
-    mark(1);
+    mark(1, st);
+    if (side) {
+        NTRUP_HIP(ctx, hipEventRecord(ctx->side_fork, st));
+        NTRUP_HIP(ctx, hipStreamWaitEvent(ss, ctx->side_fork, 0));
+    }
+    if (mfma) {
+        const dim3 grid(grid_for(n, (size_t)cfg.group_size * W)), blk(64 * W);
+        switch (W) {
+            case 1: hipLaunchKernelGGL((keygen_prefix_kernel<P, 1>), grid, blk, 0, ss, g, w.tinv); break;
+            case 2: hipLaunchKernelGGL((keygen_prefix_kernel<P, 2>), grid, blk, 0, ss, g, w.tinv); break;
+            case 4: hipLaunchKernelGGL((keygen_prefix_kernel<P, 4>), grid, blk, 0, ss, g, w.tinv); break;
+            default:
+                if constexpr (P != 1277) hipLaunchKernelGGL((keygen_prefix_kernel<P, 8>), grid, blk, 0, ss, g, w.tinv);
+                break;
+        }
+    }
+    mark(2, ss);
+    if (side) NTRUP_HIP(ctx, hipEventRecord(ctx->side_join, ss));
     R3Args a;
     a.seed = seed;
     a.first_index = first_index;
@@ -212,49 +265,30 @@ int enqueue_keygen(ntrup_ctx* ctx, const ntrup_config& cfg, const Seed& seed, ui
         a.spec = pass == 0 ? 1 : cfg.retry_parallel_attempts;
         a.max_rounds = last ? ceil_div(kMaxAttempts, a.spec) : 1;
         launch_r3<P>(pass == 0 ? cfg.lanes_per_key : cfg.retry_lanes_per_key, n, a, st);
-        if (pass == 0) mark(2);
+        if (pass == 0) mark(3, st);
     }
-    mark(3);
-    GroupArgs g;
-    g.n = (int)n;
-    g.G = cfg.group_size;
-    g.f_rows = w.f_rows;
-    g.gbits = w.gbits;
-    g.ibits = w.ibits;
-    g.bscr = w.bscr;
-    g.pk = pk;
-    g.sk = sk;
-    g.err = w.counters + 32;
-    g.a_in = nullptr;
-    g.c_out = nullptr;
-    if (cfg.product_engine == 1) {
-        const int W = cfg.inverse_share;
-        const dim3 grid(grid_for(n, (size_t)cfg.group_size * W)), blk(64 * W);
-        switch (W) {
-            case 1: hipLaunchKernelGGL((keygen_group_kernel<P, 1>), grid, blk, 0, st, g); break;
-            case 2: hipLaunchKernelGGL((keygen_group_kernel<P, 2>), grid, blk, 0, st, g); break;
-            case 4: hipLaunchKernelGGL((keygen_group_kernel<P, 4>), grid, blk, 0, st, g); break;
-            default:
-                if constexpr (P != 1277) hipLaunchKernelGGL((keygen_group_kernel<P, 8>), grid, blk, 0, st, g);
-                break;
-        }
+    mark(4, st);
+    if (side) NTRUP_HIP(ctx, hipStreamWaitEvent(st, ctx->side_join, 0));
+    if (mfma) {
+        hipLaunchKernelGGL((keygen_back_kernel<P>), dim3(grid_for(n, cfg.group_size)), dim3(64), 0, st, g,
+                           (const int16_t*)w.tinv);
     } else {
         hipLaunchKernelGGL((group_kernel<P, true>), dim3(grid_for(n, cfg.group_size)), dim3(64), 0, st, g);
     }
-    mark(4);
-    if (ctx->t_used < ctx->t_max) ctx->t_used++;
+    mark(5, st);
+    if (ctx->t_used < ctx->t_max) ctx->t_side[ctx->t_used++] = side;
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(ctx, e);
     return 0;
 }
 
 int enqueue_dispatch(ntrup_ctx* ctx, int p, const ntrup_config& cfg, const Seed& seed, uint64_t first_index,
-                     size_t n, uint8_t* pk, uint8_t* sk, const Ws& w, hipStream_t st, bool zero_err) {
+                     size_t n, uint8_t* pk, uint8_t* sk, const Ws& w, hipStream_t st, bool side_ok, bool zero_err) {
     switch (p) {
-        case 653: return enqueue_keygen<653>(ctx, cfg, seed, first_index, n, pk, sk, w, st, zero_err);
-        case 761: return enqueue_keygen<761>(ctx, cfg, seed, first_index, n, pk, sk, w, st, zero_err);
-        case 857: return enqueue_keygen<857>(ctx, cfg, seed, first_index, n, pk, sk, w, st, zero_err);
-        case 1277: return enqueue_keygen<1277>(ctx, cfg, seed, first_index, n, pk, sk, w, st, zero_err);
+        case 653: return enqueue_keygen<653>(ctx, cfg, seed, first_index, n, pk, sk, w, st, side_ok, zero_err);
+        case 761: return enqueue_keygen<761>(ctx, cfg, seed, first_index, n, pk, sk, w, st, side_ok, zero_err);
+        case 857: return enqueue_keygen<857>(ctx, cfg, seed, first_index, n, pk, sk, w, st, side_ok, zero_err);
+        case 1277: return enqueue_keygen<1277>(ctx, cfg, seed, first_index, n, pk, sk, w, st, side_ok, zero_err);
     }
     return NTRUP_EINVAL;
 }
@@ -339,6 +373,10 @@ int ntrup_ctx_create(ntrup_ctx** out, int device) {
     bool ok = set_device(ctx) == 0 && hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking) == hipSuccess;
     for (int i = 0; ok && i < kJobStreams; i++)
         ok = hipStreamCreateWithFlags(&ctx->job_streams[i], hipStreamNonBlocking) == hipSuccess;
+    ok = ok && hipStreamCreateWithFlags(&ctx->side_stream, hipStreamNonBlocking) == hipSuccess &&
+         hipEventCreateWithFlags(&ctx->side_fork, hipEventDisableTiming) == hipSuccess &&
+         hipEventCreateWithFlags(&ctx->side_join, hipEventDisableTiming) == hipSuccess &&
+         hipEventCreateWithFlags(&ctx->graph_done, hipEventDisableTiming) == hipSuccess;
     if (!ok) {
         ntrup_ctx_destroy(ctx);
         return NTRUP_EIO;
@@ -356,6 +394,10 @@ int ntrup_ctx_destroy(ntrup_ctx* ctx) {
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     for (hipStream_t js : ctx->job_streams)
         if (js) (void)hipStreamDestroy(js);
+    if (ctx->side_stream) (void)hipStreamDestroy(ctx->side_stream);
+    if (ctx->side_fork) (void)hipEventDestroy(ctx->side_fork);
+    if (ctx->side_join) (void)hipEventDestroy(ctx->side_join);
+    if (ctx->graph_done) (void)hipEventDestroy(ctx->graph_done);
     if (ctx->fork_event) (void)hipEventDestroy(ctx->fork_event);
     for (hipEvent_t e : ctx->join_events) (void)hipEventDestroy(e);
     if (ctx->ws) (void)hipFree(ctx->ws);
@@ -415,7 +457,7 @@ int ntrup_keygen_plain(ntrup_ctx* ctx, int p, const uint8_t* seed, uint64_t firs
     ntrup_params(p, nullptr, nullptr, &pkb, &skb);
     for (size_t i = 0; i < n; i++) {
         int r = enqueue_dispatch(ctx, p, cfg, sd, first_index + i, 1, pk + i * pkb, sk + i * skb, w,
-                                 (hipStream_t)stream, i == 0);
+                                 (hipStream_t)stream, false, i == 0);
         if (r) return r;
     }
     return 0;
@@ -426,11 +468,13 @@ namespace {
 // Enqueue every job on `st`: one job directly; several jobs on the context's
 // job streams between a fork and a join on `st`, so that they run
 // concurrently (and form parallel branches when captured).
-int enqueue_jobs(ntrup_ctx* ctx, const Seed& sd, const std::vector<JobDesc>& jobs, hipStream_t st) {
+// side_ok: a single job may fork its side stream (eager launches only: a
+// captured graph stays one linear stream per job).
+int enqueue_jobs(ntrup_ctx* ctx, const Seed& sd, const std::vector<JobDesc>& jobs, hipStream_t st, bool side_ok) {
     if (jobs.size() == 1) {
         const JobDesc& j = jobs[0];
         return enqueue_dispatch(ctx, j.p, j.cfg, sd, j.first_index, j.n, j.pk, j.sk,
-                                carve((char*)ctx->ws + j.ws_off, j.p, j.n), st, true);
+                                carve((char*)ctx->ws + j.ws_off, j.p, j.n), st, side_ok, true);
     }
     if (!ctx->fork_event) NTRUP_HIP(ctx, hipEventCreateWithFlags(&ctx->fork_event, hipEventDisableTiming));
     while (ctx->join_events.size() < jobs.size()) {
@@ -443,8 +487,10 @@ int enqueue_jobs(ntrup_ctx* ctx, const Seed& sd, const std::vector<JobDesc>& job
         const JobDesc& j = jobs[i];
         hipStream_t js = ctx->job_streams[i % kJobStreams];
         NTRUP_HIP(ctx, hipStreamWaitEvent(js, ctx->fork_event, 0));
+        // the jobs already run as concurrent branches: each stays on its own
+        // stream (no second-level fork inside a forked branch)
         int r = enqueue_dispatch(ctx, j.p, j.cfg, sd, j.first_index, j.n, j.pk, j.sk,
-                                 carve((char*)ctx->ws + j.ws_off, j.p, j.n), js, true);
+                                 carve((char*)ctx->ws + j.ws_off, j.p, j.n), js, false, true);
         if (r) return r;
         NTRUP_HIP(ctx, hipEventRecord(ctx->join_events[i], js));
     }
@@ -473,18 +519,20 @@ int ntrup_batch_keygen_mixed(ntrup_ctx* ctx, const uint8_t* seed, const ntrup_jo
     ctx->last_err.clear();
     for (const JobDesc& j : jd) ctx->last_err.push_back(carve((char*)ctx->ws + j.ws_off, j.p, j.n).counters + 32);
     hipStream_t st = (hipStream_t)stream;
-    if (!graph) return enqueue_jobs(ctx, sd, jd, st);
+    if (!graph) return enqueue_jobs(ctx, sd, jd, st, true);
 
     GraphKey key;
     memcpy(key.seed, sd.k, sizeof key.seed);
     key.ws = ctx->ws;
     key.jobs = jd;
     if (!ctx->have_graph || !(ctx->gkey == key)) {
+        // the previous graph may still run: wait for its last launch first
+        if (ctx->exec && ctx->graph_done) NTRUP_HIP(ctx, hipEventSynchronize(ctx->graph_done));
         if (ctx->exec) { (void)hipGraphExecDestroy(ctx->exec); ctx->exec = nullptr; }
         if (ctx->graph) { (void)hipGraphDestroy(ctx->graph); ctx->graph = nullptr; }
         ctx->have_graph = false;
         NTRUP_HIP(ctx, hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
-        int r = enqueue_jobs(ctx, sd, jd, ctx->cap_stream);
+        int r = enqueue_jobs(ctx, sd, jd, ctx->cap_stream, false);
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamEndCapture(ctx->cap_stream, &g);
         if (r) { if (g) (void)hipGraphDestroy(g); return r; }
@@ -495,6 +543,7 @@ int ntrup_batch_keygen_mixed(ntrup_ctx* ctx, const uint8_t* seed, const ntrup_jo
         ctx->have_graph = true;
     }
     NTRUP_HIP(ctx, hipGraphLaunch(ctx->exec, st));
+    NTRUP_HIP(ctx, hipEventRecord(ctx->graph_done, st));
     return 0;
 }
 
@@ -507,6 +556,7 @@ int ntrup_ctx_timing_begin(ntrup_ctx* ctx, int max_pipelines) {
         NTRUP_HIP(ctx, hipEventCreate(&e));
         ctx->tev.push_back(e);
     }
+    ctx->t_side.assign((size_t)max_pipelines, 0);
     ctx->t_max = max_pipelines;
     ctx->t_used = 0;
     return 0;
@@ -517,12 +567,22 @@ int ntrup_ctx_timing_end(ntrup_ctx* ctx, double* ms, int nstages, int* npipeline
     if (int r = set_device(ctx)) return r;
     for (int s = 0; s < nstages; s++) ms[s] = 0.0;
     for (int c = 0; c < ctx->t_used; c++) {
+        // events: 0 start, 1 sampled, 2 prefix kernel done, 3 R/3 main pass
+        // done, 4 R/3 retries done, 5 end (see enqueue_keygen)
         hipEvent_t* ev = &ctx->tev[(size_t)c * (kStages + 1)];
         NTRUP_HIP(ctx, hipEventSynchronize(ev[kStages]));
-        for (int s = 0; s < kStages; s++) {
-            float t = 0.f;
-            NTRUP_HIP(ctx, hipEventElapsedTime(&t, ev[s], ev[s + 1]));
-            ms[s] += t;
+        float t[kStages + 1][kStages + 1] = {};
+        for (int i = 0; i <= kStages; i++)
+            for (int j = i + 1; j <= kStages; j++) NTRUP_HIP(ctx, hipEventElapsedTime(&t[i][j], ev[i], ev[j]));
+        ms[0] += t[0][1];                                     // sample_short
+        ms[3] += t[1][2];                                     // group prefix + reciprocal
+        ms[2] += t[3][4];                                     // R/3 retries
+        if (ctx->t_side[c]) {
+            ms[1] += t[1][3];                                 // R/3 main pass, beside the prefix kernel
+            ms[4] += t[2][4] >= 0.f ? t[4][5] : t[2][5];      // back-substitution, from its later input
+        } else {
+            ms[1] += t[2][3];
+            ms[4] += t[4][5];
         }
     }
     if (npipelines) *npipelines = ctx->t_used;

@@ -1,26 +1,29 @@
 // Batched KeyGen group stage on the matrix cores (Section 3.1 KeyGen with the
 // batch inversion of Section 2.2): for each key h = g / (3f) in R/q, encoded
-// with f and 1/g into (pk, sk).
+// with f and 1/g into (pk, sk).  Two kernels:
 //
-// One workgroup = W waves; wave w owns a Montgomery group of G keys.
+// keygen_prefix_kernel<P, W>: one workgroup = W waves; wave w owns a
+//   Montgomery group of G keys.
 //   1. prefix (every wave): b_1 = 3f_1, b_i = 3f_i b_{i-1}; rows b_i kept in
 //      HBM, P_w = b_G stays in the wave's LDS;
-//   2. shared reciprocal (wave 0): Q_0 = P_0, Q_w = Q_{w-1} P_w, one
-//      constant-time divstep reciprocal T = 1/Q_{W-1}, then for w = W-1..1
-//      1/P_w = T Q_{w-1} and T <- T P_w; 1/P_0 = T.  W groups share one
-//      reciprocal (the same trick as inside a group, one level up);
-//   3. back-substitution (every wave), from t = 1/P_w: c_i = t b_{i-1}
-//      (= 1/(3f_i)), t <- t 3f_i, h_i = g_i c_i, then encoding.
+//   2. shared reciprocal (wave 0 alone; the others have ended): Q_0 = P_0,
+//      Q_w = Q_{w-1} P_w, one constant-time divstep reciprocal
+//      T = 1/Q_{W-1}, then for w = W-1..1: 1/P_w = T Q_{w-1} and T <- T P_w;
+//      1/P_0 = T -- the same trick one level up; each 1/P_w goes to HBM.
+//   This kernel needs only f, so it runs beside the R/3 stage.
+// keygen_back_kernel<P>: one wave per group:
+//   3. back-substitution from t = 1/P: c_i = t b_{i-1} (= 1/(3f_i)),
+//      t <- t 3f_i, h_i = g_i c_i, then encoding.
 // Every product is mfma_mul with the running value as Toeplitz operand.
 //
 // Latency: the next key's operands (the f row, the stored prefix row, the
 // bitsliced g and 1/g words) are loaded into registers one step ahead and
-// written to LDS at the start of the step; waves synchronise their own LDS
-// traffic with wave_sync and meet at workgroup barriers only around step 2.
+// written to LDS at the start of the step; waves order their own LDS traffic
+// with wave_sync.
 //
 // Register layout of the per-key operands: lane l holds coefficients
 // m = 4l + 256u + t (t = 0..3, u < NU), four per 32-bit word, which is also the
-// layout of sk (byte 4l+... covers coefficients 4b..4b+3 with b = l + 64u).
+// layout of sk (byte b = l + 64u covers coefficients 4b..4b+3).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -279,34 +282,45 @@ __device__ __forceinline__ void kg_back_step(const GroupArgs& args, KgWave<P>& L
     kg_encode<P>(key, L.Cb, cur, args.pk, args.sk);
 }
 
-// At least two waves per SIMD (at most 256 registers per lane) where that
-// fits without spills (p < 800).
-template <int P, int W>
-__global__ __launch_bounds__(64 * W, (P < 800 ? 2 : 1)) void keygen_group_kernel(GroupArgs args) {
+// Per-wave LDS of the prefix kernel (no c_i or g operands).
+template <int P>
+struct KgPrefixWave {
     using S = MfShape<P>;
-    __shared__ KgWave<P> LW[W];
+    static constexpr int STG = KgWave<P>::STG;
+    __attribute__((aligned(16))) uint8_t TL[S::TLEN];
+    __attribute__((aligned(16))) uint8_t TH[S::TLEN];
+    __attribute__((aligned(16))) uint8_t HL[S::HLEN];
+    __attribute__((aligned(16))) uint8_t HH[S::HLEN];
+    __attribute__((aligned(16))) uint8_t HS[S::HLEN];
+    __attribute__((aligned(16))) int32_t ST[STG];
+    __attribute__((aligned(16))) int16_t Bb[RqShape<P>::JP];
+    __attribute__((aligned(16))) int16_t Cb[RqShape<P>::JP];
+};
+
+// Steps 1 and 2: prefix products of each wave's group (rows b_i to HBM), then
+// wave 0 alone inverts the W group products with one reciprocal and writes
+// t = 1/P_w of every group to tinv (int16 [groups][p]).  The other waves end
+// after the prefix barrier, so their registers serve other work (the R/3
+// stage runs beside this kernel) while wave 0 runs the reciprocal.
+template <int P, int W>
+__global__ __launch_bounds__(64 * W, (P < 800 ? 2 : 1)) void keygen_prefix_kernel(GroupArgs args, int16_t* tinv) {
+    using S = MfShape<P>;
+    __shared__ KgPrefixWave<P> LW[W];
     const int wave = (int)(threadIdx.x >> 6);
-    KgWave<P>& L = LW[wave];
+    KgPrefixWave<P>& L = LW[wave];
     const int n = args.n;
     const int G = args.G;
-    const int kw0 = (blockIdx.x * W + wave) * G;
+    const int group = blockIdx.x * W + wave;
+    const int kw0 = group * G;
     const int gsz = max(0, min(G, n - kw0));
     int16_t* CS = (int16_t*)L.ST;
     int16_t* bscr = args.bscr;
 
-    // zero padding of every limb array (only [.., p) positions are rewritten)
     kg_zero<P>(L.TL, S::TLEN);
     kg_zero<P>(L.TH, S::TLEN);
-    kg_zero<P>(L.UL, S::TLEN);
-    kg_zero<P>(L.UH, S::TLEN);
-    kg_zero<P>(L.HL, S::HLEN);
-    kg_zero<P>(L.HH, S::HLEN);
     kg_zero<P>(L.HS, S::HLEN);
-    kg_zero<P>(L.HG, S::HLEN);
     wave_sync();
-
-    // 1. prefix products; TL/TH carry the limbs of b_{i-1}
-    KgRegs<P> ra, rb;
+    KgRegs<P> ra;
     if (gsz >= 1) {
         kg_load_f<P>(args.f_rows, kw0, ra);
         kg_put_3f16<P>(ra, L.Bb, L.TL, bscr + (size_t)kw0 * P);
@@ -323,64 +337,78 @@ __global__ __launch_bounds__(64 * W, (P < 800 ? 2 : 1)) void keygen_group_kernel
         kg_set_one<P>(L.Bb);
     }
     __syncthreads();
-    // operands of the first back-substitution step (prefix rows now visible)
-    if (gsz >= 1) {
-        kg_load_f<P>(args.f_rows, kw0 + gsz - 1, ra);
-        if (gsz >= 2) kg_load_b<P>(bscr, kw0 + gsz - 2, ra);
-        kg_load_bits<P>(args.gbits, args.ibits, n, kw0 + gsz - 1, ra);
-    }
+    if (wave != 0) return;   // no barrier follows: wave 0 finishes alone
 
-    // 2. one reciprocal for the W group products (Toeplitz limbs in wave 0's
-    // TL/TH; the Hankel arrays keep zero padding since build_hankel writes
-    // them whole)
-    if (wave == 0) {
-        if (W == 1) {
-            const int ok = recip_wave<P>(L.Bb, L.Bb, L.ST);
-            if (!ok && lane_id() == 0) atomicOr(args.err, 2);
-        } else {
-            // Q_{w-1} -> LW[w].Cb, Q_{W-1} -> LW[0].Cb
-            kg_copy<P>(LW[0].Bb, LW[1].Cb);
-            for (int w = 1; w < W; w++) {
-                wave_sync();
-                build_toeplitz<P>(LW[w].Cb, L.TL, L.TH);
-                build_hankel<P>(LW[w].Bb, L.HL, L.HH);
-                wave_sync();
-                mfma_mul<P, true>(L.TL, L.TH, L.HL, L.HH, CS, w + 1 < W ? LW[w + 1].Cb : LW[0].Cb, nullptr,
-                                  nullptr, nullptr);
-            }
+    if (W == 1) {
+        const int ok = recip_wave<P>(L.Bb, L.Bb, L.ST);
+        if (!ok && lane_id() == 0) atomicOr(args.err, 2);
+    } else {
+        // Q_{w-1} -> LW[w].Cb, Q_{W-1} -> LW[0].Cb; the Hankel arrays are
+        // written whole by build_hankel (zero padding included)
+        kg_copy<P>(LW[0].Bb, LW[1].Cb);
+        for (int w = 1; w < W; w++) {
             wave_sync();
-            const int ok = recip_wave<P>(LW[0].Cb, LW[0].Cb, L.ST);
-            if (!ok && lane_id() == 0) atomicOr(args.err, 2);
-            for (int w = W - 1; w >= 1; w--) {
-                wave_sync();
-                build_toeplitz<P>(LW[0].Cb, L.TL, L.TH);   // T = 1/Q_w
-                build_hankel<P>(LW[w].Bb, L.HL, L.HH);      // P_w
-                wave_sync();
-                mfma_mul<P, true>(L.TL, L.TH, L.HL, L.HH, CS, LW[0].Cb, nullptr, nullptr, nullptr);  // T <- T P_w
-                wave_sync();
-                build_hankel<P>(LW[w].Cb, L.HL, L.HH);      // Q_{w-1}
-                wave_sync();
-                mfma_mul<P, true>(L.TL, L.TH, L.HL, L.HH, CS, LW[w].Bb, nullptr, nullptr, nullptr);  // 1/P_w
-            }
+            build_toeplitz<P>(LW[w].Cb, L.TL, L.TH);
+            build_hankel<P>(LW[w].Bb, L.HL, L.HH);
             wave_sync();
-            kg_copy<P>(LW[0].Cb, LW[0].Bb);
+            mfma_mul<P, true>(L.TL, L.TH, L.HL, L.HH, CS, w + 1 < W ? LW[w + 1].Cb : LW[0].Cb, nullptr, nullptr,
+                              nullptr);
         }
+        wave_sync();
+        const int ok = recip_wave<P>(LW[0].Cb, LW[0].Cb, L.ST);
+        if (!ok && lane_id() == 0) atomicOr(args.err, 2);
+        for (int w = W - 1; w >= 1; w--) {
+            wave_sync();
+            build_toeplitz<P>(LW[0].Cb, L.TL, L.TH);   // T = 1/Q_w
+            build_hankel<P>(LW[w].Bb, L.HL, L.HH);      // P_w
+            wave_sync();
+            mfma_mul<P, true>(L.TL, L.TH, L.HL, L.HH, CS, LW[0].Cb, nullptr, nullptr, nullptr);  // T <- T P_w
+            wave_sync();
+            build_hankel<P>(LW[w].Cb, L.HL, L.HH);      // Q_{w-1}
+            wave_sync();
+            mfma_mul<P, true>(L.TL, L.TH, L.HL, L.HH, CS, LW[w].Bb, nullptr, nullptr, nullptr);  // 1/P_w
+        }
+        wave_sync();
+        kg_copy<P>(LW[0].Cb, LW[0].Bb);
     }
-    __syncthreads();
+    wave_sync();
+    for (int w = 0; w < W; w++) {
+        const int grp = blockIdx.x * W + w;
+        if ((size_t)grp * G >= (size_t)n) break;
+        for (int j = lane_id(); j < P; j += 64) tinv[(size_t)grp * P + j] = LW[w].Bb[j];
+    }
+}
 
-    // 3. back-substitution, h = g c and encoding (two steps per trip so that
-    // the operand register sets alternate at compile time)
-    if (gsz >= 1) build_toeplitz<P>(L.Bb, L.TL, L.TH);
+// Step 3: back-substitution from t = 1/P (tinv row of the group), h = g c and
+// encoding.  One wave per group.
+template <int P>
+__global__ __launch_bounds__(64, (P < 800 ? 2 : 1)) void keygen_back_kernel(GroupArgs args, const int16_t* tinv) {
+    using S = MfShape<P>;
+    __shared__ KgWave<P> L;
+    const int n = args.n;
+    const int G = args.G;
+    const int kw0 = blockIdx.x * G;
+    const int gsz = max(0, min(G, n - kw0));
+    if (gsz <= 0) return;
+    kg_zero<P>(L.UL, S::TLEN);
+    kg_zero<P>(L.UH, S::TLEN);
+    kg_zero<P>(L.HL, S::HLEN);
+    kg_zero<P>(L.HH, S::HLEN);
+    kg_zero<P>(L.HS, S::HLEN);
+    kg_zero<P>(L.HG, S::HLEN);
+    KgRegs<P> ra, rb;
+    kg_load_f<P>(args.f_rows, kw0 + gsz - 1, ra);
+    if (gsz >= 2) kg_load_b<P>(args.bscr, kw0 + gsz - 2, ra);
+    kg_load_bits<P>(args.gbits, args.ibits, n, kw0 + gsz - 1, ra);
+    for (int j = lane_id(); j < P; j += 64) L.Bb[j] = tinv[(size_t)blockIdx.x * P + j];
+    wave_sync();
+    build_toeplitz<P>(L.Bb, L.TL, L.TH);
+    // two steps per trip so that the operand register sets alternate at
+    // compile time
     for (int i = gsz; i >= 1; i -= 2) {
         kg_back_step<P>(args, L, kw0, i, ra, rb);
         if (i >= 2) kg_back_step<P>(args, L, kw0, i - 1, rb, ra);
     }
-}
-
-// Workgroup LDS of the kernel above.
-template <int P, int W>
-constexpr size_t keygen_group_lds() {
-    return sizeof(KgWave<P>) * W;
 }
 
 }  // namespace ntrup

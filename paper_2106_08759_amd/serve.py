@@ -74,7 +74,7 @@ class GpuBackend:
         Refills never repeat their arguments (each starts at a new key index),
         so they launch eagerly rather than through a captured graph."""
         from . import autotune
-        autotune.tune(ctx, p, n, reps=2, use_graph=0)
+        autotune.tune(ctx, p, n, reps=2, mode="eager")
 
     def keygen(self, ctx, p, seed, first_index, n, pk, sk, stream):
         ctx.batch_keygen(p, seed, first_index, n, pk, sk, stream=stream, check=False)

@@ -7,18 +7,19 @@ from paper_2106_08759_amd import autotune
 def test_candidates_cover_the_knobs():
     c761 = autotune.candidates(761, 65536)
     assert {c["group_size"] for c in c761} == set(autotune.GROUP_SIZES)
-    assert {c["lanes_per_key"] for c in c761} == {1, 2, 4}
+    assert {c["lanes_per_key"] for c in c761} == {1, 2, 4, 8}
     assert {c["retry_passes"] for c in c761} == {1}
     c1277 = autotune.candidates(1277, 65536)
-    assert {c["lanes_per_key"] for c in c1277} == {2, 4}
+    assert {c["lanes_per_key"] for c in c1277} == {2, 4, 8}
     assert {c["retry_passes"] for c in c1277} == {0, 1}
     assert {c["retry_lanes_per_key"] for c in c1277} == {4, 8}
     assert {c["retry_parallel_attempts"] for c in c1277} == {2, 4, 8}
     assert all(c["retry_lanes_per_key"] * c["retry_parallel_attempts"] <= 64 for c in c1277)
     assert all(c["group_size"] <= 16 for c in autotune.candidates(761, 10))
+    assert {c["group_size"] for c in autotune.candidates(761, 10)} == {8, 16}
     assert {c["inverse_share"] for c in c761} == {1, 2, 4, 8}
     assert {c["inverse_share"] for c in c1277} == {1, 2, 4}          # LDS bound for p = 1277
-    assert {(c["group_size"], c["inverse_share"]) for c in autotune.candidates(761, 10)} == {(16, 1)}
+    assert {(c["group_size"], c["inverse_share"]) for c in autotune.candidates(761, 10)} == {(8, 1), (8, 2), (16, 1)}
 
 
 def test_bucket():
@@ -35,3 +36,4 @@ def test_cache_roundtrip(tmp_path):
     assert autotune.lookup("dev", 761, 65536, path) == entry      # same bucket
     assert autotune.lookup("dev", 761, 70000, path) is None       # next bucket
     assert autotune.lookup("other", 761, 65536, path) is None
+    assert autotune.lookup("dev", 761, 65536, path, mode="graph") is None   # per launch form
