@@ -315,6 +315,10 @@ __global__ __launch_bounds__(64 * W, (P < 800 ? 2 : 1)) void keygen_prefix_kerne
     const int gsz = max(0, min(G, n - kw0));
     int16_t* CS = (int16_t*)L.ST;
     int16_t* bscr = args.bscr;
+    // this kernel's latency (a chain of products, then one long divstep
+    // reciprocal on one wave) bounds the pipeline while the R/3 stage runs
+    // beside it: its waves take issue priority over the R/3 waves
+    __builtin_amdgcn_s_setprio(3);
 
     kg_zero<P>(L.TL, S::TLEN);
     kg_zero<P>(L.TH, S::TLEN);
