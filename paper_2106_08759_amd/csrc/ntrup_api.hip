@@ -681,7 +681,7 @@ int ntrup_op_batch_inv_rq(ntrup_ctx* ctx, int p, const int16_t* a, int16_t* out,
     const bool mfma = ctx->cfg[param_slot(p)].product_engine == 1;
 #define NTRUP_INV(PP)                                                                      \
     case PP:                                                                               \
-        if (mfma) hipLaunchKernelGGL((group_mfma_kernel<PP, false>), grid, blk, 0, st, g); \
+        if (mfma) hipLaunchKernelGGL((group_mfma_kernel<PP>), grid, blk, 0, st, g); \
         else hipLaunchKernelGGL((group_kernel<PP, false>), grid, blk, 0, st, g);           \
         break;
     switch (p) { NTRUP_INV(653) NTRUP_INV(761) NTRUP_INV(857) NTRUP_INV(1277) }

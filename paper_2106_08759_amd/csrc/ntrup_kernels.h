@@ -452,71 +452,27 @@ __global__ __launch_bounds__(64) void group_kernel(GroupArgs args) {
 }
 
 // ----------------------------------------------------------------------------
-// The same Montgomery group on the int8 matrix cores: every product is
-// mfma_mul, with the big running value (b_i, t_i, c_i) as the Toeplitz operand.
+// Batch inversion (Section 2.2) on the int8 matrix cores: the Montgomery group
+// of group_kernel with every product done by mfma_mul, the big running value
+// (b_i, t_i) as the Toeplitz operand and the input rows as folded Hankel
+// operands.
 // ----------------------------------------------------------------------------
 template <int P>
 struct GroupMfLds {
     using S = MfShape<P>;
-    static constexpr int STG = (64 * RqShape<P>::RI > S::CLEN / 2) ? 64 * RqShape<P>::RI : S::CLEN / 2;
     __attribute__((aligned(16))) uint8_t TL[S::TLEN];     // Toeplitz limbs of the running value
     __attribute__((aligned(16))) uint8_t TH[S::TLEN];
-    __attribute__((aligned(16))) uint8_t HL[S::HLEN];     // Hankel limbs: big operand ...
+    __attribute__((aligned(16))) uint8_t HL[S::HLEN];     // Hankel limbs of an input or prefix row
     __attribute__((aligned(16))) uint8_t HH[S::HLEN];
-    __attribute__((aligned(16))) uint8_t HS[S::HLEN];     // ... and the small one
-    __attribute__((aligned(16))) int32_t ST[STG];         // conv staging / divstep staging
+    __attribute__((aligned(16))) int32_t ST[64 * RqShape<P>::RI];   // divstep staging
     __attribute__((aligned(16))) int16_t Bb[RqShape<P>::JP];  // running value (natural order)
-    __attribute__((aligned(16))) int16_t Cb[RqShape<P>::JP];  // c_i, then h_i
+    __attribute__((aligned(16))) int16_t Cb[RqShape<P>::JP];  // c_i
 };
-
-// HS[HOFF + m] = 3 f_m (int8), zero padding elsewhere.
-template <int P>
-__device__ __forceinline__ void hankel_3f(const int8_t* row, uint8_t* HS) {
-    using S = MfShape<P>;
-    for (int i = lane_id(); i < S::HLEN / 4; i += 64) {
-        uint32_t w = 0;
-#pragma unroll
-        for (int t = 0; t < 4; t++) {
-            const int m = 4 * i + t - S::HOFF;
-            const int32_t v = (m >= 0 && m < P) ? 3 * (int32_t)row[m] : 0;
-            w |= (uint32_t)(uint8_t)(int8_t)v << (8 * t);
-        }
-        ((uint32_t*)HS)[i] = w;
-    }
-}
-
-// HS[HOFF + m] = g_m (int8) of key `key` from the bitsliced words.
-template <int P>
-__device__ __forceinline__ void hankel_g(const uint32_t* gbits, int n, int key, uint8_t* HS) {
-    using S = MfShape<P>;
-    static_assert(S::HOFF % 4 == 0, "dwords of HS start at multiples of 4 coefficients");
-    for (int i = lane_id(); i < S::HLEN / 4; i += 64) {
-        const int m0 = 4 * i - S::HOFF;
-        uint32_t w = 0;
-        if (m0 >= 0 && m0 < P) {
-            const int wd = m0 >> 5, sh = m0 & 31;
-            const uint32_t mb = gbits[(size_t)(2 * wd) * n + key] >> sh;
-            const uint32_t sb = gbits[(size_t)(2 * wd + 1) * n + key] >> sh;
-#pragma unroll
-            for (int t = 0; t < 4; t++) {
-                const uint32_t byte = ((mb >> t) & 1u) ? (((sb >> t) & 1u) ? 0xFFu : 0x01u) : 0u;
-                if (m0 + t < P) w |= byte << (8 * t);
-            }
-        }
-        ((uint32_t*)HS)[i] = w;
-    }
-}
-
-// Hankel limbs of a global int16 row (big operand).
-template <int P>
-__device__ __forceinline__ void hankel_row(const int16_t* row, uint8_t* HL, uint8_t* HH) {
-    build_hankel<P>(row, HL, HH);
-}
 
 #ifndef NTRUP_GM_WAVES
 #define NTRUP_GM_WAVES 1
 #endif
-template <int P, bool KEYGEN>
+template <int P>
 __global__ __launch_bounds__(64, NTRUP_GM_WAVES) void group_mfma_kernel(GroupArgs args) {
     __shared__ GroupMfLds<P> L;
     const int lane = lane_id();
@@ -524,23 +480,18 @@ __global__ __launch_bounds__(64, NTRUP_GM_WAVES) void group_mfma_kernel(GroupArg
     const int k0 = blockIdx.x * args.G;
     const int gsz = min(args.G, n - k0);
     if (gsz <= 0) return;
-    const int8_t* f_rows = args.f_rows;
     const int16_t* a_in = args.a_in;
     int16_t* bscr = args.bscr;
-    int16_t* CS = (int16_t*)L.ST;
 
     // prefix products: b_1 = a_1, b_i = a_i b_{i-1} (Toeplitz operand b_{i-1})
-    if (KEYGEN) load_3f<P>(f_rows + (size_t)k0 * P, L.Bb);
-    else load_row16<P>(a_in + (size_t)k0 * P, L.Bb);
+    load_row16<P>(a_in + (size_t)k0 * P, L.Bb);
     __syncthreads();
     for (int j = lane; j < P; j += 64) bscr[(size_t)k0 * P + j] = L.Bb[j];
     for (int i = 1; i < gsz; i++) {
         build_toeplitz<P>(L.Bb, L.TL, L.TH);
-        if (KEYGEN) hankel_3f<P>(f_rows + (size_t)(k0 + i) * P, L.HS);
-        else hankel_row<P>(a_in + (size_t)(k0 + i) * P, L.HL, L.HH);
+        build_hankel<P>(a_in + (size_t)(k0 + i) * P, L.HL, L.HH);
         __syncthreads();
-        if (KEYGEN) mfma_mul<P, false>(L.TL, L.TH, L.HS, nullptr, CS, L.Bb, nullptr, nullptr, bscr + (size_t)(k0 + i) * P);
-        else mfma_mul<P, true>(L.TL, L.TH, L.HL, L.HH, CS, L.Bb, nullptr, nullptr, bscr + (size_t)(k0 + i) * P);
+        mfma_mul<P, true>(L.TL, L.TH, L.HL, L.HH, L.Bb, nullptr, nullptr, bscr + (size_t)(k0 + i) * P);
         __syncthreads();
     }
     // one reciprocal per group: t = 1/b_gsz
@@ -553,29 +504,18 @@ __global__ __launch_bounds__(64, NTRUP_GM_WAVES) void group_mfma_kernel(GroupArg
         const int16_t* C = L.Bb;  // i == 1: c_1 = t_1
         if (i > 1) {
             build_toeplitz<P>(L.Bb, L.TL, L.TH);
-            hankel_row<P>(bscr + (size_t)(k0 + i - 2) * P, L.HL, L.HH);
-            if (KEYGEN) hankel_3f<P>(f_rows + (size_t)(k0 + i - 1) * P, L.HS);
+            build_hankel<P>(bscr + (size_t)(k0 + i - 2) * P, L.HL, L.HH);
             __syncthreads();
-            mfma_mul<P, true>(L.TL, L.TH, L.HL, L.HH, CS, L.Cb, nullptr, nullptr, nullptr);
-            if (!KEYGEN) hankel_row<P>(a_in + (size_t)(k0 + i - 1) * P, L.HL, L.HH);
+            mfma_mul<P, true>(L.TL, L.TH, L.HL, L.HH, L.Cb, nullptr, nullptr, nullptr);
             __syncthreads();
-            if (KEYGEN) mfma_mul<P, false>(L.TL, L.TH, L.HS, nullptr, CS, L.Bb, nullptr, nullptr, nullptr);
-            else mfma_mul<P, true>(L.TL, L.TH, L.HL, L.HH, CS, L.Bb, nullptr, nullptr, nullptr);
+            build_hankel<P>(a_in + (size_t)(k0 + i - 1) * P, L.HL, L.HH);
+            __syncthreads();
+            mfma_mul<P, true>(L.TL, L.TH, L.HL, L.HH, L.Bb, nullptr, nullptr, nullptr);
             __syncthreads();
             C = L.Cb;
         }
         const int key = k0 + i - 1;
-        if (KEYGEN) {
-            // h = g c (Toeplitz operand c)
-            build_toeplitz<P>(C, L.TL, L.TH);
-            hankel_g<P>(args.gbits, n, key, L.HS);
-            __syncthreads();
-            mfma_mul<P, false>(L.TL, L.TH, L.HS, nullptr, CS, L.Cb, nullptr, nullptr, nullptr);
-            __syncthreads();
-            encode_key<P>(key, L.Cb, args.pk, args.sk, f_rows, args.ibits, n);
-        } else {
-            for (int j = lane; j < P; j += 64) args.c_out[(size_t)key * P + j] = C[j];
-        }
+        for (int j = lane; j < P; j += 64) args.c_out[(size_t)key * P + j] = C[j];
         __syncthreads();
     }
 }
@@ -598,7 +538,7 @@ __global__ __launch_bounds__(64) void mul_kernel(int n, const int16_t* a, const 
     store_row<P>(acc[0], c + (size_t)e * P);
 }
 
-// LDS of one product on the matrix cores: operand rows, limb arrays, staging.
+// LDS of one product on the matrix cores: operand rows and limb arrays.
 template <int P>
 struct MfLds {
     using S = MfShape<P>;
@@ -606,7 +546,6 @@ struct MfLds {
     __attribute__((aligned(16))) uint8_t TH[S::TLEN];
     __attribute__((aligned(16))) uint8_t HL[S::HLEN];
     __attribute__((aligned(16))) uint8_t HH[S::HLEN];
-    __attribute__((aligned(16))) int16_t CS[S::CLEN];
     __attribute__((aligned(16))) int16_t X[RqShape<P>::JP];
     __attribute__((aligned(16))) int16_t Y[RqShape<P>::JP];
 };
@@ -624,7 +563,7 @@ __global__ __launch_bounds__(64) void mulm_kernel(int n, const int16_t* a, const
     build_toeplitz<P>(L.Y, L.TL, L.TH);
     build_hankel<P>(L.X, L.HL, BIG ? L.HH : nullptr);
     __syncthreads();
-    mfma_mul<P, BIG>(L.TL, L.TH, L.HL, L.HH, L.CS, nullptr, nullptr, nullptr, c + (size_t)e * P);
+    mfma_mul<P, BIG>(L.TL, L.TH, L.HL, L.HH, nullptr, nullptr, nullptr, c + (size_t)e * P);
 }
 
 template <int P>

@@ -45,7 +45,7 @@ struct KgShape {
 template <int P>
 struct KgWave {
     using S = MfShape<P>;
-    static constexpr int STG = (64 * RqShape<P>::RI > S::CLEN / 2) ? 64 * RqShape<P>::RI : S::CLEN / 2;
+    static constexpr int STG = 64 * RqShape<P>::RI;
     __attribute__((aligned(16))) uint8_t TL[S::TLEN];   // Toeplitz limbs of the running value
     __attribute__((aligned(16))) uint8_t TH[S::TLEN];
     __attribute__((aligned(16))) uint8_t UL[S::TLEN];   // Toeplitz limbs of c_i
@@ -54,7 +54,7 @@ struct KgWave {
     __attribute__((aligned(16))) uint8_t HH[S::HLEN];
     __attribute__((aligned(16))) uint8_t HS[S::HLEN];   // 3 f of the current key
     __attribute__((aligned(16))) uint8_t HG[S::HLEN];   // g of the current key
-    __attribute__((aligned(16))) int32_t ST[STG];       // conv / divstep staging
+    __attribute__((aligned(16))) int32_t ST[STG];       // divstep staging
     __attribute__((aligned(16))) int16_t Bb[RqShape<P>::JP];  // running value
     __attribute__((aligned(16))) int16_t Cb[RqShape<P>::JP];  // c_i, h_i, chain values
 };
@@ -135,49 +135,28 @@ __device__ __forceinline__ uint32_t spread2(uint32_t x) {
     return (x & 1u) | ((x & 2u) << 1) | ((x & 4u) << 2) | ((x & 8u) << 3);
 }
 
-// HS[HOFF + m] = 3 f_m: bytes 0x00, 0x01, 0xFF -> 0x00, 0x03, 0xFD.
+// Folded Hankel bytes of 3 f (bytes 0x00, 0x01, 0xFF -> 0x00, 0x03, 0xFD).
 template <int P>
 __device__ __forceinline__ void kg_put_3f(const KgRegs<P>& r, uint8_t* HS) {
-    const int lane = lane_id();
+    uint32_t w[KgShape<P>::NU];
 #pragma unroll
-    for (int u = 0; u < KgShape<P>::NU; u++) {
-        const int m0 = 4 * lane + 256 * u;
-        if (m0 < P) *(uint32_t*)(HS + MfShape<P>::HOFF + m0) = r.f[u] ^ ((r.f[u] & 0x01010101u) << 1);
-    }
+    for (int u = 0; u < KgShape<P>::NU; u++) w[u] = r.f[u] ^ ((r.f[u] & 0x01010101u) << 1);
+    put_folded8<P>(w, HS);
 }
 
-// HG[HOFF + m] = g_m: byte 0x01 (g = 1) or 0xFF (g = -1).
+// Folded Hankel bytes of g (byte 0x01 for g = 1, 0xFF for g = -1).
 template <int P>
 __device__ __forceinline__ void kg_put_g(const KgRegs<P>& r, uint8_t* HG) {
-    const int lane = lane_id();
+    uint32_t w[KgShape<P>::NU];
 #pragma unroll
-    for (int u = 0; u < KgShape<P>::NU; u++) {
-        const int m0 = 4 * lane + 256 * u;
-        if (m0 < P) *(uint32_t*)(HG + MfShape<P>::HOFF + m0) = spread4(r.gm[u]) | (spread4(r.gs[u]) * 0xFEu);
-    }
+    for (int u = 0; u < KgShape<P>::NU; u++) w[u] = spread4(r.gm[u]) | (spread4(r.gs[u]) * 0xFEu);
+    put_folded8<P>(w, HG);
 }
 
-// HL/HH[HOFF + m] = limbs of the stored row b_m.
+// Folded Hankel limbs of the stored row b.
 template <int P>
 __device__ __forceinline__ void kg_put_b(const KgRegs<P>& r, uint8_t* HL, uint8_t* HH) {
-    const int lane = lane_id();
-#pragma unroll
-    for (int u = 0; u < KgShape<P>::NU; u++) {
-        const int m0 = 4 * lane + 256 * u;
-        if (m0 < P) {
-            uint32_t lo = 0, hi = 0;
-#pragma unroll
-            for (int t = 0; t < 4; t++) {
-                const int32_t v = (int32_t)(int16_t)(r.b[u][t >> 1] >> (16 * (t & 1)));
-                uint32_t l, h;
-                split_limb(v, l, h);
-                lo |= l << (8 * t);
-                hi |= h << (8 * t);
-            }
-            *(uint32_t*)(HL + MfShape<P>::HOFF + m0) = lo;
-            *(uint32_t*)(HH + MfShape<P>::HOFF + m0) = hi;
-        }
-    }
+    put_folded16<P>(r.b, HL, HH);
 }
 
 // The first prefix value b_1 = 3 f: X[m] = 3 f_m (int16), the same row to
@@ -256,7 +235,6 @@ __device__ __forceinline__ void kg_copy(const int16_t* src, int16_t* dst) {
 template <int P>
 __device__ __forceinline__ void kg_back_step(const GroupArgs& args, KgWave<P>& L, int kw0, int i, KgRegs<P>& cur,
                                              KgRegs<P>& nxt) {
-    int16_t* CS = (int16_t*)L.ST;
     const int key = kw0 + i - 1;
     kg_put_3f<P>(cur, L.HS);
     kg_put_g<P>(cur, L.HG);
@@ -270,14 +248,14 @@ __device__ __forceinline__ void kg_back_step(const GroupArgs& args, KgWave<P>& L
     const uint8_t* CL = L.TL;   // i == 1: c_1 = t_1
     const uint8_t* CH = L.TH;
     if (i > 1) {
-        mfma_mul<P, true>(L.TL, L.TH, L.HL, L.HH, CS, nullptr, L.UL, L.UH, nullptr);   // c_i = t b_{i-1}
+        mfma_mul<P, true>(L.TL, L.TH, L.HL, L.HH, nullptr, L.UL, L.UH, nullptr);   // c_i = t b_{i-1}
         wave_sync();
-        mfma_mul<P, false>(L.TL, L.TH, L.HS, nullptr, CS, nullptr, L.TL, L.TH, nullptr); // t <- t 3f_i
+        mfma_mul<P, false>(L.TL, L.TH, L.HS, nullptr, nullptr, L.TL, L.TH, nullptr); // t <- t 3f_i
         wave_sync();
         CL = L.UL;
         CH = L.UH;
     }
-    mfma_mul<P, false>(CL, CH, L.HG, nullptr, CS, L.Cb, nullptr, nullptr, nullptr);     // h = g c_i
+    mfma_mul<P, false>(CL, CH, L.HG, nullptr, L.Cb, nullptr, nullptr, nullptr);     // h = g c_i
     wave_sync();
     kg_encode<P>(key, L.Cb, cur, args.pk, args.sk);
 }
@@ -313,7 +291,6 @@ __global__ __launch_bounds__(64 * W, (P < 800 ? 2 : 1)) void keygen_prefix_kerne
     const int group = blockIdx.x * W + wave;
     const int kw0 = group * G;
     const int gsz = max(0, min(G, n - kw0));
-    int16_t* CS = (int16_t*)L.ST;
     int16_t* bscr = args.bscr;
     // this kernel's latency (a chain of products, then one long divstep
     // reciprocal on one wave) bounds the pipeline while the R/3 stage runs
@@ -333,7 +310,7 @@ __global__ __launch_bounds__(64 * W, (P < 800 ? 2 : 1)) void keygen_prefix_kerne
             kg_put_3f<P>(ra, L.HS);
             if (i + 1 < gsz) kg_load_f<P>(args.f_rows, kw0 + i + 1, ra);
             wave_sync();
-            mfma_mul<P, false>(L.TL, L.TH, L.HS, nullptr, CS, i + 1 == gsz ? L.Bb : nullptr, L.TL, L.TH,
+            mfma_mul<P, false>(L.TL, L.TH, L.HS, nullptr, i + 1 == gsz ? L.Bb : nullptr, L.TL, L.TH,
                                bscr + (size_t)(kw0 + i) * P);
             wave_sync();
         }
@@ -355,7 +332,7 @@ __global__ __launch_bounds__(64 * W, (P < 800 ? 2 : 1)) void keygen_prefix_kerne
             build_toeplitz<P>(LW[w].Cb, L.TL, L.TH);
             build_hankel<P>(LW[w].Bb, L.HL, L.HH);
             wave_sync();
-            mfma_mul<P, true>(L.TL, L.TH, L.HL, L.HH, CS, w + 1 < W ? LW[w + 1].Cb : LW[0].Cb, nullptr, nullptr,
+            mfma_mul<P, true>(L.TL, L.TH, L.HL, L.HH, w + 1 < W ? LW[w + 1].Cb : LW[0].Cb, nullptr, nullptr,
                               nullptr);
         }
         wave_sync();
@@ -366,11 +343,11 @@ __global__ __launch_bounds__(64 * W, (P < 800 ? 2 : 1)) void keygen_prefix_kerne
             build_toeplitz<P>(LW[0].Cb, L.TL, L.TH);   // T = 1/Q_w
             build_hankel<P>(LW[w].Bb, L.HL, L.HH);      // P_w
             wave_sync();
-            mfma_mul<P, true>(L.TL, L.TH, L.HL, L.HH, CS, LW[0].Cb, nullptr, nullptr, nullptr);  // T <- T P_w
+            mfma_mul<P, true>(L.TL, L.TH, L.HL, L.HH, LW[0].Cb, nullptr, nullptr, nullptr);  // T <- T P_w
             wave_sync();
             build_hankel<P>(LW[w].Cb, L.HL, L.HH);      // Q_{w-1}
             wave_sync();
-            mfma_mul<P, true>(L.TL, L.TH, L.HL, L.HH, CS, LW[w].Bb, nullptr, nullptr, nullptr);  // 1/P_w
+            mfma_mul<P, true>(L.TL, L.TH, L.HL, L.HH, LW[w].Bb, nullptr, nullptr, nullptr);  // 1/P_w
         }
         wave_sync();
         kg_copy<P>(LW[0].Cb, LW[0].Bb);

@@ -1,20 +1,28 @@
 // Exact R/q product on the int8 matrix cores (v_mfma_i32_16x16x64_i8).
 //
-// The ring is R/q = (Z/q)[x]/(x^p - x - 1) (Section 2.1).  With 16-coefficient
-// blocks, the schoolbook convolution conv = a*b (degree <= 2p-2) is one matrix
-// product per 16-block w of conv:
-//   conv_{16w + r} = sum_d sum_k a_{16d + r - k} * b_{16(w - d) + k},
-//                    r, k in [0, 16), coefficients outside [0, p) being 0,
-// i.e. R (16 x NW) = T (16 x 16 ND) * H (16 ND x NW) with the block Toeplitz
-// T[r][(d,k)] = a_{16d + r - k} and the block Hankel H[(d,k)][w] = b_{16(w-d)+k};
-// each pair (a_j, b_m) with j + m = 16w + r appears exactly once.  The
-// reduction x^p = x + 1 then gives c_i = conv_i + conv_{i+p} + [i>=1] conv_{i+p-1}.
+// The ring is R/q = (Z/q)[x]/(x^p - x - 1) (Section 2.1).  Since x^p = x + 1
+// and every product degree k in [p, 2p-2] reduces in one step to
+// x^{k-p+1} + x^{k-p}, the product c = a b is
+//   c_i = conv_i + conv_{i+p} + [i >= 1] conv_{i+p-1},   conv = a * b,
+// which is one Toeplitz-by-vector product with the folded operand
+//   E_m = b_m (1 <= m < p),  E_0 = b_0 + b_{p-1},
+//   E_m = b_{m+p} + b_{m+p-1} (-(p-1) <= m <= -1),  0 elsewhere:
+//   c_i = sum_j a_j E_{i-j} for i >= 1, and for i = 0 the same sum minus
+//   conv_{p-1} = c_{p-1} - a_{p-1} b_{p-1} (the one pair (j, m) = (0, 0) whose
+//   b_{p-1} term belongs to x^{p-1}, not to x^0 + x^p).
+// With 16-coefficient blocks this is one matrix product per 16-block w of c:
+//   c_{16w + r} = sum_d sum_k a_{16d + r - k} * E_{16(w - d) + k},
+// R (16 x NWO) = T (16 x 16 ND) * H (16 ND x NWO) with the block Toeplitz
+// T[r][(d,k)] = a_{16d + r - k} and the block Hankel H[(d,k)][w] = E_{16(w-d)+k}.
+// Folding the reduction into H halves the output columns of the schoolbook
+// product (p instead of 2p - 1) and leaves no convolution to stage and fold.
 //
-// Exactness.  A centered residue x (|x| <= (q-1)/2 < 4096) is split as
-// x = 128 x_h + x_l with x_l in [-64, 64) and |x_h| <= 31; small operands
-// (|x| <= 3) are one int8 limb.  Each MFMA accumulates at most 16 ND <= 1296
-// products of int8 limbs in int32 (< 2^23 in magnitude), and the limb
-// partial sums are reduced mod q before they are combined.
+// Exactness.  A centered residue x (|x| <= (q-1)/2 < 2300) is split as
+// x = 128 x_h + x_l with x_l in [-64, 64) and |x_h| <= 18; an entry of E is
+// a sum of two residues (|x_h| <= 36 after the split).  Small operands
+// (|x| <= 3, |E_m| <= 6) are one int8 limb.  Each output sums at most p
+// nonzero products of int8 limbs in int32 (< 2^23 in magnitude), and the
+// limb partial sums are reduced mod q before they are combined.
 //
 // Layouts on one wave (16x16x64 int8: A lane l = row l%16 with K-bytes
 // 16(l/16) .. 16(l/16)+15; B lane l = column l%16 with the same K-bytes;
@@ -24,11 +32,11 @@
 //     bytes of the reversed limb array TL[z] = limb(a_{Z0 - z}) starting at
 //     Z0 - 16d - r, assembled from 5 aligned dwords with v_alignbyte (the byte
 //     offset (Z0 - r) mod 4 is fixed per lane);
-//   B (Hankel): lane (c, g) of tile t needs b_{16j + e}, j = 16t + c - 4 kappa - g:
+//   B (Hankel): lane (c, g) of tile t needs E_{16j + e}, j = 16t + c - 4 kappa - g:
 //     one aligned 16-byte read of the zero-padded limb array HL;
-//   the accumulator of lane (c, g), tile t, holds conv_{16(16t+c) + 4g + v}.
-// Only (tile, K-step) pairs whose blocks overlap the operands are issued;
-// the loops are unrolled so that this selection happens at compile time.
+//   the accumulator of lane (c, g), tile t, holds c_{256t + 16c + 4g + v}.
+// Every (tile, K-step) pair meets nonzero blocks of both operands; the loops
+// are unrolled at compile time.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -49,39 +57,22 @@ struct MfShape {
     static constexpr int Q = Param<P>::q;
     static constexpr int ND = (P + 14) / 16 + 1;        // Toeplitz blocks: 16d - 15 <= p - 1
     static constexpr int NKS = ceil_div(ND, 4);         // K-steps
-    static constexpr int NBH = (P - 1) / 16 + 1;        // blocks of the Hankel operand
-    static constexpr int NW = ceil_div(2 * P - 1, 16);  // blocks of the convolution
-    static constexpr int NT = ceil_div(NW, 16);         // 16-column tiles
+    static constexpr int NWO = ceil_div(P, 16);         // 16-blocks of the product
+    static constexpr int NT = ceil_div(NWO, 16);        // 16-column tiles
     static constexpr int Z0 = 64 * NKS + 15;            // TL[z] = limb(a_{Z0 - z})
     static constexpr int TLEN = round_up(Z0 + 20, 16);
-    static constexpr int klo(int t) {
-        const int d = 16 * t - NBH + 1;
-        return d > 0 ? d / 4 : 0;
-    }
-    static constexpr int khi(int t) {
-        const int d = 16 * t + 15;
-        return (d < ND - 1 ? d : ND - 1) / 4;
-    }
-    static constexpr int jmin() {
-        int m = 0;
-        for (int t = 0; t < NT; t++) m = (16 * t - 3 - 4 * khi(t) < m) ? 16 * t - 3 - 4 * khi(t) : m;
-        return m;
-    }
-    static constexpr int jmax() {
-        int m = 0;
-        for (int t = 0; t < NT; t++) m = (16 * t + 15 - 4 * klo(t) > m) ? 16 * t + 15 - 4 * klo(t) : m;
-        return m;
-    }
-    static constexpr int HOFF = -16 * jmin();           // HL[HOFF + m] = limb(b_m)
-    static constexpr int HLEN = 16 * (jmax() - jmin() + 1);
-    static constexpr int CLEN = 256 * NT;               // conv staging (int16)
-    static_assert(256 * NT >= 2 * P, "tiles cover conv and conv_{2p-1} = 0");
-    static_assert(HOFF + 16 * NBH <= HLEN, "padding covers the Hankel operand");
-    static constexpr int pairs() {
-        int s = 0;
-        for (int t = 0; t < NT; t++) s += khi(t) - klo(t) + 1;
-        return s;
-    }
+    static constexpr int HOFF = 64 * NKS - 16;          // HL[HOFF + m] = limb(E_m): lowest block read is -(4 NKS - 1)
+    static constexpr int HLEN = HOFF + 256 * NT;        // highest block read is 16 NT - 1
+    static constexpr int NEG = HOFF - (P - 1);          // first byte of E_{-(p-1)}
+    static_assert(P % 4 == 1, "every parameter set has p = 1 mod 4: the folded words stay dword-aligned");
+    static_assert(NEG >= 0 && NEG % 4 == 0, "E_{-(p-1)} starts on a dword inside the array");
+    static_assert(HOFF % 16 == 0 && HLEN % 16 == 0, "16-byte Hankel reads are aligned");
+    static_assert((Z0 - 3) % 4 == 0, "reversed limb words are aligned");
+    static constexpr int pairs() { return NT * NKS; }
+    // lane and tile holding c_{p-1} (accumulator element 0)
+    static constexpr int TP = (P - 1) / 256;
+    static constexpr int LP = ((P - 1) % 256) / 16 + 16 * (((P - 1) % 16) / 4);
+    static_assert((P - 1) % 4 == 0, "c_{p-1} is accumulator element 0 of its lane");
 };
 
 typedef int mf_v4i __attribute__((ext_vector_type(4)));
@@ -91,6 +82,11 @@ __device__ __forceinline__ void split_limb(int32_t x, uint32_t& lo, uint32_t& hi
     const int32_t h = (x + 64) >> 7;
     lo = (uint32_t)(uint8_t)(int8_t)(x - 128 * h);
     hi = (uint32_t)(uint8_t)(int8_t)h;
+}
+
+// Byte-wise sum of two words of four int8 values (no carries between bytes).
+__device__ __forceinline__ uint32_t add8x4(uint32_t a, uint32_t b) {
+    return ((a & 0x7F7F7F7Fu) + (b & 0x7F7F7F7Fu)) ^ ((a ^ b) & 0x80808080u);
 }
 
 // Reversed Toeplitz limbs of X (int16, p centered entries):
@@ -114,8 +110,18 @@ __device__ __forceinline__ void build_toeplitz(const int16_t* X, uint8_t* TL, ui
     }
 }
 
-// Zero-padded Hankel limbs of X: HL[HOFF + m] = lo(X[m]), HH likewise; a
-// small operand (|X_m| <= 3, hi = 0) needs HL only: pass HH = nullptr.
+// Folded coefficient E_m of X (int16, p centered entries).
+template <int P>
+__device__ __forceinline__ int32_t folded_coef(const int16_t* X, int m) {
+    if (m >= 1 && m < P) return X[m];
+    if (m == 0) return (int32_t)X[0] + (int32_t)X[P - 1];
+    if (m < 0 && m >= -(P - 1)) return (int32_t)X[m + P] + (int32_t)X[m + P - 1];
+    return 0;
+}
+
+// Hankel limbs of X, folded and zero-padded: HL[HOFF + m] = lo(E_m), HH
+// likewise; a small operand (|X_m| <= 3, hi = 0) needs HL only: pass
+// HH = nullptr.  X may be in LDS or in global memory.
 template <int P>
 __device__ __forceinline__ void build_hankel(const int16_t* X, uint8_t* HL, uint8_t* HH) {
     using S = MfShape<P>;
@@ -123,10 +129,8 @@ __device__ __forceinline__ void build_hankel(const int16_t* X, uint8_t* HL, uint
         uint32_t lo = 0, hi = 0;
 #pragma unroll
         for (int t = 0; t < 4; t++) {
-            const int m = 4 * i + t - S::HOFF;
-            const int32_t v = (m >= 0 && m < P) ? (int32_t)X[m] : 0;
             uint32_t l, h;
-            split_limb(v, l, h);
+            split_limb(folded_coef<P>(X, 4 * i + t - S::HOFF), l, h);
             lo |= l << (8 * t);
             hi |= h << (8 * t);
         }
@@ -135,17 +139,90 @@ __device__ __forceinline__ void build_hankel(const int16_t* X, uint8_t* HL, uint
     }
 }
 
-// conv of T-operand (limbs TL, TH) and H-operand (limbs HL, and HH when
-// H_BIG) over the tiles [T0, T1), written to CS as centered int16:
-// CS[16w + r] = conv_{16w+r} mod q.  Software-pipelined: the fragments of
-// K-step k+1 are read from LDS while the MFMAs of K-step k run.
+// Folded Hankel bytes of a small operand held in registers: lane l holds
+// x_m, m = 4l + 256u + t (t = 0..3), as the int8 bytes of w[u] (zero for
+// m >= p).  Writes E_m for -(p-1) <= m < p at H[HOFF + m]; the padding
+// around it is left as it is (zero).
+template <int P, int NU>
+__device__ __forceinline__ void put_folded8(const uint32_t (&w)[NU], uint8_t* H) {
+    using S = MfShape<P>;
+    constexpr int UP = (P - 1) / 256, LPB = ((P - 1) / 4) % 64;   // word and lane of x_{p-1} (byte 0)
+    static_assert(NU * 256 >= P, "the words cover the operand");
+    const int lane = lane_id();
+    const uint32_t xp = (uint32_t)__builtin_amdgcn_readlane((int)w[UP], LPB) & 0xFFu;
+#pragma unroll
+    for (int u = 0; u < NU; u++) {
+        const int m0 = 4 * lane + 256 * u;
+        uint32_t nx = (uint32_t)__shfl_down((int)w[u], 1);   // word of m0 + 4
+        if (u + 1 < NU) {
+            const uint32_t n0 = (uint32_t)__builtin_amdgcn_readlane((int)w[u + 1 < NU ? u + 1 : u], 0);
+            nx = (lane == 63) ? n0 : nx;
+        }
+        if (m0 < P) {
+            // E_m = x_m (m >= 1), E_0 = x_0 + x_{p-1}
+            const uint32_t pos = (u == 0 && lane == 0) ? add8x4(w[u], xp) : w[u];
+            *(uint32_t*)(H + S::HOFF + m0) = pos;
+            // E_{m0 - (p-1) + t} = x_{m0+t+1} + x_{m0+t}
+            if (m0 + 4 < P) *(uint32_t*)(H + S::NEG + m0) = add8x4(w[u], (w[u] >> 8) | (nx << 24));
+        }
+    }
+}
+
+// The same for a big operand: lane l holds x_m (int16, centered) as two
+// words per u, w[u][0] = (x_{m0}, x_{m0+1}), w[u][1] = (x_{m0+2}, x_{m0+3});
+// writes the limbs of E_m to HL and HH.
+template <int P, int NU>
+__device__ __forceinline__ void put_folded16(const uint32_t (&w)[NU][2], uint8_t* HL, uint8_t* HH) {
+    using S = MfShape<P>;
+    constexpr int UP = (P - 1) / 256, LPB = ((P - 1) / 4) % 64;
+    static_assert(NU * 256 >= P, "the words cover the operand");
+    const int lane = lane_id();
+    const int32_t xp = (int32_t)(int16_t)(__builtin_amdgcn_readlane((int)w[UP][0], LPB) & 0xFFFF);
+#pragma unroll
+    for (int u = 0; u < NU; u++) {
+        const int m0 = 4 * lane + 256 * u;
+        uint32_t nx = (uint32_t)__shfl_down((int)w[u][0], 1);
+        if (u + 1 < NU) {
+            const uint32_t n0 = (uint32_t)__builtin_amdgcn_readlane((int)w[u + 1 < NU ? u + 1 : u][0], 0);
+            nx = (lane == 63) ? n0 : nx;
+        }
+        if (m0 < P) {
+            int32_t x[5];
+#pragma unroll
+            for (int t = 0; t < 4; t++) x[t] = (int32_t)(int16_t)(w[u][t >> 1] >> (16 * (t & 1)));
+            x[4] = (int32_t)(int16_t)(nx & 0xFFFFu);
+            uint32_t pl = 0, ph = 0, nl = 0, nh = 0;
+#pragma unroll
+            for (int t = 0; t < 4; t++) {
+                uint32_t l, h;
+                split_limb(x[t] + ((u == 0 && t == 0 && lane == 0) ? xp : 0), l, h);
+                pl |= l << (8 * t);
+                ph |= h << (8 * t);
+                split_limb(x[t] + x[t + 1], l, h);
+                nl |= l << (8 * t);
+                nh |= h << (8 * t);
+            }
+            *(uint32_t*)(HL + S::HOFF + m0) = pl;
+            *(uint32_t*)(HH + S::HOFF + m0) = ph;
+            if (m0 + 4 < P) {
+                *(uint32_t*)(HL + S::NEG + m0) = nl;
+                *(uint32_t*)(HH + S::NEG + m0) = nh;
+            }
+        }
+    }
+}
+
+// Output tiles [T0, T1) of c = a b (before the correction of c_0): T-operand
+// limbs (TL, TH), folded H-operand limbs (HL, and HH when H_BIG).  Lane
+// (c, g) returns c_{i+v}, i = 256t + 16c + 4g, in out[t] as centered int16
+// pairs (zero for i + v >= p).  Software-pipelined: the fragments of K-step
+// k+1 are read from LDS while the MFMAs of K-step k run.
 template <int P, bool H_BIG, int T0, int T1>
-__device__ __forceinline__ void mfma_conv(const uint8_t* TL, const uint8_t* TH, const uint8_t* HL,
-                                          const uint8_t* HH, int16_t* CS) {
+__device__ __forceinline__ void mfma_tiles(const uint8_t* TL, const uint8_t* TH, const uint8_t* HL,
+                                           const uint8_t* HH, uint32_t (&out)[MfShape<P>::NT][2]) {
     using S = MfShape<P>;
     constexpr int Q = S::Q;
     constexpr int NTC = T1 - T0;
-    constexpr int KLO = S::klo(T0), KHI = S::khi(T1 - 1);
     const int lane = lane_id();
     const int rc = lane & 15, g = lane >> 4;
     // Toeplitz read position of K-step 0: bytes from Z0 - 16 g - rc
@@ -174,15 +251,14 @@ __device__ __forceinline__ void mfma_conv(const uint8_t* TL, const uint8_t* TH, 
         }
 #pragma unroll
         for (int t = 0; t < NTC; t++) {
-            if (k < S::klo(T0 + t) || k > S::khi(T0 + t)) continue;
             const int off = 16 * (16 * (T0 + t) - 4 * k);
             nBL[t] = *(const mf_v4i*)(hl + off);
             if (H_BIG) nBH[t] = *(const mf_v4i*)(hh + off);
         }
     };
-    load_step(KLO);
+    load_step(0);
 #pragma unroll
-    for (int k = KLO; k <= KHI; k++) {
+    for (int k = 0; k < S::NKS; k++) {
         // one K-step of fragments in flight beyond the current one
         if (NTRUP_MF_SCHED) __builtin_amdgcn_sched_barrier(0);
         uint32_t DL[5], DH[5];
@@ -197,7 +273,7 @@ __device__ __forceinline__ void mfma_conv(const uint8_t* TL, const uint8_t* TH, 
             BL[t] = nBL[t];
             BH[t] = nBH[t];
         }
-        if (k < KHI) load_step(k + 1);
+        if (k + 1 < S::NKS) load_step(k + 1);
         mf_v4i tl, th;
 #pragma unroll
         for (int j = 0; j < 4; j++) {
@@ -206,7 +282,6 @@ __device__ __forceinline__ void mfma_conv(const uint8_t* TL, const uint8_t* TH, 
         }
 #pragma unroll
         for (int t = 0; t < NTC; t++) {
-            if (k < S::klo(T0 + t) || k > S::khi(T0 + t)) continue;
             if (H_BIG) {
                 acc0[t] = __builtin_amdgcn_mfma_i32_16x16x64_i8(tl, BL[t], acc0[t], 0, 0, 0);
                 acc1[t] = __builtin_amdgcn_mfma_i32_16x16x64_i8(tl, BH[t], acc1[t], 0, 0, 0);
@@ -222,6 +297,7 @@ __device__ __forceinline__ void mfma_conv(const uint8_t* TL, const uint8_t* TH, 
     constexpr int32_t C14 = ((16384 % Q) > Q / 2) ? (16384 % Q) - Q : (16384 % Q);
 #pragma unroll
     for (int t = 0; t < NTC; t++) {
+        const int i = 256 * (T0 + t) + 16 * rc + 4 * g;
         int32_t v[4];
 #pragma unroll
         for (int e = 0; e < 4; e++) {
@@ -230,95 +306,21 @@ __device__ __forceinline__ void mfma_conv(const uint8_t* TL, const uint8_t* TH, 
                                  C14 * reduce_rough<Q>(acc2[t][e]));
             else
                 v[e] = freeze<Q>(acc0[t][e] + 128 * acc1[t][e]);
+            v[e] = (i + e < P) ? v[e] : 0;
         }
-        const uint32_t w0 = (uint32_t)(uint16_t)v[0] | ((uint32_t)(uint16_t)v[1] << 16);
-        const uint32_t w1 = (uint32_t)(uint16_t)v[2] | ((uint32_t)(uint16_t)v[3] << 16);
-        *(uint2*)(CS + 16 * (16 * (T0 + t) + rc) + 4 * g) = make_uint2(w0, w1);
-    }
-}
-
-// c = a * b in R/q from the staged convolution:
-//   c_i = conv_i + conv_{i+p} + [i >= 1] conv_{i+p-1},
-// four consecutive outputs i = 4 lane + 256 u + t per lane.  Any of
-//   dst  (LDS int16, c_i at dst[i]),
-//   TLo/THo (LDS, the reversed Toeplitz limbs of c for the next product:
-//        TLo[Z0 - i] = lo(c_i), THo[Z0 - i] = hi(c_i)),
-//   row  (global int16)
-// may be nullptr.
-template <int P>
-__device__ __forceinline__ void mfma_fold(const int16_t* CS, int16_t* dst, uint8_t* TLo, uint8_t* THo,
-                                          int16_t* row) {
-    using S = MfShape<P>;
-    constexpr int Q = S::Q;
-    constexpr int NU = ceil_div(P, 256);
-    static_assert(S::CLEN >= 2 * P + 4, "the last window read stays in the staging");
-    static_assert((S::Z0 - 3) % 4 == 0, "reversed limb words are aligned");
-    const int lane = lane_id();
-    uint32_t A[NU][2], E[NU][3];
-#pragma unroll
-    for (int u = 0; u < NU; u++) {
-        const int i = 4 * lane + 256 * u;
-        if (i < P) {
-            const uint2 a = *(const uint2*)(CS + i);
-            const uint32_t* e = (const uint32_t*)(CS + i + P - 1);   // i + p - 1 is even
-            A[u][0] = a.x;
-            A[u][1] = a.y;
-            E[u][0] = e[0];
-            E[u][1] = e[1];
-            E[u][2] = e[2];
-        }
-    }
-#pragma unroll
-    for (int u = 0; u < NU; u++) {
-        const int i = 4 * lane + 256 * u;
-        if (i >= P) continue;
-        int32_t c[4];
-#pragma unroll
-        for (int t = 0; t < 4; t++) {
-            const int32_t cs = (int16_t)(A[u][t >> 1] >> (16 * (t & 1)));
-            const int32_t e0 = (int16_t)(E[u][t >> 1] >> (16 * (t & 1)));               // conv_{i+p-1+t}
-            const int32_t e1 = (int16_t)(E[u][(t + 1) >> 1] >> (16 * ((t + 1) & 1)));   // conv_{i+p+t}
-            const int32_t v = cs + e1 + ((i + t >= 1) ? e0 : 0);
-            c[t] = (i + t < P) ? freeze<Q>(v) : 0;
-        }
-        if (dst) {
-            if (i + 3 < P) {
-                *(uint2*)(dst + i) = make_uint2((uint32_t)(uint16_t)c[0] | ((uint32_t)(uint16_t)c[1] << 16),
-                                                (uint32_t)(uint16_t)c[2] | ((uint32_t)(uint16_t)c[3] << 16));
-            } else {
-#pragma unroll
-                for (int t = 0; t < 4; t++)
-                    if (i + t < P) dst[i + t] = (int16_t)c[t];
-            }
-        }
-        if (TLo) {
-            uint32_t lo = 0, hi = 0;
-#pragma unroll
-            for (int t = 0; t < 4; t++) {
-                uint32_t l, h;
-                split_limb(c[t], l, h);
-                lo |= l << (8 * (3 - t));
-                hi |= h << (8 * (3 - t));
-            }
-            *(uint32_t*)(TLo + S::Z0 - i - 3) = lo;
-            *(uint32_t*)(THo + S::Z0 - i - 3) = hi;
-        }
-        if (row) {
-#pragma unroll
-            for (int t = 0; t < 4; t++)
-                if (i + t < P) row[i + t] = (int16_t)c[t];
-        }
+        out[T0 + t][0] = (uint32_t)(uint16_t)v[0] | ((uint32_t)(uint16_t)v[1] << 16);
+        out[T0 + t][1] = (uint32_t)(uint16_t)v[2] | ((uint32_t)(uint16_t)v[3] << 16);
     }
 }
 
 // Tile chunks of one product: at most MAXC tiles share one pass over the
 // K-steps, so that the accumulators (2 or 3 sets of 4 registers per tile)
-// stay in registers next to the Toeplitz fragments.
+// stay in registers next to the fragments.
 #ifndef NTRUP_MF_MAXC_SMALL
 #define NTRUP_MF_MAXC_SMALL 6
 #endif
 #ifndef NTRUP_MF_MAXC_BIG
-#define NTRUP_MF_MAXC_BIG 4
+#define NTRUP_MF_MAXC_BIG 5
 #endif
 template <int P, bool H_BIG>
 struct MfSplit {
@@ -329,25 +331,68 @@ struct MfSplit {
 };
 
 template <int P, bool H_BIG, int C>
-__device__ __forceinline__ void mfma_conv_chunks(const uint8_t* TL, const uint8_t* TH, const uint8_t* HL,
-                                                 const uint8_t* HH, int16_t* CS) {
+__device__ __forceinline__ void mfma_chunks(const uint8_t* TL, const uint8_t* TH, const uint8_t* HL,
+                                            const uint8_t* HH, uint32_t (&out)[MfShape<P>::NT][2]) {
     using SP = MfSplit<P, H_BIG>;
     if constexpr (C < SP::NC) {
-        mfma_conv<P, H_BIG, SP::lo(C), SP::lo(C + 1)>(TL, TH, HL, HH, CS);
-        mfma_conv_chunks<P, H_BIG, C + 1>(TL, TH, HL, HH, CS);
+        mfma_tiles<P, H_BIG, SP::lo(C), SP::lo(C + 1)>(TL, TH, HL, HH, out);
+        mfma_chunks<P, H_BIG, C + 1>(TL, TH, HL, HH, out);
     }
 }
 
-// c = a * b: T-operand limbs (TL, TH) and H-operand limbs (HL, HH) already
-// built; CS = conv staging (CLEN int16).  Ends with the result in dst, the
-// Toeplitz limbs (TLo, THo; may be TL, TH themselves) and / or row.
-// Wave-local: the caller orders the inputs (wave_sync) before the call.
+// c = a b in R/q: T-operand limbs (TL, TH) of a and folded H-operand limbs
+// (HL, HH) of b already built.  Any of
+//   dst  (LDS int16, c_i at dst[i]),
+//   TLo/THo (LDS, the reversed Toeplitz limbs of c for the next product:
+//        TLo[Z0 - i] = lo(c_i), THo[Z0 - i] = hi(c_i); may be TL, TH),
+//   row  (global int16)
+// may be nullptr.  Wave-local: the caller orders the inputs (wave_sync)
+// before the call and the outputs after it.
 template <int P, bool H_BIG>
 __device__ __forceinline__ void mfma_mul(const uint8_t* TL, const uint8_t* TH, const uint8_t* HL, const uint8_t* HH,
-                                         int16_t* CS, int16_t* dst, uint8_t* TLo, uint8_t* THo, int16_t* row) {
-    mfma_conv_chunks<P, H_BIG, 0>(TL, TH, HL, HH, CS);
+                                         int16_t* dst, uint8_t* TLo, uint8_t* THo, int16_t* row) {
+    using S = MfShape<P>;
+    constexpr int Q = S::Q;
+    // a_{p-1} b_{p-1} (b_{p-1} = E_{p-1}), read before TLo may replace TL
+    const int32_t ap = (int32_t)(int8_t)TL[S::Z0 - (P - 1)] + 128 * (int32_t)(int8_t)TH[S::Z0 - (P - 1)];
+    const int32_t bp = (int32_t)(int8_t)HL[S::HOFF + P - 1] +
+                       (H_BIG ? 128 * (int32_t)(int8_t)HH[S::HOFF + P - 1] : 0);
+    uint32_t out[S::NT][2];
+    mfma_chunks<P, H_BIG, 0>(TL, TH, HL, HH, out);
+    // c_0 = (folded sum at 0) - conv_{p-1},  conv_{p-1} = c_{p-1} - a_{p-1} b_{p-1}
+    const int lane = lane_id();
+    const int32_t cp = (int32_t)(int16_t)(__builtin_amdgcn_readlane((int)out[S::TP][0], S::LP) & 0xFFFF);
+    const int32_t c0 = freeze<Q>((int32_t)(int16_t)(out[0][0] & 0xFFFFu) - cp + ap * bp);
+    if (lane == 0) out[0][0] = (out[0][0] & 0xFFFF0000u) | (uint32_t)(uint16_t)c0;
     wave_sync();
-    mfma_fold<P>(CS, dst, TLo, THo, row);
+    const int rc = lane & 15, g = lane >> 4;
+#pragma unroll
+    for (int t = 0; t < S::NT; t++) {
+        const int i = 256 * t + 16 * rc + 4 * g;
+        if (i >= P) continue;
+        const uint32_t w0 = out[t][0], w1 = out[t][1];
+        if (dst) {
+            if (i + 3 < P) *(uint2*)(dst + i) = make_uint2(w0, w1);
+            else dst[i] = (int16_t)(w0 & 0xFFFFu);   // p = 1 mod 4: c_{p-1} alone
+        }
+        if (TLo) {
+            uint32_t lo = 0, hi = 0;
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                uint32_t l, h;
+                split_limb((int32_t)(int16_t)((e < 2 ? w0 : w1) >> (16 * (e & 1))), l, h);
+                lo |= l << (8 * (3 - e));
+                hi |= h << (8 * (3 - e));
+            }
+            *(uint32_t*)(TLo + S::Z0 - i - 3) = lo;
+            *(uint32_t*)(THo + S::Z0 - i - 3) = hi;
+        }
+        if (row) {
+#pragma unroll
+            for (int e = 0; e < 4; e++)
+                if (i + e < P) row[i + e] = (int16_t)((e < 2 ? w0 : w1) >> (16 * (e & 1)));
+        }
+    }
 }
 
 }  // namespace ntrup
