@@ -68,7 +68,8 @@ __device__ __forceinline__ uint32_t row_prev(uint32_t x) {
 constexpr uint32_t kSel = ((0xF0u & 0xCCu) | (~0xF0u & 0xAAu)) & 0xFFu;   // x ? y : z  (0xCA)
 constexpr uint32_t kXor3 = (0xF0u ^ 0xCCu ^ 0xAAu) & 0xFFu;              // x ^ y ^ z  (0x96)
 constexpr uint32_t kAddM = ((0xF0u ^ 0xCCu) | (0xF0u & 0xCCu & ~0xAAu)) & 0xFFu;  // (0x7C)
-static_assert(kSel == 0xCA && kXor3 == 0x96 && kAddM == 0x7C, "bitop3 tables");
+constexpr uint32_t kAndXnor = (0xF0u & ~(0xCCu ^ 0xAAu)) & 0xFFu;            // x & ~(y ^ z)  (0x90)
+static_assert(kSel == 0xCA && kXor3 == 0x96 && kAddM == 0x7C && kAndXnor == 0x90, "bitop3 tables");
 
 __device__ __forceinline__ uint32_t sel(uint32_t mask, uint32_t a, uint32_t b) {
     return __builtin_amdgcn_bitop3_b32(mask, a, b, kSel);
@@ -139,19 +140,24 @@ __device__ __forceinline__ int r3_divsteps(typename R3Shape<P, LPK>::Words& gm,
         vm[k] = 0;
         vs[k] = 0;
     }
-    int delta = 1;
+    // e = delta - 1: delta > 0 iff the sign bit of e is clear
+    int32_t e = 0;
     const uint32_t last = (h == LPK - 1) ? 0xFFFFFFFFu : 0u;   // top lane of the key's group
     const uint32_t first = (h == 0) ? 0xFFFFFFFFu : 0u;        // bottom lane
-#pragma unroll 1
+    // three steps per trip: the register renaming of the updates needs no moves
+#pragma unroll 3
     for (int step = 0; step < 2 * P - 1; step++) {
-        // coefficient 0 of f and g lives in bit 0 of word 0 of the even lane
-        uint32_t c0 = (fm[0] & 1u) | ((fs[0] & 1u) << 1) | ((gm[0] & 1u) << 2) | ((gs[0] & 1u) << 3);
-        c0 = group_first<LPK>(c0);
-        const uint32_t f0s = (c0 >> 1) & 1u, g0m = (c0 >> 2) & 1u, g0s = (c0 >> 3) & 1u;
-        const uint32_t SW = 0u - ((uint32_t)(delta > 0) & g0m);  // swap mask
-        const uint32_t NZ = 0u - g0m;                             // s != 0
-        const uint32_t NEG = NZ & (0u - (1u ^ g0s ^ f0s));        // s == -1
-        delta = (int)((((uint32_t)(-delta)) & SW) | (((uint32_t)delta) & ~SW)) + 1;
+        // coefficient 0 of f and g lives in bit 0 of word 0 of the group's first
+        // lane; f(0) != 0, so only its sign matters
+        const uint32_t fs0 = group_first<LPK>(fs[0]);
+        const uint32_t gm0 = group_first<LPK>(gm[0]);
+        const uint32_t gs0 = group_first<LPK>(gs[0]);
+        const uint32_t NZ = (uint32_t)__builtin_amdgcn_sbfe((int)gm0, 0, 1);          // s != 0
+        const uint32_t NEG = (uint32_t)__builtin_amdgcn_sbfe(
+            (int)__builtin_amdgcn_bitop3_b32(gm0, gs0, fs0, kAndXnor), 0, 1);          // s == -1
+        const uint32_t SW = NZ & ~(uint32_t)(e >> 31);                               // swap mask
+        // delta' = swap ? 1 - delta : 1 + delta, i.e. e' = swap ? ~e : e + 1
+        e = (int32_t)((uint32_t)e ^ SW) + (int32_t)SW + 1;
 #pragma unroll
         for (int k = 0; k < W2; k++) {
             // g' = s*g + (s != 0 ? f : 0); r' = s*r + (s != 0 ? v : 0)   (F_3 adds)
@@ -201,7 +207,7 @@ __device__ __forceinline__ int r3_divsteps(typename R3Shape<P, LPK>::Words& gm,
     const uint32_t FLIP = 0u - f0;
 #pragma unroll
     for (int k = 0; k < W2; k++) vs[k] = (vs[k] ^ FLIP) & vm[k];
-    return delta;
+    return e + 1;
 }
 
 }  // namespace ntrup
