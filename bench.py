@@ -65,6 +65,49 @@ def stored_traffic(kernel: str):
     return None if entry is None else entry["bytes_per_launch"]
 
 
+def kernel_key(name: str) -> str:
+    """'void ntrup::r3_kernel<761, 4>(ntrup::R3Args)' -> 'r3_kernel<761,4>'."""
+    base = name.split("(")[0].replace("void ", "").replace("ntrup::", "")
+    return base.replace(" ", "")
+
+
+def summarize_counters(directory: str, copy_mib: int, workload: str) -> dict:
+    """profiles/hbm_traffic.json from two rocprofv3 --pmc runs of bench.py with
+    --calib-copy-mib: <directory>/fetch and <directory>/write, each holding
+    pmc_counter_collection.csv (FETCH_SIZE, WRITE_SIZE in KiB per dispatch).
+    The plain device copy of copy_mib MiB reads and writes copy_mib MiB; the
+    ratio of that to what the counters report for it scales every kernel.
+    Host-only: reads CSV files, runs nothing on the GPU."""
+    import csv
+    per = {}
+    for which, counter in (("fetch", "FETCH_SIZE"), ("write", "WRITE_SIZE")):
+        path = os.path.join(directory, which, "pmc_counter_collection.csv")
+        with open(path) as fh:
+            for row in csv.DictReader(fh):
+                if row["Counter_Name"] != counter:
+                    continue
+                key = kernel_key(row["Kernel_Name"])
+                per.setdefault(key, {}).setdefault(which, []).append(float(row["Counter_Value"]))
+    copy = per.get("__amd_rocclr_copyBuffer")
+    if not copy or "fetch" not in copy or "write" not in copy:
+        raise SystemExit("no calibration copy in %s (run bench.py with --calib-copy-mib)" % directory)
+    expected = copy_mib * 1024.0
+    cal_f, cal_w = max(copy["fetch"]), max(copy["write"])
+    fs, ws = expected / cal_f, expected / cal_w
+    kernels = {}
+    for key, d in sorted(per.items()):
+        if not key.startswith(("r3_kernel", "keygen_", "sample_short", "group_")) or "fetch" not in d or "write" not in d:
+            continue
+        f = sum(d["fetch"]) / len(d["fetch"])
+        w = sum(d["write"]) / len(d["write"])
+        kernels[key] = {"fetch_kib_raw": round(f, 2), "write_kib_raw": round(w, 2),
+                        "bytes_per_launch": int(round((f * fs + w * ws) * 1024))}
+    return {"sources_sha256": sources_digest(),
+            "calibration": {"copy_mib": copy_mib, "fetch_kib": round(cal_f, 2), "write_kib": round(cal_w, 2),
+                            "fetch_scale": round(fs, 4), "write_scale": round(ws, 4)},
+            "workload": workload, "kernels": kernels}
+
+
 def ceil_div(a, b):
     return -(-a // b)
 
@@ -148,9 +191,21 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the plain-form and N=1024 side measurements")
+    ap.add_argument("--summarize-counters", metavar="DIR", default=None,
+                    help="host only: write profiles/hbm_traffic.json from DIR/fetch and DIR/write "
+                         "(rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs of this script) and exit")
+    ap.add_argument("--workload-note", default="", help="workload line stored with --summarize-counters")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one device-to-device copy of this many MiB first (HBM counter calibration)")
     args = ap.parse_args()
+
+    if args.summarize_counters:
+        data = summarize_counters(args.summarize_counters, args.calib_copy_mib or 256, args.workload_note)
+        with open(TRAFFIC_FILE, "w") as fh:
+            json.dump(data, fh, indent=1)
+            fh.write("\n")
+        print(json.dumps(data["kernels"], indent=1))
+        return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "

@@ -14,11 +14,14 @@ Knobs (see ``ntrup_config`` in include/ntrupkg.h):
                  invertible (matters for p = 653, 1277, where the retry
                  passes are latency-bound).
 
-The group knobs (G, W) and the R/3 knobs act on different kernels, so they
-are tuned one after the other: first (G, W) with the default R/3 knobs, then
-the R/3 knobs with the chosen (G, W), each timed in the launch form of the
-tuning mode (eager launches run the prefix kernel beside the R/3 stage; graph
-replay is one linear stream per job); mode "auto" then compares the two forms.  The product tiles are fixed by p.
+The group knobs (G, W) and the R/3 knobs act on different kernels, but in
+eager launches the prefix kernel runs beside the R/3 stage and the two compete
+for the same compute units, so the first phase times (G, W) jointly with the
+lanes per key of the R/3 main pass (PHASE1_LANES); the second phase then times
+every R/3 setting (lanes per key, retry knobs) with the chosen (G, W).  Each
+candidate runs in the launch form of the tuning mode (eager launches, or graph
+replay: one linear stream per job); mode "auto" then compares the two forms.
+The product tiles are fixed by p.
 Every candidate is timed on the real pipeline with HIP events on the launch
 stream; the winner per (device, p, N rounded up to a power of two) is cached
 as JSON.
@@ -31,6 +34,7 @@ import time
 
 GROUP_SIZES = (8, 16, 32, 64, 128)
 SHARES = (1, 2, 4, 8)
+PHASE1_LANES = (2, 4)   # R/3 lanes per key timed jointly with (G, W)
 KNOBS = ("group_size", "inverse_share", "lanes_per_key", "retry_passes", "retry_lanes_per_key",
          "retry_parallel_attempts")
 
@@ -74,6 +78,11 @@ def r3_candidates(p: int):
 def candidates(p: int, n: int):
     """All configurations the two tuning phases may time (for reference)."""
     return [dict(g, **r) for g in group_candidates(p, n) for r in r3_candidates(p)]
+
+
+def phase1_candidates(p: int, n: int):
+    """The (G, W, lanes per key) settings of the first phase."""
+    return [dict(g, lanes_per_key=l) for l in PHASE1_LANES for g in group_candidates(p, n)]
 
 
 def device_id(device: int) -> str:
@@ -162,10 +171,11 @@ def tune(ctx, p: int, n: int, seed: bytes | None = None, reps: int = 3, force: b
     cur = {k: base[k] for k in KNOBS}
     ctx.set_config(p, product_engine=1)
     table = []
-    # phase 1: the group stage
-    for gc in group_candidates(p, n):
-        cfg = dict(cur, **gc)
-        table.append(dict(cfg, ms=round(time_config(ctx, p, n, cfg, seed, reps, pk, sk, ug), 4)))
+    # phase 1: the group stage, jointly with the R/3 main pass's lanes per key
+    for lanes in PHASE1_LANES:
+        for gc in group_candidates(p, n):
+            cfg = dict(cur, lanes_per_key=lanes, **gc)
+            table.append(dict(cfg, ms=round(time_config(ctx, p, n, cfg, seed, reps, pk, sk, ug), 4)))
     best = min(table, key=lambda r: r["ms"])
     cur.update({k: best[k] for k in ("group_size", "inverse_share")})
     # phase 2: the R/3 stage

@@ -37,3 +37,12 @@ def test_cache_roundtrip(tmp_path):
     assert autotune.lookup("dev", 761, 70000, path) is None       # next bucket
     assert autotune.lookup("other", 761, 65536, path) is None
     assert autotune.lookup("dev", 761, 65536, path, mode="graph") is None   # per launch form
+
+
+def test_phase1_times_group_knobs_with_both_lane_counts():
+    c = autotune.phase1_candidates(761, 65536)
+    assert {x["lanes_per_key"] for x in c} == set(autotune.PHASE1_LANES)
+    # every (G, W) pair appears once per lane count
+    pairs = [(x["group_size"], x["inverse_share"]) for x in c]
+    assert len(pairs) == len(autotune.PHASE1_LANES) * len(autotune.group_candidates(761, 65536))
+    assert (32, 8) in pairs and (64, 2) in pairs
