@@ -271,20 +271,27 @@ def main():
     assert cfg["product_engine"] == 1, "the roofline below prices the matrix-core group kernel"
     ops = dict(group_kernel_ops(p, n, cfg["group_size"], cfg["inverse_share"]),
                r3_main=r3_kernel_ops(p, n), sample_short=short_kernel_ops(p, n))
+    # the persistent fused kernel does all of it; priced on its vector-ALU work
+    # (R/3 divsteps and sampling), its matrix-core work being the smaller share
+    ops["fused"] = ops["r3_main"] + ops["sample_short"]
     peaks = {"group_prefix": I8_MFMA_PEAK, "group_back": I8_MFMA_PEAK, "r3_main": VALU_PEAK,
-             "sample_short": VALU_PEAK}
+             "sample_short": VALU_PEAK, "fused": VALU_PEAK}
     units = {"group_prefix": "T int8-op/s", "group_back": "T int8-op/s", "r3_main": "T lane-op/s",
-             "sample_short": "T lane-op/s"}
+             "sample_short": "T lane-op/s", "fused": "T lane-op/s"}
     # the dominant kernel is the longest stage on the critical path; in eager
     # mode the prefix kernel runs beside the R/3 stage, so its wall time is
     # shared and it is not a candidate
-    crit = [k for k in ops if not (k == "group_prefix" and not cfg["use_graph"])]
-    dom = max(crit, key=lambda k: avg[k])
+    if cfg.get("persistent"):
+        dom = "fused"
+    else:
+        crit = [k for k in ops if k != "fused" and not (k == "group_prefix" and not cfg["use_graph"])]
+        dom = max(crit, key=lambda k: avg[k])
     achieved = ops[dom] / (avg[dom] / 1e3)
     kernel_names = {"group_prefix": "keygen_prefix_kernel<%d,%d>" % (p, cfg["inverse_share"]),
                     "group_back": "keygen_back_kernel<%d>" % p,
                     "r3_main": "r3_kernel<%d,%d>" % (p, cfg["lanes_per_key"]),
-                    "sample_short": "sample_short_kernel<%d>" % p}
+                    "sample_short": "sample_short_kernel<%d>" % p,
+                    "fused": "keygen_persistent_kernel<%d,%d>" % (cfg["lanes_per_key"], p)}
     roofline = {"bound": "mfma" if dom.startswith("group") else "alu", "kernel": kernel_names[dom],
                 "achieved": round(achieved / 1e12, 3),
                 "peak": round(peaks[dom] / 1e12, 2), "unit": units[dom], "frac": round(achieved / peaks[dom], 4),
@@ -332,8 +339,47 @@ def main():
         torch.cuda.synchronize()
         assert ctx.status() == 0
         mixed_ms = e0.elapsed_time(e1) / 5
+        all_pers = all(ctx.get_config(q_)["persistent"] for q_ in (653, 761, 857, 1277))
         extras["mixed_4x16384"] = {"keys_per_s": round(4 * 16384 / mixed_ms * 1e3, 1), "ms": round(mixed_ms, 3),
-                                   "launch": "one hipGraph, four concurrent branches"}
+                                   "launch": ("one persistent fused kernel (autotuned)" if all_pers else
+                                              "one hipGraph, four concurrent branches (autotuned)")}
+        # the same jobs as one launch of the persistent fused kernel
+        saved = {q_: ctx.get_config(q_) for q_ in (653, 761, 857, 1277)}
+        for q_ in saved:
+            ctx.set_config(q_, persistent=1, product_engine=1, lanes_per_key=2, group_size=32,
+                           inverse_share=2, use_graph=1)
+        ctx.batch_keygen_mixed(wl.SEED, jobs, check=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(5):
+            ctx.batch_keygen_mixed(wl.SEED, jobs, check=False)
+        e1.record()
+        torch.cuda.synchronize()
+        assert ctx.status() == 0
+        pm_ms = e0.elapsed_time(e1) / 5
+        extras["mixed_4x16384_persistent"] = {"keys_per_s": round(4 * 16384 / pm_ms * 1e3, 1), "ms": round(pm_ms, 3),
+                                              "launch": "one persistent fused kernel (G=32, W=2, 2 lanes per key)"}
+        for q_, c_ in saved.items():
+            ctx.set_config(q_, **c_)
+        # this workload (N keys of p) in the persistent fused form, at the
+        # autotuner's best persistent setting
+        pers = [r for r in (tuned or {}).get("table", []) if r.get("persistent")]
+        pcfg = {k: v for k, v in min(pers, key=lambda r: r["ms"]).items() if k != "ms"} if pers else \
+            {"group_size": 32, "inverse_share": 2, "lanes_per_key": 2, "persistent": 1}
+        saved = ctx.get_config(p)
+        ctx.set_config(p, use_graph=0, **pcfg)
+        ctx.batch_keygen(p, wl.SEED, 0, n, pk, sk, check=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(5):
+            ctx.batch_keygen(p, wl.SEED, 0, n, pk, sk, check=False)
+        e1.record()
+        torch.cuda.synchronize()
+        assert ctx.status() == 0
+        pf_ms = e0.elapsed_time(e1) / 5
+        extras["persistent_fused"] = {"keys_per_s": round(n / pf_ms * 1e3, 1), "ms": round(pf_ms, 3),
+                                      "config": {k: pcfg[k] for k in ("group_size", "inverse_share", "lanes_per_key")}}
+        ctx.set_config(p, **saved)
         # serving: Poisson arrivals, 70/20/10 % sntrup761/857/1277, device pools
         if args.serve_seconds > 0:
             from paper_2106_08759_amd import serve
@@ -361,7 +407,8 @@ def main():
                    "p": p, "q": prm.q, "w": prm.w, "n_keys": n, "group_size": cfg["group_size"],
                    "inverse_share": cfg["inverse_share"], "lanes_per_key": cfg["lanes_per_key"],
                    "product_engine": "int8 matrix cores" if cfg["product_engine"] == 1 else "v_dot2",
-                   "launch": ("one captured hipGraph per call (stages on one stream)" if cfg["use_graph"] else
+                   "launch": ("one persistent fused kernel per call" if cfg.get("persistent") else
+                              "one captured hipGraph per call (stages on one stream)" if cfg["use_graph"] else
                               "eager launches: prefix kernel on a side stream beside the R/3 stage")},
         "roofline": roofline,
         "stages": stage_fracs,
@@ -372,9 +419,11 @@ def main():
         out["autotune"] = {"config": tuned["config"], "use_graph": tuned.get("use_graph"),
                            "eager_ms": tuned.get("eager_ms"), "graph_ms": tuned.get("graph_ms"),
                            "cached": tuned["cached"],
-                           "table_ms": {"G%d/W%d/L%d/R%dx%dx%d" % (r["group_size"], r["inverse_share"], r["lanes_per_key"],
-                                                                   r["retry_passes"], r["retry_lanes_per_key"],
-                                                                   r["retry_parallel_attempts"]): r["ms"]
+                           "table_ms": {"%sG%d/W%d/L%d/R%dx%dx%d" % ("P:" if r.get("persistent") else "",
+                                                                     r["group_size"], r["inverse_share"],
+                                                                     r["lanes_per_key"], r["retry_passes"],
+                                                                     r["retry_lanes_per_key"],
+                                                                     r["retry_parallel_attempts"]): r["ms"]
                                         for r in tuned.get("table", [])}}
     if cb is not None:
         out["cpu_baseline"] = cb

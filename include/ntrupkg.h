@@ -55,6 +55,8 @@ extern "C" {
 #define NTRUP_ENOMEM (-12)  /* device allocation failed */
 #define NTRUP_EINVAL (-22)  /* bad parameter set, size, pointer or config */
 #define NTRUP_EFAULT (-14)  /* a group product was not a unit (cannot happen in a field) */
+#define NTRUP_ETIME (-62)   /* persistent form: an item's input was not ready within
+                               its bounded wait (about 0.1 s); outputs are invalid */
 
 #define NTRUP_MAX_ATTEMPTS 64
 
@@ -102,7 +104,16 @@ const char *ntrup_strerror(int code);
  *                        Toeplitz MFMA with two 7-bit limbs); both exact
  *   inverse_share        1, 2, 4 or 8 Montgomery groups (one wave each) that
  *                        share one R/q reciprocal (product_engine 1 only;
- *                        at most 4 for p = 1277)                            */
+ *                        at most 4 for p = 1277)
+ *   persistent           0: the stage pipeline above (one kernel per stage);
+ *                        1: one persistent fused kernel per call: sampling,
+ *                        R/3, prefix chains, shared reciprocals, retries and
+ *                        back-substitution of every job are items of one work
+ *                        list that resident waves drain in dependency order
+ *                        (requires product_engine 1 and lanes_per_key 2 or 4;
+ *                        retries use 8 lanes per key; a mixed call of up to 4
+ *                        jobs, all persistent, is one launch and takes the
+ *                        first job's lanes_per_key)                        */
 typedef struct {
     int group_size;
     int lanes_per_key;
@@ -112,6 +123,7 @@ typedef struct {
     int use_graph;
     int product_engine;
     int inverse_share;
+    int persistent;
 } ntrup_config;
 
 int ntrup_get_config(const ntrup_ctx *ctx, int p, ntrup_config *cfg);
@@ -152,13 +164,15 @@ int ntrup_ctx_status(ntrup_ctx *ctx, void *stream);
 /* Stage timing with HIP events recorded on the launch streams.  After
  * ntrup_ctx_timing_begin(ctx, m) the next m pipelines (one per job of a keygen
  * call; graph replay is bypassed meanwhile) record 6 events each, bounding
- * 5 stages: [0] Short sampler, [1] R/3 main pass, [2] R/3 retry and final
+ * the stages: [0] Short sampler, [1] R/3 main pass, [2] R/3 retry and final
  * passes, [3] prefix products and group reciprocals, [4] back-substitution,
- * h = g/(3f) and encoding.  With the matrix-core engine in an eager
- * single-job call, [3] runs on a side stream beside [1] and [4] is timed from
- * the later of its inputs.
+ * h = g/(3f) and encoding; [5] the persistent fused kernel (a persistent
+ * call, counted once per call, puts all of its time there and none in
+ * [0..4]).  With the matrix-core engine in an eager single-job call, [3]
+ * runs on a side stream beside [1] and [4] is timed from the later of its
+ * inputs.
  * ntrup_ctx_timing_end waits for them, writes the summed milliseconds per
- * stage to ms[0..4] (nstages >= 5), the number of pipelines timed to
+ * stage to ms[0..5] (nstages >= 6), the number of pipelines timed to
  * *npipelines, and switches timing off. */
 int ntrup_ctx_timing_begin(ntrup_ctx *ctx, int max_pipelines);
 int ntrup_ctx_timing_end(ntrup_ctx *ctx, double *ms, int nstages, int *npipelines);

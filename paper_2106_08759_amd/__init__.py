@@ -23,6 +23,7 @@ NTRUP_EAGAIN = -11
 NTRUP_ENOMEM = -12
 NTRUP_EINVAL = -22
 NTRUP_EFAULT = -14
+NTRUP_ETIME = -62
 
 
 class NtrupError(RuntimeError):
@@ -44,7 +45,8 @@ class _Config(ctypes.Structure):
     _fields_ = [("group_size", ctypes.c_int), ("lanes_per_key", ctypes.c_int),
                 ("retry_lanes_per_key", ctypes.c_int), ("retry_parallel_attempts", ctypes.c_int),
                 ("retry_passes", ctypes.c_int), ("use_graph", ctypes.c_int),
-                ("product_engine", ctypes.c_int), ("inverse_share", ctypes.c_int)]
+                ("product_engine", ctypes.c_int), ("inverse_share", ctypes.c_int),
+                ("persistent", ctypes.c_int)]
 
 
 _lib = None
@@ -173,14 +175,14 @@ class Context:
                 "retry_lanes_per_key": c.retry_lanes_per_key,
                 "retry_parallel_attempts": c.retry_parallel_attempts, "retry_passes": c.retry_passes,
                 "use_graph": c.use_graph, "product_engine": c.product_engine,
-                "inverse_share": c.inverse_share}
+                "inverse_share": c.inverse_share, "persistent": c.persistent}
 
     def set_config(self, p: int, **kw):
         cur = self.get_config(p)
         cur.update(kw)
         c = _Config(cur["group_size"], cur["lanes_per_key"], cur["retry_lanes_per_key"],
                     cur["retry_parallel_attempts"], cur["retry_passes"], cur["use_graph"],
-                    cur["product_engine"], cur["inverse_share"])
+                    cur["product_engine"], cur["inverse_share"], cur["persistent"])
         self._check(lib().ntrup_set_config(self._h, p, ctypes.byref(c)), "ntrup_set_config")
 
     def reserve(self, p: int, n: int):
@@ -189,7 +191,7 @@ class Context:
     def workspace_bytes(self) -> int:
         return lib().ntrup_ctx_workspace_bytes(self._h)
 
-    STAGES = ("sample_short", "r3_main", "r3_retry", "group_prefix", "group_back")
+    STAGES = ("sample_short", "r3_main", "r3_retry", "group_prefix", "group_back", "fused")
 
     def timing_begin(self, max_pipelines: int):
         self._check(lib().ntrup_ctx_timing_begin(self._h, max_pipelines), "timing_begin")

@@ -12,15 +12,19 @@ Knobs (see ``ntrup_config`` in include/ntrupkg.h):
                  lanes per key, g draws tried side by side per key, and the
                  number of compacted passes for the keys whose g was not
                  invertible (matters for p = 653, 1277, where the retry
-                 passes are latency-bound).
+                 passes are latency-bound);
+  persistent     the stage pipeline (0) or one persistent fused kernel per
+                 call (1).
 
 The group knobs (G, W) and the R/3 knobs act on different kernels, but in
 eager launches the prefix kernel runs beside the R/3 stage and the two compete
 for the same compute units, so the first phase times (G, W) jointly with the
 lanes per key of the R/3 main pass (PHASE1_LANES); the second phase then times
-every R/3 setting (lanes per key, retry knobs) with the chosen (G, W).  Each
-candidate runs in the launch form of the tuning mode (eager launches, or graph
-replay: one linear stream per job); mode "auto" then compares the two forms.
+every R/3 setting (lanes per key, retry knobs) with the chosen (G, W), and
+the persistent fused form (one kernel per call, ``persistent`` = 1) at the
+settings in PERSISTENT_CANDIDATES.  Each candidate runs in the launch form of
+the tuning mode (eager launches, or graph replay: one linear stream per job);
+mode "auto" then compares the two forms.
 The product tiles are fixed by p.
 Every candidate is timed on the real pipeline with HIP events on the launch
 stream; the winner per (device, p, N rounded up to a power of two) is cached
@@ -36,7 +40,9 @@ GROUP_SIZES = (8, 16, 32, 64, 128)
 SHARES = (1, 2, 4, 8)
 PHASE1_LANES = (2, 4)   # R/3 lanes per key timed jointly with (G, W)
 KNOBS = ("group_size", "inverse_share", "lanes_per_key", "retry_passes", "retry_lanes_per_key",
-         "retry_parallel_attempts")
+         "retry_parallel_attempts", "persistent")
+# (G, W, lanes per key) settings timed for the persistent fused form
+PERSISTENT_CANDIDATES = ((32, 2, 2), (32, 4, 2), (64, 2, 2), (32, 4, 4), (16, 4, 2))
 
 
 def cache_path() -> str:
@@ -97,8 +103,9 @@ MODES = ("auto", "eager", "graph")
 
 
 def _key(device_name: str, p: int, n: int, mode: str = "auto") -> str:
-    # v3: entries carry inverse_share and the launch form (eager / graph)
-    return "%s|p=%d|n<=%d|%s|v3" % (device_name, p, bucket(n), mode)
+    # v4: entries carry inverse_share, the launch form (eager / graph) and
+    # the kernel form (stage pipeline / persistent fused kernel)
+    return "%s|p=%d|n<=%d|%s|v4" % (device_name, p, bucket(n), mode)
 
 
 def load_cache(path: str | None = None) -> dict:
@@ -169,6 +176,7 @@ def tune(ctx, p: int, n: int, seed: bytes | None = None, reps: int = 3, force: b
     ctx.reserve(p, n)
     base = ctx.get_config(p)
     cur = {k: base[k] for k in KNOBS}
+    cur["persistent"] = 0
     ctx.set_config(p, product_engine=1)
     table = []
     # phase 1: the group stage, jointly with the R/3 main pass's lanes per key
@@ -182,6 +190,15 @@ def tune(ctx, p: int, n: int, seed: bytes | None = None, reps: int = 3, force: b
     for rc in r3_candidates(p):
         cfg = dict(cur, **rc)
         table.append(dict(cfg, ms=round(time_config(ctx, p, n, cfg, seed, reps, pk, sk, ug), 4)))
+    best = min(table, key=lambda r: r["ms"])
+    # phase 2b: the persistent fused form (one kernel per call) at a few
+    # (G, W, lanes per key) settings, with the chosen retry knobs
+    for g_, w_, l_ in PERSISTENT_CANDIDATES:
+        if (g_, w_) not in {(c["group_size"], c["inverse_share"]) for c in group_candidates(p, n)}:
+            continue
+        pc = dict(best, group_size=g_, inverse_share=w_, lanes_per_key=l_, persistent=1)
+        pc = {k: pc[k] for k in KNOBS}
+        table.append(dict(pc, ms=round(time_config(ctx, p, n, pc, seed, reps, pk, sk, ug), 4)))
     best = min(table, key=lambda r: r["ms"])
     cfg = {k: best[k] for k in KNOBS}
     # phase 3 (auto): eager launches (stage overlap) or graph replay (one

@@ -4,12 +4,14 @@
 #include <stdint.h>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
 #include <vector>
 
 #include "../../include/ntrupkg.h"
 #include "ntrup_kernels.h"
 #include "ntrup_keygen.h"
+#include "ntrup_persist.h"
 
 using namespace ntrup;
 
@@ -36,12 +38,17 @@ struct Ws {
     uint8_t* attempts;
     int* lists[2];
     int* counters;
+    int16_t* qrow;     // persistent form: partial products of the shared reciprocals
+    int* flags;        // persistent form: dependency counters
 };
+
+// Dependency counters of a persistent job of n keys (every G >= 1).
+size_t flag_ints(size_t n) { return 4 * n + 64; }
 
 size_t ws_bytes(int p, size_t n) {
     const size_t wn = (size_t)ceil_div(p, 32);
     return align256(n * p) + 2 * align256(wn * 2 * n * 4) + 2 * align256(n * p * 2) + align256(n) +
-           2 * align256(n * 4) + align256(kCounterInts * 4);
+           2 * align256(n * 4) + align256(kCounterInts * 4) + align256(n * p * 2) + align256(flag_ints(n) * 4);
 }
 
 Ws carve(void* base, int p, size_t n) {
@@ -56,7 +63,9 @@ Ws carve(void* base, int p, size_t n) {
     w.attempts = (uint8_t*)c;    c += align256(n);
     w.lists[0] = (int*)c;        c += align256(n * 4);
     w.lists[1] = (int*)c;        c += align256(n * 4);
-    w.counters = (int*)c;
+    w.counters = (int*)c;        c += align256(kCounterInts * 4);
+    w.qrow = (int16_t*)c;        c += align256(n * p * 2);
+    w.flags = (int*)c;
     return w;
 }
 
@@ -247,6 +256,7 @@ int enqueue_keygen(ntrup_ctx* ctx, const ntrup_config& cfg, const Seed& seed, ui
     mark(2, ss);
     if (side) NTRUP_HIP(ctx, hipEventRecord(ctx->side_join, ss));
     R3Args a;
+    memset(&a, 0, sizeof a);
     a.seed = seed;
     a.first_index = first_index;
     a.n = (int)n;
@@ -293,6 +303,115 @@ int enqueue_dispatch(ntrup_ctx* ctx, int p, const ntrup_config& cfg, const Seed&
     return NTRUP_EINVAL;
 }
 
+// ---------------------------------------------------------------------------
+// Persistent form: every stage of every job as items of one work list, run by
+// one launch of keygen_persistent_kernel (see ntrup_persist.h).
+// ---------------------------------------------------------------------------
+template <int LPK, int... Ps>
+int launch_persistent(ntrup_ctx* ctx, const PLaunch& pl, hipStream_t st) {
+    auto kernel = keygen_persistent_kernel<LPK, Ps...>;
+    int per_cu = 0, cus = 0;
+    NTRUP_HIP(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 64, 0));
+    NTRUP_HIP(ctx, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device));
+    const int grid = std::max(1, std::min(pl.total, std::max(1, per_cu) * cus));
+    hipLaunchKernelGGL(kernel, dim3(grid), dim3(64), 0, st, pl);
+    NTRUP_HIP(ctx, hipGetLastError());
+    return 0;
+}
+
+template <int LPK>
+int launch_persistent_p(ntrup_ctx* ctx, int p, bool mixed, const PLaunch& pl, hipStream_t st) {
+    if (mixed) return launch_persistent<LPK, 653, 761, 857, 1277>(ctx, pl, st);
+    switch (p) {
+        case 653: return launch_persistent<LPK, 653>(ctx, pl, st);
+        case 761: return launch_persistent<LPK, 761>(ctx, pl, st);
+        case 857: return launch_persistent<LPK, 857>(ctx, pl, st);
+        case 1277: return launch_persistent<LPK, 1277>(ctx, pl, st);
+    }
+    return NTRUP_EINVAL;
+}
+
+// The work list of `jobs` (each with cfg.persistent set; the R/3 lanes per
+// key of the first job apply to all): stage counts, dependency counters in
+// each job's workspace (zeroed here), segments in the order S | R and C
+// interleaved in 8 chunks | Q | T | B, job by job within each stage.
+int enqueue_persistent(ntrup_ctx* ctx, const Seed& sd, const std::vector<JobDesc>& jobs, hipStream_t st) {
+    if (jobs.empty() || jobs.size() > (size_t)kPMaxJobs) return NTRUP_EINVAL;
+    PLaunch pl;
+    memset(&pl, 0, sizeof pl);
+    pl.seed = sd;
+    pl.njobs = (int)jobs.size();
+    const int lpk = jobs[0].cfg.lanes_per_key;
+    bool mixed = false;
+    for (size_t j = 0; j < jobs.size(); j++) {
+        const JobDesc& jd = jobs[j];
+        mixed = mixed || jd.p != jobs[0].p;
+        const Ws w = carve((char*)ctx->ws + jd.ws_off, jd.p, jd.n);
+        PJob& J = pl.jobs[j];
+        const int n = (int)jd.n;
+        J.p = jd.p;
+        J.n = n;
+        J.G = jd.cfg.group_size;
+        J.W = jd.cfg.inverse_share;
+        J.ns = (int)grid_for(n, kPKeysPerS);
+        J.nr = (int)grid_for(n, 64 / lpk);
+        J.ngroups = (int)grid_for(n, J.G);
+        J.nq = (int)grid_for(J.ngroups, J.W);
+        J.nt = std::min(64, std::max(1, (int)grid_for(n, 512)));
+        J.retry_spec = jd.cfg.retry_parallel_attempts;
+        J.first_index = jd.first_index;
+        J.g.n = n;
+        J.g.G = J.G;
+        J.g.f_rows = w.f_rows;
+        J.g.gbits = w.gbits;
+        J.g.ibits = w.ibits;
+        J.g.bscr = w.bscr;
+        J.g.pk = jd.pk;
+        J.g.sk = jd.sk;
+        J.g.err = w.counters + 32;
+        J.g.a_in = nullptr;
+        J.g.c_out = nullptr;
+        J.tinv = w.tinv;
+        J.qrow = w.qrow;
+        J.attempts = w.attempts;
+        J.list = w.lists[0];
+        J.list_count = w.counters;
+        J.sdone = w.flags;
+        J.cdone = J.sdone + J.ns;
+        J.qdone = J.cdone + J.ngroups;
+        J.kfinal = J.qdone + J.nq;
+        J.rcount = J.kfinal + J.ngroups;
+        const int used = J.ns + 2 * J.ngroups + J.nq + 2;   // rcount, then the list's next index (job 0)
+        hipLaunchKernelGGL(zero_ints_kernel, dim3(1), dim3(64), 0, st, w.counters, kCounterInts);
+        hipLaunchKernelGGL(zero_ints_kernel, dim3(grid_for(used, 256)), dim3(256), 0, st, w.flags, used);
+        if (j == 0) pl.next = J.rcount + 1;
+    }
+    auto add = [&](int job, int stage, int local0, int count) {
+        if (count <= 0) return;
+        PSeg& g = pl.segs[pl.nsegs++];
+        g.first = pl.total;
+        g.local0 = local0;
+        g.count = count;
+        g.jobstage = job * 8 + stage;
+        pl.total += count;
+    };
+    constexpr int kChunks = 8;
+    static_assert(kPMaxJobs * (4 + 2 * kChunks) <= kPMaxSegs, "segment table");
+    for (int j = 0; j < pl.njobs; j++) add(j, PS_SAMPLE, 0, pl.jobs[j].ns);
+    for (int c = 0; c < kChunks; c++)
+        for (int j = 0; j < pl.njobs; j++) {
+            const PJob& J = pl.jobs[j];
+            add(j, PS_R3, J.nr * c / kChunks, J.nr * (c + 1) / kChunks - J.nr * c / kChunks);
+            add(j, PS_CHAIN, J.ngroups * c / kChunks, J.ngroups * (c + 1) / kChunks - J.ngroups * c / kChunks);
+        }
+    for (int j = 0; j < pl.njobs; j++) add(j, PS_RECIP, 0, pl.jobs[j].nq);
+    for (int j = 0; j < pl.njobs; j++) add(j, PS_RETRY, 0, pl.jobs[j].nt);
+    for (int j = 0; j < pl.njobs; j++) add(j, PS_BACK, 0, pl.jobs[j].ngroups);
+    NTRUP_HIP(ctx, hipGetLastError());
+    return lpk == 2 ? launch_persistent_p<2>(ctx, jobs[0].p, mixed, pl, st)
+                    : launch_persistent_p<4>(ctx, jobs[0].p, mixed, pl, st);
+}
+
 bool valid_config(const ntrup_config& c) {
     auto lpk_ok = [](int l) { return l == 1 || l == 2 || l == 4 || l == 8; };
     return c.group_size >= 1 && c.group_size <= 1024 && lpk_ok(c.lanes_per_key) &&
@@ -300,7 +419,9 @@ bool valid_config(const ntrup_config& c) {
            c.retry_lanes_per_key * c.retry_parallel_attempts <= 64 && c.retry_passes >= 0 &&
            c.retry_passes <= 8 && (c.use_graph == 0 || c.use_graph == 1) &&
            (c.product_engine == 0 || c.product_engine == 1) &&
-           (c.inverse_share == 1 || c.inverse_share == 2 || c.inverse_share == 4 || c.inverse_share == 8);
+           (c.inverse_share == 1 || c.inverse_share == 2 || c.inverse_share == 4 || c.inverse_share == 8) &&
+           (c.persistent == 0 ||
+            (c.persistent == 1 && c.product_engine == 1 && (c.lanes_per_key == 2 || c.lanes_per_key == 4)));
 }
 
 int check_job(int p, size_t n, const void* pk, const void* sk) {
@@ -357,6 +478,7 @@ const char* ntrup_strerror(int code) {
         case NTRUP_ENOMEM: return "device allocation failed";
         case NTRUP_EINVAL: return "invalid argument";
         case NTRUP_EFAULT: return "group product not a unit";
+        case NTRUP_ETIME: return "a persistent-kernel item waited too long for its inputs";
     }
     return "unknown error";
 }
@@ -369,7 +491,7 @@ int ntrup_ctx_create(ntrup_ctx** out, int device) {
     ntrup_ctx* ctx = new (std::nothrow) ntrup_ctx();
     if (!ctx) return NTRUP_ENOMEM;
     ctx->device = device;
-    for (int i = 0; i < 4; i++) ctx->cfg[i] = ntrup_config{32, 2, 8, 4, 1, 1, 1, 4};
+    for (int i = 0; i < 4; i++) ctx->cfg[i] = ntrup_config{32, 2, 8, 4, 1, 1, 1, 4, 0};
     bool ok = set_device(ctx) == 0 && hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking) == hipSuccess;
     for (int i = 0; ok && i < kJobStreams; i++)
         ok = hipStreamCreateWithFlags(&ctx->job_streams[i], hipStreamNonBlocking) == hipSuccess;
@@ -471,6 +593,17 @@ namespace {
 // side_ok: a single job may fork its side stream (eager launches only: a
 // captured graph stays one linear stream per job).
 int enqueue_jobs(ntrup_ctx* ctx, const Seed& sd, const std::vector<JobDesc>& jobs, hipStream_t st, bool side_ok) {
+    bool persistent = jobs.size() <= (size_t)kPMaxJobs;
+    for (const JobDesc& j : jobs) persistent = persistent && j.cfg.persistent;
+    if (persistent) {
+        // one launch for every job; stage events: all of the call in "fused"
+        for (int b = 0; b < kStages; b++)
+            if (hipEvent_t ev = stage_event(ctx, b)) (void)hipEventRecord(ev, st);
+        int r = enqueue_persistent(ctx, sd, jobs, st);
+        if (hipEvent_t ev = stage_event(ctx, kStages)) (void)hipEventRecord(ev, st);
+        if (ctx->t_used < ctx->t_max) ctx->t_side[ctx->t_used++] = 2;
+        return r;
+    }
     if (jobs.size() == 1) {
         const JobDesc& j = jobs[0];
         return enqueue_dispatch(ctx, j.p, j.cfg, sd, j.first_index, j.n, j.pk, j.sk,
@@ -563,7 +696,7 @@ int ntrup_ctx_timing_begin(ntrup_ctx* ctx, int max_pipelines) {
 }
 
 int ntrup_ctx_timing_end(ntrup_ctx* ctx, double* ms, int nstages, int* npipelines) {
-    if (!ctx || !ms || nstages < kStages) return NTRUP_EINVAL;
+    if (!ctx || !ms || nstages < kStages + 1) return NTRUP_EINVAL;
     if (int r = set_device(ctx)) return r;
     for (int s = 0; s < nstages; s++) ms[s] = 0.0;
     for (int c = 0; c < ctx->t_used; c++) {
@@ -574,6 +707,10 @@ int ntrup_ctx_timing_end(ntrup_ctx* ctx, double* ms, int nstages, int* npipeline
         float t[kStages + 1][kStages + 1] = {};
         for (int i = 0; i <= kStages; i++)
             for (int j = i + 1; j <= kStages; j++) NTRUP_HIP(ctx, hipEventElapsedTime(&t[i][j], ev[i], ev[j]));
+        if (ctx->t_side[c] == 2) {
+            ms[kStages] += t[0][kStages];                     // the persistent fused kernel
+            continue;
+        }
         ms[0] += t[0][1];                                     // sample_short
         ms[3] += t[1][2];                                     // group prefix + reciprocal
         ms[2] += t[3][4];                                     // R/3 retries
@@ -601,6 +738,7 @@ int ntrup_ctx_status(ntrup_ctx* ctx, void* stream) {
         NTRUP_HIP(ctx, hipMemcpy(&v, e, sizeof v, hipMemcpyDeviceToHost));
         bits |= v;
     }
+    if (bits & 4) return NTRUP_ETIME;
     if (bits & 2) return NTRUP_EFAULT;
     if (bits & 1) return NTRUP_EAGAIN;
     return 0;

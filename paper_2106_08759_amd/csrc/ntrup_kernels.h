@@ -77,19 +77,17 @@ __device__ __forceinline__ void bitonic_sort_wave(uint32_t (&L)[EPL], int lane) 
     }
 }
 
+// f of one key (key index `index`), written to `row`; one wave.
 template <int P>
-__global__ __launch_bounds__(256) void sample_short_kernel(Seed seed, uint64_t first_index, int n,
-                                                           int8_t* __restrict__ f_rows) {
+__device__ __forceinline__ void sample_short_key(const Seed& seed, uint64_t index, int8_t* __restrict__ row) {
     constexpr int W = Param<P>::w;
     constexpr int EPL = ShortShape<P>::EPL;
     const int lane = lane_id();
-    const int key = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    if (key >= n) return;  // whole wave
     uint32_t L[EPL];
 #pragma unroll
     for (int b = 0; b < EPL / 16; b++) {
         uint32_t r[16];
-        chacha_block(seed, first_index + (uint64_t)key, P, 0, (uint32_t)(lane * (EPL / 16) + b), r);
+        chacha_block(seed, index, P, 0, (uint32_t)(lane * (EPL / 16) + b), r);
 #pragma unroll
         for (int e = 0; e < 16; e++) L[16 * b + e] = r[e];
     }
@@ -100,12 +98,19 @@ __global__ __launch_bounds__(256) void sample_short_kernel(Seed seed, uint64_t f
         L[e] = (i < P) ? ((L[e] & ~3u) | v) : 0xFFFFFFFFu;
     }
     bitonic_sort_wave<EPL>(L, lane);
-    int8_t* row = f_rows + (size_t)key * P;
 #pragma unroll
     for (int e = 0; e < EPL; e++) {
         const int i = lane * EPL + e;
         if (i < P) row[i] = (int8_t)((int)(L[e] & 3u) - 1);
     }
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void sample_short_kernel(Seed seed, uint64_t first_index, int n,
+                                                           int8_t* __restrict__ f_rows) {
+    const int key = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (key >= n) return;  // whole wave
+    sample_short_key<P>(seed, first_index + (uint64_t)key, f_rows + (size_t)key * P);
 }
 
 // ----------------------------------------------------------------------------
@@ -156,6 +161,8 @@ struct R3Args {
     uint32_t* ibits;        // [WN][2][n]
     int* err;               // |= 1 when a key exhausts kMaxAttempts
     const int8_t* g_in;     // test entry: explicit g rows [n][p], one round, no sampling
+    int* kfinal;            // optional: kfinal[key / G] += 1 once a key's result is final
+    int G;
 };
 
 // A wave holds 64/LPK lane groups; with spec = A, consecutive runs of A
@@ -164,18 +171,27 @@ struct R3Args {
 // g a one-at-a-time resampling loop would accept -- so the outputs do not
 // depend on A.  Keys whose A attempts all fail move on by A attempts.
 template <int P, int LPK>
-__global__ __launch_bounds__(64) void r3_kernel(R3Args args) {
+struct R3Lds {
+    using S = R3Shape<P, LPK>;
+    uint32_t nat[S::KPW][2][S::WT];   // natural-order g words of each lane group
+    uint32_t vst[S::KPW][2][S::WT];   // divstep outputs, for the reversal
+};
+
+// One wave's keys (wave slot ws: keys or list entries ws * KPW/A ...); a
+// wave-sized block (the barriers are wave barriers).
+template <int P, int LPK>
+__device__ __forceinline__ void r3_wave(const R3Args& args, int ws, R3Lds<P, LPK>& lds) {
     using S = R3Shape<P, LPK>;
     constexpr int W2 = S::W2;
-    __shared__ uint32_t nat[S::KPW][2][S::WT];
-    __shared__ uint32_t vst[S::KPW][2][S::WT];
+    auto& nat = lds.nat;
+    auto& vst = lds.vst;
     const int lane = lane_id();
     const int A = args.spec;
     const int gi = lane / LPK;            // lane group
     const int a = gi % A;                 // which of the key's side-by-side attempts
     const int h = lane & (LPK - 1);
     const int kw = gi / A;                // key slot in the wave
-    const int slot = blockIdx.x * (S::KPW / A) + kw;
+    const int slot = ws * (S::KPW / A) + kw;
     int key = -1, base = 0;
     if (args.list_in) {
         if (slot < *args.count_in) {
@@ -268,6 +284,17 @@ __global__ __launch_bounds__(64) void r3_kernel(R3Args args) {
     } else if (pend) {
         atomicOr(args.err, 1);
     }
+    if (args.kfinal) {
+        // every lane's outputs visible before the group counters move
+        __threadfence();
+        if (key >= 0 && done && h == 0 && a == 0) atomicAdd(&args.kfinal[key / args.G], 1);
+    }
+}
+
+template <int P, int LPK>
+__global__ __launch_bounds__(64) void r3_kernel(R3Args args) {
+    __shared__ R3Lds<P, LPK> lds;
+    r3_wave<P, LPK>(args, (int)blockIdx.x, lds);
 }
 
 // ----------------------------------------------------------------------------

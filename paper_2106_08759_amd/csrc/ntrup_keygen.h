@@ -275,28 +275,12 @@ struct KgPrefixWave {
     __attribute__((aligned(16))) int16_t Cb[RqShape<P>::JP];
 };
 
-// Steps 1 and 2: prefix products of each wave's group (rows b_i to HBM), then
-// wave 0 alone inverts the W group products with one reciprocal and writes
-// t = 1/P_w of every group to tinv (int16 [groups][p]).  The other waves end
-// after the prefix barrier, so their registers serve other work (the R/3
-// stage runs beside this kernel) while wave 0 runs the reciprocal.
-template <int P, int W>
-__global__ __launch_bounds__(64 * W, (P < 800 ? 2 : 1)) void keygen_prefix_kernel(GroupArgs args, int16_t* tinv) {
+// Step 1 for one group (keys kw0 .. kw0+gsz-1): prefix rows b_i to HBM, the
+// group product b_gsz left in L.Bb (1 for an empty group).  One wave.
+template <int P>
+__device__ __forceinline__ void kg_prefix_chain(const GroupArgs& args, int kw0, int gsz, KgPrefixWave<P>& L) {
     using S = MfShape<P>;
-    __shared__ KgPrefixWave<P> LW[W];
-    const int wave = (int)(threadIdx.x >> 6);
-    KgPrefixWave<P>& L = LW[wave];
-    const int n = args.n;
-    const int G = args.G;
-    const int group = blockIdx.x * W + wave;
-    const int kw0 = group * G;
-    const int gsz = max(0, min(G, n - kw0));
     int16_t* bscr = args.bscr;
-    // this kernel's latency (a chain of products, then one long divstep
-    // reciprocal on one wave) bounds the pipeline while the R/3 stage runs
-    // beside it: its waves take issue priority over the R/3 waves
-    __builtin_amdgcn_s_setprio(3);
-
     kg_zero<P>(L.TL, S::TLEN);
     kg_zero<P>(L.TH, S::TLEN);
     kg_zero<P>(L.HS, S::HLEN);
@@ -317,6 +301,29 @@ __global__ __launch_bounds__(64 * W, (P < 800 ? 2 : 1)) void keygen_prefix_kerne
     } else {
         kg_set_one<P>(L.Bb);
     }
+}
+
+// Steps 1 and 2: prefix products of each wave's group (rows b_i to HBM), then
+// wave 0 alone inverts the W group products with one reciprocal and writes
+// t = 1/P_w of every group to tinv (int16 [groups][p]).  The other waves end
+// after the prefix barrier, so their registers serve other work (the R/3
+// stage runs beside this kernel) while wave 0 runs the reciprocal.
+template <int P, int W>
+__global__ __launch_bounds__(64 * W, (P < 800 ? 2 : 1)) void keygen_prefix_kernel(GroupArgs args, int16_t* tinv) {
+    __shared__ KgPrefixWave<P> LW[W];
+    const int wave = (int)(threadIdx.x >> 6);
+    KgPrefixWave<P>& L = LW[wave];
+    const int n = args.n;
+    const int G = args.G;
+    const int group = blockIdx.x * W + wave;
+    const int kw0 = group * G;
+    const int gsz = max(0, min(G, n - kw0));
+    // this kernel's latency (a chain of products, then one long divstep
+    // reciprocal on one wave) bounds the pipeline while the R/3 stage runs
+    // beside it: its waves take issue priority over the R/3 waves
+    __builtin_amdgcn_s_setprio(3);
+
+    kg_prefix_chain<P>(args, kw0, gsz, L);
     __syncthreads();
     if (wave != 0) return;   // no barrier follows: wave 0 finishes alone
 
@@ -360,15 +367,57 @@ __global__ __launch_bounds__(64 * W, (P < 800 ? 2 : 1)) void keygen_prefix_kerne
     }
 }
 
-// Step 3: back-substitution from t = 1/P (tinv row of the group), h = g c and
-// encoding.  One wave per group.
+// Step 2 with the group products in HBM: groups grp0 .. grp0+wn-1 hold P_w
+// in rows of tinv ([groups][p]); on exit those rows hold 1/P_w.  qrow
+// ([groups][p]) keeps the partial products Q_0 .. Q_{wn-2}.  One wave.
 template <int P>
-__global__ __launch_bounds__(64, (P < 800 ? 2 : 1)) void keygen_back_kernel(GroupArgs args, const int16_t* tinv) {
+__device__ __forceinline__ void kg_shared_recip_rows(const GroupArgs& args, int grp0, int wn, int16_t* tinv, int16_t* qrow,
+                                     KgPrefixWave<P>& L) {
+    const int lane = lane_id();
+    int16_t* P0 = tinv + (size_t)grp0 * P;
+    for (int j = lane; j < P; j += 64) {
+        const int16_t v = P0[j];
+        L.Cb[j] = v;                                   // Q_0 = P_0
+        qrow[(size_t)grp0 * P + j] = v;
+    }
+    for (int w = 1; w < wn; w++) {
+        wave_sync();
+        build_toeplitz<P>(L.Cb, L.TL, L.TH);                            // Q_{w-1}
+        build_hankel<P>(tinv + (size_t)(grp0 + w) * P, L.HL, L.HH);     // P_w
+        wave_sync();
+        mfma_mul<P, true>(L.TL, L.TH, L.HL, L.HH, L.Cb, nullptr, nullptr,
+                          w + 1 < wn ? qrow + (size_t)(grp0 + w) * P : nullptr);   // Q_w
+    }
+    wave_sync();
+    const int ok = recip_wave<P>(L.Cb, L.Bb, L.ST);                      // T = 1/Q_{wn-1}
+    if (!ok && lane == 0) atomicOr(args.err, 2);
+    __threadfence();   // the qrow rows this wave wrote are read back below
+    for (int w = wn - 1; w >= 1; w--) {
+        wave_sync();
+        build_toeplitz<P>(L.Bb, L.TL, L.TH);                            // T
+        build_hankel<P>(tinv + (size_t)(grp0 + w) * P, L.HL, L.HH);     // P_w
+        wave_sync();
+        mfma_mul<P, true>(L.TL, L.TH, L.HL, L.HH, L.Cb, nullptr, nullptr, nullptr);   // T P_w
+        wave_sync();
+        build_hankel<P>(qrow + (size_t)(grp0 + w - 1) * P, L.HL, L.HH); // Q_{w-1}
+        wave_sync();
+        mfma_mul<P, true>(L.TL, L.TH, L.HL, L.HH, nullptr, nullptr, nullptr,
+                          tinv + (size_t)(grp0 + w) * P);                // 1/P_w over P_w
+        wave_sync();
+        kg_copy<P>(L.Cb, L.Bb);                                          // T <- T P_w
+    }
+    wave_sync();
+    for (int j = lane; j < P; j += 64) P0[j] = L.Bb[j];                  // 1/P_0 = T
+}
+
+// Step 3: back-substitution from t = 1/P (row trow of the group's
+// reciprocal), h = g c and encoding, for group `group`.  One wave.
+template <int P>
+__device__ __forceinline__ void kg_back_group(const GroupArgs& args, int group, const int16_t* trow, KgWave<P>& L) {
     using S = MfShape<P>;
-    __shared__ KgWave<P> L;
     const int n = args.n;
     const int G = args.G;
-    const int kw0 = blockIdx.x * G;
+    const int kw0 = group * G;
     const int gsz = max(0, min(G, n - kw0));
     if (gsz <= 0) return;
     kg_zero<P>(L.UL, S::TLEN);
@@ -381,7 +430,7 @@ __global__ __launch_bounds__(64, (P < 800 ? 2 : 1)) void keygen_back_kernel(Grou
     kg_load_f<P>(args.f_rows, kw0 + gsz - 1, ra);
     if (gsz >= 2) kg_load_b<P>(args.bscr, kw0 + gsz - 2, ra);
     kg_load_bits<P>(args.gbits, args.ibits, n, kw0 + gsz - 1, ra);
-    for (int j = lane_id(); j < P; j += 64) L.Bb[j] = tinv[(size_t)blockIdx.x * P + j];
+    for (int j = lane_id(); j < P; j += 64) L.Bb[j] = trow[j];
     wave_sync();
     build_toeplitz<P>(L.Bb, L.TL, L.TH);
     // two steps per trip so that the operand register sets alternate at
@@ -390,6 +439,13 @@ __global__ __launch_bounds__(64, (P < 800 ? 2 : 1)) void keygen_back_kernel(Grou
         kg_back_step<P>(args, L, kw0, i, ra, rb);
         if (i >= 2) kg_back_step<P>(args, L, kw0, i - 1, rb, ra);
     }
+}
+
+// Step 3 as a kernel: one wave per group.
+template <int P>
+__global__ __launch_bounds__(64, (P < 800 ? 2 : 1)) void keygen_back_kernel(GroupArgs args, const int16_t* tinv) {
+    __shared__ KgWave<P> L;
+    kg_back_group<P>(args, (int)blockIdx.x, tinv + (size_t)blockIdx.x * P, L);
 }
 
 }  // namespace ntrup

@@ -48,3 +48,10 @@ def test_params_and_errors_without_gpu(lib):
     assert lib.ntrup_batch_keygen(None, 761, bytes(32), 0, 1, 1, 1, None) == nk.NTRUP_EINVAL
     assert lib.ntrup_ctx_create(None, 0) == nk.NTRUP_EINVAL
     assert lib.ntrup_strerror(nk.NTRUP_EAGAIN).decode().startswith("no invertible")
+
+
+def test_persistent_timeout_code_has_a_message():
+    import paper_2106_08759_amd as nk
+    lib = nk.lib()
+    assert nk.NTRUP_ETIME == -62
+    assert "waited too long" in lib.ntrup_strerror(nk.NTRUP_ETIME).decode()

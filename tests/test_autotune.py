@@ -46,3 +46,9 @@ def test_phase1_times_group_knobs_with_both_lane_counts():
     pairs = [(x["group_size"], x["inverse_share"]) for x in c]
     assert len(pairs) == len(autotune.PHASE1_LANES) * len(autotune.group_candidates(761, 65536))
     assert (32, 8) in pairs and (64, 2) in pairs
+
+
+def test_persistent_form_is_a_knob():
+    assert "persistent" in autotune.KNOBS
+    for g, w, l in autotune.PERSISTENT_CANDIDATES:
+        assert l in (2, 4) and w in autotune.SHARES and g in autotune.GROUP_SIZES
