@@ -113,7 +113,18 @@ const char *ntrup_strerror(int code);
  *                        (requires product_engine 1 and lanes_per_key 2 or 4;
  *                        retries use 8 lanes per key; a mixed call of up to 4
  *                        jobs, all persistent, is one launch and takes the
- *                        first job's lanes_per_key)                        */
+ *                        first job's lanes_per_key)
+ *   r3_batch             0: one divstep reciprocal in R/3 per key; 1: the
+ *                        reciprocals of each Montgomery group of g's batched
+ *                        over R/3 as in Algorithm 1 (screen of each g against
+ *                        the small irreducible factors of x^p - x - 1 mod 3,
+ *                        prefix products on the matrix cores, one divstep
+ *                        reciprocal per group, back-substitution; a group
+ *                        whose product is not a unit falls back to per-key
+ *                        divsteps).  Same keys either way.  Requires
+ *                        product_engine 1 and persistent 0.  2: the same
+ *                        without the screen, so that every group holding a
+ *                        non-unit g takes the fallback (for its tests).    */
 typedef struct {
     int group_size;
     int lanes_per_key;
@@ -124,6 +135,7 @@ typedef struct {
     int product_engine;
     int inverse_share;
     int persistent;
+    int r3_batch;
 } ntrup_config;
 
 int ntrup_get_config(const ntrup_ctx *ctx, int p, ntrup_config *cfg);
@@ -186,6 +198,11 @@ int ntrup_ctx_timing_end(ntrup_ctx *ctx, double *ms, int nstages, int *npipeline
  * the context's product_engine for p. */
 int ntrup_op_mul_rq(ntrup_ctx *ctx, int p, const int16_t *a, const int16_t *b, int16_t *c, size_t n,
                     int small_a, void *stream);
+
+/* c = a * b in R/3 (Section 2.1), n rows of p int8 coefficients in {-1, 0, 1}
+   (device pointers), on the int8 matrix cores with the reduction mod 3: the
+   product of the batched R/3 reciprocals. */
+int ntrup_op_mul_r3(ntrup_ctx *ctx, int p, const int8_t *a, const int8_t *b, int8_t *c, size_t n, void *stream);
 
 /* out = 1/a in R/q by divsteps; ok[i] = 1 iff a_i is a unit. */
 int ntrup_op_recip_rq(ntrup_ctx *ctx, int p, const int16_t *a, int16_t *out, int32_t *ok, size_t n,

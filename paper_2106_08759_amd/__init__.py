@@ -46,7 +46,7 @@ class _Config(ctypes.Structure):
                 ("retry_lanes_per_key", ctypes.c_int), ("retry_parallel_attempts", ctypes.c_int),
                 ("retry_passes", ctypes.c_int), ("use_graph", ctypes.c_int),
                 ("product_engine", ctypes.c_int), ("inverse_share", ctypes.c_int),
-                ("persistent", ctypes.c_int)]
+                ("persistent", ctypes.c_int), ("r3_batch", ctypes.c_int)]
 
 
 _lib = None
@@ -80,6 +80,7 @@ def lib() -> ctypes.CDLL:
         "ntrup_ctx_timing_begin": (i32, [vp, i32]),
         "ntrup_ctx_timing_end": (i32, [vp, ctypes.POINTER(ctypes.c_double), i32, ctypes.POINTER(i32)]),
         "ntrup_op_mul_rq": (i32, [vp, i32, vp, vp, vp, sz, i32, vp]),
+        "ntrup_op_mul_r3": (i32, [vp, i32, vp, vp, vp, sz, vp]),
         "ntrup_op_recip_rq": (i32, [vp, i32, vp, vp, vp, sz, vp]),
         "ntrup_op_recip_r3": (i32, [vp, i32, vp, vp, vp, sz, vp]),
         "ntrup_op_batch_inv_rq": (i32, [vp, i32, vp, vp, sz, sz, vp]),
@@ -175,14 +176,14 @@ class Context:
                 "retry_lanes_per_key": c.retry_lanes_per_key,
                 "retry_parallel_attempts": c.retry_parallel_attempts, "retry_passes": c.retry_passes,
                 "use_graph": c.use_graph, "product_engine": c.product_engine,
-                "inverse_share": c.inverse_share, "persistent": c.persistent}
+                "inverse_share": c.inverse_share, "persistent": c.persistent, "r3_batch": c.r3_batch}
 
     def set_config(self, p: int, **kw):
         cur = self.get_config(p)
         cur.update(kw)
         c = _Config(cur["group_size"], cur["lanes_per_key"], cur["retry_lanes_per_key"],
                     cur["retry_parallel_attempts"], cur["retry_passes"], cur["use_graph"],
-                    cur["product_engine"], cur["inverse_share"], cur["persistent"])
+                    cur["product_engine"], cur["inverse_share"], cur["persistent"], cur["r3_batch"])
         self._check(lib().ntrup_set_config(self._h, p, ctypes.byref(c)), "ntrup_set_config")
 
     def reserve(self, p: int, n: int):
@@ -249,6 +250,13 @@ class Context:
         c = self._empty((n, p), self._torch.int16)
         self._check(lib().ntrup_op_mul_rq(self._h, p, _ptr(a), _ptr(b), _ptr(c), n, int(small_a),
                                           _stream(stream)), "op_mul_rq")
+        return c
+
+    def mul_r3(self, p: int, a, b, stream=None):
+        """c = a * b in R/3 for int8 rows with coefficients in {-1, 0, 1}."""
+        n = a.shape[0]
+        c = self._empty((n, p), self._torch.int8)
+        self._check(lib().ntrup_op_mul_r3(self._h, p, _ptr(a), _ptr(b), _ptr(c), n, _stream(stream)), "op_mul_r3")
         return c
 
     def recip_rq(self, p: int, a, stream=None):

@@ -12,6 +12,7 @@
 #include "ntrup_kernels.h"
 #include "ntrup_keygen.h"
 #include "ntrup_persist.h"
+#include "ntrup_r3batch.h"
 
 using namespace ntrup;
 
@@ -39,7 +40,11 @@ struct Ws {
     int* lists[2];
     int* counters;
     int16_t* qrow;     // persistent form: partial products of the shared reciprocals
+                       // (batched R/3: the group products, int8)
     int* flags;        // persistent form: dependency counters
+    int8_t* r3rows;    // batched R/3: prefix products [n][p]
+    uint32_t* pgbits;  // batched R/3: group products' bitsliced words [WN][2][groups]
+    uint32_t* pinv;    // batched R/3: their reciprocals [WN][2][groups]
 };
 
 // Dependency counters of a persistent job of n keys (every G >= 1).
@@ -48,7 +53,8 @@ size_t flag_ints(size_t n) { return 4 * n + 64; }
 size_t ws_bytes(int p, size_t n) {
     const size_t wn = (size_t)ceil_div(p, 32);
     return align256(n * p) + 2 * align256(wn * 2 * n * 4) + 2 * align256(n * p * 2) + align256(n) +
-           2 * align256(n * 4) + align256(kCounterInts * 4) + align256(n * p * 2) + align256(flag_ints(n) * 4);
+           2 * align256(n * 4) + align256(kCounterInts * 4) + align256(n * p * 2) + align256(flag_ints(n) * 4) +
+           align256(n * p) + 2 * align256(wn * 2 * n * 4);
 }
 
 Ws carve(void* base, int p, size_t n) {
@@ -65,7 +71,10 @@ Ws carve(void* base, int p, size_t n) {
     w.lists[1] = (int*)c;        c += align256(n * 4);
     w.counters = (int*)c;        c += align256(kCounterInts * 4);
     w.qrow = (int16_t*)c;        c += align256(n * p * 2);
-    w.flags = (int*)c;
+    w.flags = (int*)c;           c += align256(flag_ints(n) * 4);
+    w.r3rows = (int8_t*)c;       c += align256(n * p);
+    w.pgbits = (uint32_t*)c;     c += align256(wn * 2 * n * 4);
+    w.pinv = (uint32_t*)c;
     return w;
 }
 
@@ -266,7 +275,53 @@ int enqueue_keygen(ntrup_ctx* ctx, const ntrup_config& cfg, const Seed& seed, ui
     a.err = w.counters + 32;
     a.g_in = nullptr;
     const int R = cfg.retry_passes;
-    for (int pass = 0; pass <= R + 1; pass++) {
+    if (cfg.r3_batch) {
+        // batched R/3 reciprocals: screen, prefix products, group reciprocals,
+        // back-substitution; groups whose product is not a unit go to the
+        // per-key divstep pass
+        R3bArgs<P> b;
+        b.seed = seed;
+        b.first_index = first_index;
+        b.n = (int)n;
+        b.G = cfg.group_size;
+        b.gbits = w.gbits;
+        b.ibits = w.ibits;
+        b.attempts = w.attempts;
+        b.rows = w.r3rows;
+        b.pj = (int8_t*)w.qrow;
+        b.pinv = w.pinv;
+        b.pok = (const uint8_t*)w.lists[1];
+        b.fb_list = w.lists[0];
+        b.fb_count = w.counters;
+        b.err = w.counters + 32;
+        b.screen = cfg.r3_batch == 1;
+        const unsigned ngroups = grid_for(n, cfg.group_size);
+        hipLaunchKernelGGL((r3b_sample_kernel<P>), dim3(grid_for(n * (size_t)ceil_div(P, 32), 256)), dim3(256), 0, st,
+                           b);
+        hipLaunchKernelGGL((r3b_screen_kernel<P>), dim3(grid_for(n, 256)), dim3(256), 0, st, b);
+        hipLaunchKernelGGL((r3b_prefix_kernel<P>), dim3(ngroups), dim3(64), 0, st, b);
+        R3Args gi;
+        memset(&gi, 0, sizeof gi);
+        gi.n = (int)ngroups;
+        gi.max_rounds = 1;
+        gi.spec = 1;
+        gi.attempts = (uint8_t*)w.lists[1];
+        gi.gbits = w.pgbits;
+        gi.ibits = w.pinv;
+        gi.err = w.counters + 32;
+        gi.g_in = (const int8_t*)w.qrow;
+        launch_r3<P>(8, ngroups, gi, st);   // latency-bound: few products, most lanes per product
+        hipLaunchKernelGGL((r3b_back_kernel<P>), dim3(ngroups), dim3(64), 0, st, b);
+        mark(3, st);
+        a.list_in = w.lists[0];
+        a.count_in = w.counters;
+        a.list_out = nullptr;
+        a.count_out = nullptr;
+        a.spec = cfg.retry_parallel_attempts;
+        a.max_rounds = ceil_div(kMaxAttempts, a.spec);
+        launch_r3<P>(cfg.retry_lanes_per_key, n, a, st);
+    }
+    for (int pass = 0; pass <= R + 1 && !cfg.r3_batch; pass++) {
         const bool last = pass == R + 1;
         a.list_in = pass == 0 ? nullptr : w.lists[(pass - 1) & 1];
         a.count_in = pass == 0 ? nullptr : w.counters + (pass - 1);
@@ -421,7 +476,8 @@ bool valid_config(const ntrup_config& c) {
            (c.product_engine == 0 || c.product_engine == 1) &&
            (c.inverse_share == 1 || c.inverse_share == 2 || c.inverse_share == 4 || c.inverse_share == 8) &&
            (c.persistent == 0 ||
-            (c.persistent == 1 && c.product_engine == 1 && (c.lanes_per_key == 2 || c.lanes_per_key == 4)));
+            (c.persistent == 1 && c.product_engine == 1 && (c.lanes_per_key == 2 || c.lanes_per_key == 4))) &&
+           (c.r3_batch == 0 || ((c.r3_batch == 1 || c.r3_batch == 2) && c.product_engine == 1 && c.persistent == 0));
 }
 
 int check_job(int p, size_t n, const void* pk, const void* sk) {
@@ -491,7 +547,7 @@ int ntrup_ctx_create(ntrup_ctx** out, int device) {
     ntrup_ctx* ctx = new (std::nothrow) ntrup_ctx();
     if (!ctx) return NTRUP_ENOMEM;
     ctx->device = device;
-    for (int i = 0; i < 4; i++) ctx->cfg[i] = ntrup_config{32, 2, 8, 4, 1, 1, 1, 4, 0};
+    for (int i = 0; i < 4; i++) ctx->cfg[i] = ntrup_config{32, 2, 8, 4, 1, 1, 1, 4, 0, 0};
     bool ok = set_device(ctx) == 0 && hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking) == hipSuccess;
     for (int i = 0; ok && i < kJobStreams; i++)
         ok = hipStreamCreateWithFlags(&ctx->job_streams[i], hipStreamNonBlocking) == hipSuccess;
@@ -762,6 +818,21 @@ int ntrup_op_mul_rq(ntrup_ctx* ctx, int p, const int16_t* a, const int16_t* b, i
         break;
     switch (p) { NTRUP_MUL(653) NTRUP_MUL(761) NTRUP_MUL(857) NTRUP_MUL(1277) }
 #undef NTRUP_MUL
+    NTRUP_HIP(ctx, hipGetLastError());
+    return 0;
+}
+
+int ntrup_op_mul_r3(ntrup_ctx* ctx, int p, const int8_t* a, const int8_t* b, int8_t* c, size_t n, void* stream) {
+    if (!ctx || param_slot(p) < 0 || !a || !b || !c || n == 0 || n > 0x7FFFFFFF) return NTRUP_EINVAL;
+    if (int r = set_device(ctx)) return r;
+    hipStream_t st = (hipStream_t)stream;
+    const dim3 grid((unsigned)n), blk(64);
+    switch (p) {
+        case 653: hipLaunchKernelGGL(mul3_kernel<653>, grid, blk, 0, st, (int)n, a, b, c); break;
+        case 761: hipLaunchKernelGGL(mul3_kernel<761>, grid, blk, 0, st, (int)n, a, b, c); break;
+        case 857: hipLaunchKernelGGL(mul3_kernel<857>, grid, blk, 0, st, (int)n, a, b, c); break;
+        case 1277: hipLaunchKernelGGL(mul3_kernel<1277>, grid, blk, 0, st, (int)n, a, b, c); break;
+    }
     NTRUP_HIP(ctx, hipGetLastError());
     return 0;
 }

@@ -217,11 +217,12 @@ __device__ __forceinline__ void put_folded16(const uint32_t (&w)[NU][2], uint8_t
 // (c, g) returns c_{i+v}, i = 256t + 16c + 4g, in out[t] as centered int16
 // pairs (zero for i + v >= p).  Software-pipelined: the fragments of K-step
 // k+1 are read from LDS while the MFMAs of K-step k run.
-template <int P, bool H_BIG, int T0, int T1>
+template <int P, bool H_BIG, int T0, int T1, bool T_BIG, int MOD>
 __device__ __forceinline__ void mfma_tiles(const uint8_t* TL, const uint8_t* TH, const uint8_t* HL,
                                            const uint8_t* HH, uint32_t (&out)[MfShape<P>::NT][2]) {
     using S = MfShape<P>;
-    constexpr int Q = S::Q;
+    constexpr int Q = MOD;
+    static_assert(T_BIG || !H_BIG, "a one-limb Toeplitz operand goes with a one-limb Hankel operand");
     constexpr int NTC = T1 - T0;
     const int lane = lane_id();
     const int rc = lane & 15, g = lane >> 4;
@@ -229,7 +230,7 @@ __device__ __forceinline__ void mfma_tiles(const uint8_t* TL, const uint8_t* TH,
     const int s0 = S::Z0 - 16 * g - rc;
     const int sh = s0 & 3;
     const uint32_t* tl32 = (const uint32_t*)TL + (s0 >> 2);
-    const uint32_t* th32 = (const uint32_t*)TH + (s0 >> 2);
+    const uint32_t* th32 = (const uint32_t*)(T_BIG ? TH : TL) + (s0 >> 2);
     // Hankel read position of tile 0, K-step 0: block rc - g
     const uint8_t* hl = HL + S::HOFF + 16 * (rc - g);
     const uint8_t* hh = H_BIG ? HH + S::HOFF + 16 * (rc - g) : hl;
@@ -247,7 +248,7 @@ __device__ __forceinline__ void mfma_tiles(const uint8_t* TL, const uint8_t* TH,
 #pragma unroll
         for (int j = 0; j < 5; j++) {
             nDL[j] = tl32[j - 16 * k];
-            nDH[j] = th32[j - 16 * k];
+            if (T_BIG) nDH[j] = th32[j - 16 * k];
         }
 #pragma unroll
         for (int t = 0; t < NTC; t++) {
@@ -266,7 +267,7 @@ __device__ __forceinline__ void mfma_tiles(const uint8_t* TL, const uint8_t* TH,
 #pragma unroll
         for (int j = 0; j < 5; j++) {
             DL[j] = nDL[j];
-            DH[j] = nDH[j];
+            if (T_BIG) DH[j] = nDH[j];
         }
 #pragma unroll
         for (int t = 0; t < NTC; t++) {
@@ -278,7 +279,7 @@ __device__ __forceinline__ void mfma_tiles(const uint8_t* TL, const uint8_t* TH,
 #pragma unroll
         for (int j = 0; j < 4; j++) {
             tl[j] = (int)__builtin_amdgcn_alignbyte(DL[j + 1], DL[j], sh);
-            th[j] = (int)__builtin_amdgcn_alignbyte(DH[j + 1], DH[j], sh);
+            if (T_BIG) th[j] = (int)__builtin_amdgcn_alignbyte(DH[j + 1], DH[j], sh);
         }
 #pragma unroll
         for (int t = 0; t < NTC; t++) {
@@ -289,7 +290,7 @@ __device__ __forceinline__ void mfma_tiles(const uint8_t* TL, const uint8_t* TH,
                 acc2[t] = __builtin_amdgcn_mfma_i32_16x16x64_i8(th, BH[t], acc2[t], 0, 0, 0);
             } else {
                 acc0[t] = __builtin_amdgcn_mfma_i32_16x16x64_i8(tl, BL[t], acc0[t], 0, 0, 0);
-                acc1[t] = __builtin_amdgcn_mfma_i32_16x16x64_i8(th, BL[t], acc1[t], 0, 0, 0);
+                if (T_BIG) acc1[t] = __builtin_amdgcn_mfma_i32_16x16x64_i8(th, BL[t], acc1[t], 0, 0, 0);
             }
         }
     }
@@ -304,8 +305,10 @@ __device__ __forceinline__ void mfma_tiles(const uint8_t* TL, const uint8_t* TH,
             if (H_BIG)
                 v[e] = freeze<Q>(reduce_rough<Q>(acc0[t][e]) + 128 * reduce_rough<Q>(acc1[t][e]) +
                                  C14 * reduce_rough<Q>(acc2[t][e]));
-            else
+            else if (T_BIG)
                 v[e] = freeze<Q>(acc0[t][e] + 128 * acc1[t][e]);
+            else
+                v[e] = freeze<Q>(acc0[t][e]);
             v[e] = (i + e < P) ? v[e] : 0;
         }
         out[T0 + t][0] = (uint32_t)(uint16_t)v[0] | ((uint32_t)(uint16_t)v[1] << 16);
@@ -330,13 +333,13 @@ struct MfSplit {
     static constexpr int lo(int c) { return c * NT / NC; }
 };
 
-template <int P, bool H_BIG, int C>
+template <int P, bool H_BIG, int C, bool T_BIG, int MOD>
 __device__ __forceinline__ void mfma_chunks(const uint8_t* TL, const uint8_t* TH, const uint8_t* HL,
                                             const uint8_t* HH, uint32_t (&out)[MfShape<P>::NT][2]) {
     using SP = MfSplit<P, H_BIG>;
     if constexpr (C < SP::NC) {
-        mfma_tiles<P, H_BIG, SP::lo(C), SP::lo(C + 1)>(TL, TH, HL, HH, out);
-        mfma_chunks<P, H_BIG, C + 1>(TL, TH, HL, HH, out);
+        mfma_tiles<P, H_BIG, SP::lo(C), SP::lo(C + 1), T_BIG, MOD>(TL, TH, HL, HH, out);
+        mfma_chunks<P, H_BIG, C + 1, T_BIG, MOD>(TL, TH, HL, HH, out);
     }
 }
 
@@ -345,20 +348,25 @@ __device__ __forceinline__ void mfma_chunks(const uint8_t* TL, const uint8_t* TH
 //   dst  (LDS int16, c_i at dst[i]),
 //   TLo/THo (LDS, the reversed Toeplitz limbs of c for the next product:
 //        TLo[Z0 - i] = lo(c_i), THo[Z0 - i] = hi(c_i); may be TL, TH),
-//   row  (global int16)
+//   row  (global int16), row8 (global int8, for |c_i| < 128)
 // may be nullptr.  Wave-local: the caller orders the inputs (wave_sync)
 // before the call and the outputs after it.
-template <int P, bool H_BIG>
+// T_BIG = false: a one-limb Toeplitz operand (TH unused; then THo is not
+// written and H is one limb too); MOD: the coefficient modulus (q for R/q,
+// 3 for R/3 with both operands in {-1, 0, 1}).
+template <int P, bool H_BIG, bool T_BIG = true, int MOD = Param<P>::q>
 __device__ __forceinline__ void mfma_mul(const uint8_t* TL, const uint8_t* TH, const uint8_t* HL, const uint8_t* HH,
-                                         int16_t* dst, uint8_t* TLo, uint8_t* THo, int16_t* row) {
+                                         int16_t* dst, uint8_t* TLo, uint8_t* THo, int16_t* row,
+                                         int8_t* row8 = nullptr) {
     using S = MfShape<P>;
-    constexpr int Q = S::Q;
+    constexpr int Q = MOD;
     // a_{p-1} b_{p-1} (b_{p-1} = E_{p-1}), read before TLo may replace TL
-    const int32_t ap = (int32_t)(int8_t)TL[S::Z0 - (P - 1)] + 128 * (int32_t)(int8_t)TH[S::Z0 - (P - 1)];
+    const int32_t ap = (int32_t)(int8_t)TL[S::Z0 - (P - 1)] +
+                       (T_BIG ? 128 * (int32_t)(int8_t)TH[S::Z0 - (P - 1)] : 0);
     const int32_t bp = (int32_t)(int8_t)HL[S::HOFF + P - 1] +
                        (H_BIG ? 128 * (int32_t)(int8_t)HH[S::HOFF + P - 1] : 0);
     uint32_t out[S::NT][2];
-    mfma_chunks<P, H_BIG, 0>(TL, TH, HL, HH, out);
+    mfma_chunks<P, H_BIG, 0, T_BIG, MOD>(TL, TH, HL, HH, out);
     // c_0 = (folded sum at 0) - conv_{p-1},  conv_{p-1} = c_{p-1} - a_{p-1} b_{p-1}
     const int lane = lane_id();
     const int32_t cp = (int32_t)(int16_t)(__builtin_amdgcn_readlane((int)out[S::TP][0], S::LP) & 0xFFFF);
@@ -385,12 +393,17 @@ __device__ __forceinline__ void mfma_mul(const uint8_t* TL, const uint8_t* TH, c
                 hi |= h << (8 * (3 - e));
             }
             *(uint32_t*)(TLo + S::Z0 - i - 3) = lo;
-            *(uint32_t*)(THo + S::Z0 - i - 3) = hi;
+            if (T_BIG) *(uint32_t*)(THo + S::Z0 - i - 3) = hi;
         }
         if (row) {
 #pragma unroll
             for (int e = 0; e < 4; e++)
                 if (i + e < P) row[i + e] = (int16_t)((e < 2 ? w0 : w1) >> (16 * (e & 1)));
+        }
+        if (row8) {
+#pragma unroll
+            for (int e = 0; e < 4; e++)
+                if (i + e < P) row8[i + e] = (int8_t)((e < 2 ? w0 : w1) >> (16 * (e & 1)));
         }
     }
 }

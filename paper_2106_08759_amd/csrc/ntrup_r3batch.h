@@ -1,0 +1,339 @@
+// Batched R/3 reciprocals (Section 3.1, Algorithm 1: batchInv over R/3 with
+// the isInvertible check of each g), on the int8 matrix cores.
+//
+// r3b_screen_kernel   one lane per key: draw g (stream 1 + attempt) until g
+//                     mod f_i != 0 for every irreducible factor f_i of
+//                     x^p - x - 1 over F_3 of degree <= 32 (Horner, one
+//                     bitsliced word per factor); writes g's bitsliced words
+//                     and the accepted attempt.  The factors left unscreened
+//                     have degree >= 60, so a non-unit g passes with
+//                     probability below 3^-60 per draw.
+// r3b_prefix_kernel   one wave per Montgomery group: b_1 = g_1, b_i = g_i
+//                     b_{i-1} in R/3 (int8 rows), the group product to pj.
+// (group reciprocals: the per-key divstep kernel on the rows of pj)
+// r3b_back_kernel     one wave per group: from t = 1/b_G, 1/g_i = t b_{i-1},
+//                     t <- t g_i, written as bitsliced words.  A group whose
+//                     product is not a unit (one of its g failed on an
+//                     unscreened factor) instead lists its keys for the
+//                     per-key divstep pass, which resumes each key at its
+//                     screened attempt; outputs are the same either way.
+// Products are mfma_mul with one int8 limb per operand, reduced mod 3.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ntrup_keygen.h"
+#include "ntrup_mfma.h"
+#include "ntrup_r3_factors.h"
+
+namespace ntrup {
+
+template <int P>
+struct R3bArgs {
+    Seed seed;
+    uint64_t first_index;
+    int n, G;
+    uint32_t* gbits;        // [WN][2][n] bitsliced g (nonzero, negative)
+    uint32_t* ibits;        // [WN][2][n] bitsliced 1/g
+    uint8_t* attempts;      // [n] accepted attempt of each key
+    int8_t* rows;           // [n][p] prefix products b_i
+    int8_t* pj;             // [groups][p] group products
+    const uint32_t* pinv;   // [WN][2][groups] their reciprocals (bitsliced)
+    const uint8_t* pok;     // [groups] 1 iff the group product is a unit
+    int* fb_list;           // keys of groups whose product is not a unit
+    int* fb_count;
+    int* err;               // |= 1 when a key finds no screened g in 64 draws
+    int screen;             // 0: accept the first draw (tests of the fallback path)
+};
+
+// g mod f for every screened factor f, from the top coefficient down
+// (Horner): r <- r x + g_i, then the coefficient of x^d is folded back with
+// x^d = -(c_0 + ... + c_{d-1} x^{d-1}).  Words are fed from the highest.
+template <int P>
+struct R3Screen {
+    using F = R3Factors<P>;
+    uint32_t rm[F::count], rs[F::count];
+    __device__ __forceinline__ void reset() {
+#pragma unroll
+        for (int j = 0; j < F::count; j++) rm[j] = rs[j] = 0u;
+    }
+    __device__ __forceinline__ void feed_word(uint32_t m, uint32_t s) {
+#pragma unroll
+        for (int b = 31; b >= 0; b--) {
+            const uint32_t gm = (m >> b) & 1u, gs = (s >> b) & 1u;
+#pragma unroll
+            for (int j = 0; j < F::count; j++) {
+                const int d = F::f[j].d;
+                const uint32_t mask = d == 32 ? 0xFFFFFFFFu : ((1u << d) - 1u);
+                const uint32_t tm = (rm[j] >> (d - 1)) & 1u, ts = (rs[j] >> (d - 1)) & 1u;
+                uint32_t am = ((rm[j] << 1) | gm) & mask, as = ((rs[j] << 1) | gs) & mask;
+                // add (-t) (c_0 .. c_{d-1}): nonzero where c is and t != 0,
+                // negative where c and -t differ in sign
+                const uint32_t bm = F::f[j].m & (0u - tm);
+                const uint32_t bs = F::f[j].s ^ (ts - 1u);
+                rm[j] = (am ^ bm) | (am & bm & ~(as ^ bs));
+                rs[j] = (am & (as ^ bm)) | (~am & bs);
+            }
+        }
+    }
+    __device__ __forceinline__ bool nonzero_all() const {
+        bool ok = true;
+#pragma unroll
+        for (int j = 0; j < F::count; j++) ok = ok && rm[j] != 0u;
+        return ok;
+    }
+};
+
+// First draw of every key's g: one thread per (key, 32-coefficient word).
+template <int P>
+__global__ __launch_bounds__(256) void r3b_sample_kernel(R3bArgs<P> a) {
+    constexpr int WN = ceil_div(P, 32);
+    const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (size_t)a.n * WN) return;
+    const int key = (int)(t % (size_t)a.n), k = (int)(t / (size_t)a.n);
+    uint32_t mw, sw;
+    sample_small_word<P>(a.seed, a.first_index + (uint64_t)key, 0, k, mw, sw);
+    a.gbits[(size_t)(2 * k) * a.n + key] = mw;
+    a.gbits[(size_t)(2 * k + 1) * a.n + key] = sw & mw;
+}
+
+// The screen of every key's draw, one lane per key; a draw that fails is
+// replaced by the next (stream 1 + attempt) until one passes.
+template <int P>
+__global__ __launch_bounds__(256) void r3b_screen_kernel(R3bArgs<P> a) {
+    constexpr int WN = ceil_div(P, 32);
+    const int key = blockIdx.x * blockDim.x + threadIdx.x;
+    if (key >= a.n) return;
+    const uint64_t index = a.first_index + (uint64_t)key;
+    const size_t n = (size_t)a.n;
+    int att = 0;
+    if (a.screen) {
+        for (; att < kMaxAttempts; att++) {
+            R3Screen<P> sc;
+            sc.reset();
+            for (int k = WN - 1; k >= 0; k--) {
+                uint32_t mw, sw;
+                if (att == 0) {
+                    mw = a.gbits[(size_t)(2 * k) * n + key];
+                    sw = a.gbits[(size_t)(2 * k + 1) * n + key];
+                } else {
+                    sample_small_word<P>(a.seed, index, att, k, mw, sw);
+                    sw &= mw;
+                    a.gbits[(size_t)(2 * k) * n + key] = mw;
+                    a.gbits[(size_t)(2 * k + 1) * n + key] = sw;
+                }
+                sc.feed_word(mw, sw);
+            }
+            if (sc.nonzero_all()) break;
+        }
+        if (att >= kMaxAttempts) atomicOr(a.err, 1);
+    }
+    a.attempts[key] = (uint8_t)(att < kMaxAttempts ? att : kMaxAttempts);
+}
+
+// Reversed Toeplitz bytes of a ternary polynomial from its bitsliced words
+// (four coefficients per lane word, as kg_load_bits loads them).
+template <int P>
+__device__ __forceinline__ void r3b_put_toeplitz(const uint32_t (&m)[KgShape<P>::NU], const uint32_t (&s)[KgShape<P>::NU],
+                                                 uint8_t* TL) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int u = 0; u < KgShape<P>::NU; u++) {
+        const int m0 = 4 * lane + 256 * u;
+        if (m0 >= P) continue;
+        const uint32_t w = spread4(m[u]) | (spread4(s[u]) * 0xFEu);
+        *(uint32_t*)(TL + MfShape<P>::Z0 - m0 - 3) = __builtin_amdgcn_perm(0u, w, 0x00010203u);   // byte reverse
+    }
+}
+
+template <int P>
+struct R3bLds {
+    using S = MfShape<P>;
+    __attribute__((aligned(16))) uint8_t TL[S::TLEN];   // Toeplitz bytes of the running value
+    __attribute__((aligned(16))) uint8_t HB[S::HLEN];   // folded Hankel bytes of b_{i-1}
+    __attribute__((aligned(16))) uint8_t HG[S::HLEN];   // folded Hankel bytes of g_i
+    __attribute__((aligned(16))) int16_t C[RqShape<P>::JP];   // 1/g_i
+};
+
+template <int P>
+__device__ __forceinline__ void r3b_load_g(const R3bArgs<P>& a, int key, uint32_t (&m)[KgShape<P>::NU],
+                                           uint32_t (&s)[KgShape<P>::NU]) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int u = 0; u < KgShape<P>::NU; u++) {
+        const int m0 = 4 * lane + 256 * u;
+        uint32_t gm = 0, gs = 0;
+        if (m0 < P) {
+            const int wd = m0 >> 5, sh = m0 & 31;
+            const uint32_t live = live4<P>(m0);
+            gm = (a.gbits[(size_t)(2 * wd) * a.n + key] >> sh) & live;
+            gs = (a.gbits[(size_t)(2 * wd + 1) * a.n + key] >> sh) & live;
+        }
+        m[u] = gm;
+        s[u] = gs;
+    }
+}
+
+// Prefix products of one group per wave.
+template <int P>
+__global__ __launch_bounds__(64) void r3b_prefix_kernel(R3bArgs<P> a) {
+    using S = MfShape<P>;
+    constexpr int NU = KgShape<P>::NU;
+    __shared__ R3bLds<P> L;
+    const int group = blockIdx.x;
+    const int kw0 = group * a.G;
+    const int gsz = min(a.G, a.n - kw0);
+    if (gsz <= 0) return;
+    const int lane = lane_id();
+    kg_zero<P>(L.TL, S::TLEN);
+    kg_zero<P>(L.HG, S::HLEN);
+    wave_sync();
+    uint32_t m[NU], s[NU], w[NU];
+    r3b_load_g<P>(a, kw0, m, s);
+    r3b_put_toeplitz<P>(m, s, L.TL);                          // b_1 = g_1
+    int8_t* row0 = a.rows + (size_t)kw0 * P;
+    int8_t* prow = a.pj + (size_t)group * P;
+#pragma unroll
+    for (int u = 0; u < NU; u++) {
+        const int m0 = 4 * lane + 256 * u;
+        const uint32_t bytes = spread4(m[u]) | (spread4(s[u]) * 0xFEu);
+#pragma unroll
+        for (int t = 0; t < 4; t++)
+            if (m0 + t < P) {
+                row0[m0 + t] = (int8_t)(bytes >> (8 * t));
+                if (gsz == 1) prow[m0 + t] = (int8_t)(bytes >> (8 * t));
+            }
+    }
+    if (gsz == 1) return;
+    for (int i = 1; i < gsz; i++) {
+        r3b_load_g<P>(a, kw0 + i, m, s);
+#pragma unroll
+        for (int u = 0; u < NU; u++) w[u] = spread4(m[u]) | (spread4(s[u]) * 0xFEu);
+        put_folded8<P>(w, L.HG);
+        wave_sync();
+        mfma_mul<P, false, false, 3>(L.TL, nullptr, L.HG, nullptr, nullptr, L.TL, nullptr, nullptr,
+                                     a.rows + (size_t)(kw0 + i) * P);                    // b_{i+1}
+        if (i + 1 == gsz) {
+            wave_sync();
+            // the group product from the reversed Toeplitz bytes
+            for (int j = lane; j < P; j += 64) prow[j] = (int8_t)L.TL[S::Z0 - j];
+        }
+        wave_sync();
+    }
+}
+
+// Back-substitution of one group per wave.
+template <int P>
+__global__ __launch_bounds__(64) void r3b_back_kernel(R3bArgs<P> a) {
+    using S = MfShape<P>;
+    constexpr int NU = KgShape<P>::NU;
+    constexpr int WN = ceil_div(P, 32);
+    __shared__ R3bLds<P> L;
+    const int group = blockIdx.x;
+    const int kw0 = group * a.G;
+    const int gsz = min(a.G, a.n - kw0);
+    if (gsz <= 0) return;
+    const int lane = lane_id();
+    const int ngroups = ceil_div(a.n, a.G);
+    if (a.pok[group] != 1) {
+        // some g of this group is not a unit: per-key divsteps for all of them
+        int b0 = 0;
+        if (lane == 0) b0 = atomicAdd(a.fb_count, gsz);
+        b0 = __shfl(b0, 0);
+        for (int i = lane; i < gsz; i += 64) a.fb_list[b0 + i] = kw0 + i;
+        return;
+    }
+    kg_zero<P>(L.TL, S::TLEN);
+    kg_zero<P>(L.HB, S::HLEN);
+    kg_zero<P>(L.HG, S::HLEN);
+    wave_sync();
+    uint32_t m[NU], s[NU], w[NU];
+    // t = 1/b_G from the group reciprocal's bitsliced words
+#pragma unroll
+    for (int u = 0; u < NU; u++) {
+        const int m0 = 4 * lane + 256 * u;
+        uint32_t gm = 0, gs = 0;
+        if (m0 < P) {
+            const int wd = m0 >> 5, sh = m0 & 31;
+            const uint32_t live = live4<P>(m0);
+            gm = (a.pinv[(size_t)(2 * wd) * ngroups + group] >> sh) & live;
+            gs = (a.pinv[(size_t)(2 * wd + 1) * ngroups + group] >> sh) & live;
+        }
+        m[u] = gm;
+        s[u] = gs;
+    }
+    r3b_put_toeplitz<P>(m, s, L.TL);
+    for (int i = gsz; i >= 1; i--) {
+        const int key = kw0 + i - 1;
+        wave_sync();
+        if (i > 1) {
+            // c_i = t b_{i-1}
+            const int8_t* brow = a.rows + (size_t)(key - 1) * P;
+#pragma unroll
+            for (int u = 0; u < NU; u++) {
+                const int m0 = 4 * lane + 256 * u;
+                uint32_t v = 0;
+#pragma unroll
+                for (int t = 0; t < 4; t++)
+                    if (m0 + t < P) v |= (uint32_t)(uint8_t)brow[m0 + t] << (8 * t);
+                w[u] = v;
+            }
+            put_folded8<P>(w, L.HB);
+            wave_sync();
+            mfma_mul<P, false, false, 3>(L.TL, nullptr, L.HB, nullptr, L.C, nullptr, nullptr, nullptr);
+            // t <- t g_i
+            r3b_load_g<P>(a, key, m, s);
+#pragma unroll
+            for (int u = 0; u < NU; u++) w[u] = spread4(m[u]) | (spread4(s[u]) * 0xFEu);
+            put_folded8<P>(w, L.HG);
+            wave_sync();
+            mfma_mul<P, false, false, 3>(L.TL, nullptr, L.HG, nullptr, nullptr, L.TL, nullptr, nullptr);
+        } else {
+            for (int j = lane; j < P; j += 64) L.C[j] = (int16_t)(int8_t)L.TL[S::Z0 - j];   // c_1 = t
+        }
+        wave_sync();
+        // 1/g of key as bitsliced words: one ballot per 64 coefficients and plane
+#pragma unroll
+        for (int r = 0; r < ceil_div(WN, 2); r++) {
+            const int i2 = 64 * r + lane;
+            const int v = i2 < P ? L.C[i2] : 0;
+            const unsigned long long bm = __ballot(v != 0), bs = __ballot(v < 0);
+            if (lane < 2 && 2 * r + lane < WN) {
+                const int k = 2 * r + lane;
+                a.ibits[(size_t)(2 * k) * a.n + key] = (uint32_t)(bm >> (32 * lane));
+                a.ibits[(size_t)(2 * k + 1) * a.n + key] = (uint32_t)(bs >> (32 * lane));
+            }
+        }
+    }
+}
+
+// c = a b in R/3 (int8 rows, centered), for the kernel tests.
+template <int P>
+__global__ __launch_bounds__(64) void mul3_kernel(int n, const int8_t* x, const int8_t* y, int8_t* z) {
+    using S = MfShape<P>;
+    constexpr int NU = KgShape<P>::NU;
+    __shared__ R3bLds<P> L;
+    const int e = blockIdx.x;
+    if (e >= n) return;
+    const int lane = lane_id();
+    kg_zero<P>(L.TL, S::TLEN);
+    kg_zero<P>(L.HG, S::HLEN);
+    wave_sync();
+    uint32_t w[NU];
+    for (int j = lane; j < P; j += 64) L.TL[S::Z0 - j] = (uint8_t)y[(size_t)e * P + j];
+#pragma unroll
+    for (int u = 0; u < NU; u++) {
+        const int m0 = 4 * lane + 256 * u;
+        uint32_t v = 0;
+#pragma unroll
+        for (int t = 0; t < 4; t++)
+            if (m0 + t < P) v |= (uint32_t)(uint8_t)x[(size_t)e * P + m0 + t] << (8 * t);
+        w[u] = v;
+    }
+    put_folded8<P>(w, L.HG);
+    wave_sync();
+    mfma_mul<P, false, false, 3>(L.TL, nullptr, L.HG, nullptr, nullptr, nullptr, nullptr, nullptr,
+                                 z + (size_t)e * P);
+}
+
+}  // namespace ntrup
