@@ -244,26 +244,35 @@ int enqueue_keygen(ntrup_ctx* ctx, const ntrup_config& cfg, const Seed& seed, ui
 
     hipLaunchKernelGGL(zero_ints_kernel, dim3(1), dim3(64), 0, st, w.counters, zero_err ? kCounterInts : 16);
     mark(0, st);
+    // batched R/3 needs no f: its whole stage runs on the side stream from
+    // the start, beside sampling and the prefix kernel (which stay on st)
+    const bool r3_first = side && cfg.r3_batch;
+    hipStream_t sp = r3_first ? st : ss;   // prefix kernel
+    hipStream_t sr = r3_first ? ss : st;   // R/3 stage
+    if (r3_first) {
+        NTRUP_HIP(ctx, hipEventRecord(ctx->side_fork, st));
+        NTRUP_HIP(ctx, hipStreamWaitEvent(ss, ctx->side_fork, 0));
+    }
     hipLaunchKernelGGL(sample_short_kernel<P>, dim3(grid_for(n, 4)), dim3(256), 0, st, seed, first_index, (int)n,
                        w.f_rows);
     mark(1, st);
-    if (side) {
+    if (side && !r3_first) {
         NTRUP_HIP(ctx, hipEventRecord(ctx->side_fork, st));
         NTRUP_HIP(ctx, hipStreamWaitEvent(ss, ctx->side_fork, 0));
     }
     if (mfma) {
         const dim3 grid(grid_for(n, (size_t)cfg.group_size * W)), blk(64 * W);
         switch (W) {
-            case 1: hipLaunchKernelGGL((keygen_prefix_kernel<P, 1>), grid, blk, 0, ss, g, w.tinv); break;
-            case 2: hipLaunchKernelGGL((keygen_prefix_kernel<P, 2>), grid, blk, 0, ss, g, w.tinv); break;
-            case 4: hipLaunchKernelGGL((keygen_prefix_kernel<P, 4>), grid, blk, 0, ss, g, w.tinv); break;
+            case 1: hipLaunchKernelGGL((keygen_prefix_kernel<P, 1>), grid, blk, 0, sp, g, w.tinv); break;
+            case 2: hipLaunchKernelGGL((keygen_prefix_kernel<P, 2>), grid, blk, 0, sp, g, w.tinv); break;
+            case 4: hipLaunchKernelGGL((keygen_prefix_kernel<P, 4>), grid, blk, 0, sp, g, w.tinv); break;
             default:
-                if constexpr (P != 1277) hipLaunchKernelGGL((keygen_prefix_kernel<P, 8>), grid, blk, 0, ss, g, w.tinv);
+                if constexpr (P != 1277) hipLaunchKernelGGL((keygen_prefix_kernel<P, 8>), grid, blk, 0, sp, g, w.tinv);
                 break;
         }
     }
-    mark(2, ss);
-    if (side) NTRUP_HIP(ctx, hipEventRecord(ctx->side_join, ss));
+    mark(2, sp);
+    if (side && !r3_first) NTRUP_HIP(ctx, hipEventRecord(ctx->side_join, ss));
     R3Args a;
     memset(&a, 0, sizeof a);
     a.seed = seed;
@@ -295,11 +304,22 @@ int enqueue_keygen(ntrup_ctx* ctx, const ntrup_config& cfg, const Seed& seed, ui
         b.fb_count = w.counters;
         b.err = w.counters + 32;
         b.screen = cfg.r3_batch == 1;
+        // retry list: lists[0] and counters[1] (the fallback reuses lists[0]
+        // afterwards, with counters[0]); retry draws in the group-reciprocal
+        // buffers (pgbits, pinv: 2 [WN][2][n] words), which are written later
+        b.rt_list = w.lists[0];
+        b.rt_count = w.counters + 1;
+        b.rt_scratch = w.pgbits;
+        b.rt_cap = (int)(2 * n / kR3bRetryDraws);
         const unsigned ngroups = grid_for(n, cfg.group_size);
-        hipLaunchKernelGGL((r3b_sample_kernel<P>), dim3(grid_for(n * (size_t)ceil_div(P, 32), 256)), dim3(256), 0, st,
+        hipLaunchKernelGGL((r3b_sample_kernel<P>), dim3(grid_for(n * (size_t)ceil_div(P, 32), 256)), dim3(256), 0, sr,
                            b);
-        hipLaunchKernelGGL((r3b_screen_kernel<P>), dim3(grid_for(n, 256)), dim3(256), 0, st, b);
-        hipLaunchKernelGGL((r3b_prefix_kernel<P>), dim3(ngroups), dim3(64), 0, st, b);
+        hipLaunchKernelGGL((r3b_screen_kernel<P>), dim3(grid_for(n, 256)), dim3(256), 0, sr, b);
+        if (b.screen) {
+            hipLaunchKernelGGL((r3b_retry_sample_kernel<P>), dim3(256), dim3(256), 0, sr, b);
+            hipLaunchKernelGGL((r3b_retry_screen_kernel<P>), dim3(64), dim3(256), 0, sr, b);
+        }
+        hipLaunchKernelGGL((r3b_prefix_kernel<P>), dim3(ngroups), dim3(64), 0, sr, b);
         R3Args gi;
         memset(&gi, 0, sizeof gi);
         gi.n = (int)ngroups;
@@ -310,16 +330,16 @@ int enqueue_keygen(ntrup_ctx* ctx, const ntrup_config& cfg, const Seed& seed, ui
         gi.ibits = w.pinv;
         gi.err = w.counters + 32;
         gi.g_in = (const int8_t*)w.qrow;
-        launch_r3<P>(8, ngroups, gi, st);   // latency-bound: few products, most lanes per product
-        hipLaunchKernelGGL((r3b_back_kernel<P>), dim3(ngroups), dim3(64), 0, st, b);
-        mark(3, st);
+        launch_r3<P>(8, ngroups, gi, sr);   // latency-bound: few products, most lanes per product
+        hipLaunchKernelGGL((r3b_back_kernel<P>), dim3(ngroups), dim3(64), 0, sr, b);
+        mark(3, sr);
         a.list_in = w.lists[0];
         a.count_in = w.counters;
         a.list_out = nullptr;
         a.count_out = nullptr;
         a.spec = cfg.retry_parallel_attempts;
         a.max_rounds = ceil_div(kMaxAttempts, a.spec);
-        launch_r3<P>(cfg.retry_lanes_per_key, n, a, st);
+        launch_r3<P>(cfg.retry_lanes_per_key, n, a, sr);
     }
     for (int pass = 0; pass <= R + 1 && !cfg.r3_batch; pass++) {
         const bool last = pass == R + 1;
@@ -332,7 +352,8 @@ int enqueue_keygen(ntrup_ctx* ctx, const ntrup_config& cfg, const Seed& seed, ui
         launch_r3<P>(pass == 0 ? cfg.lanes_per_key : cfg.retry_lanes_per_key, n, a, st);
         if (pass == 0) mark(3, st);
     }
-    mark(4, st);
+    mark(4, sr);
+    if (r3_first) NTRUP_HIP(ctx, hipEventRecord(ctx->side_join, ss));
     if (side) NTRUP_HIP(ctx, hipStreamWaitEvent(st, ctx->side_join, 0));
     if (mfma) {
         hipLaunchKernelGGL((keygen_back_kernel<P>), dim3(grid_for(n, cfg.group_size)), dim3(64), 0, st, g,
@@ -341,7 +362,7 @@ int enqueue_keygen(ntrup_ctx* ctx, const ntrup_config& cfg, const Seed& seed, ui
         hipLaunchKernelGGL((group_kernel<P, true>), dim3(grid_for(n, cfg.group_size)), dim3(64), 0, st, g);
     }
     mark(5, st);
-    if (ctx->t_used < ctx->t_max) ctx->t_side[ctx->t_used++] = side;
+    if (ctx->t_used < ctx->t_max) ctx->t_side[ctx->t_used++] = r3_first ? 3 : side ? 1 : 0;
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(ctx, e);
     return 0;
@@ -770,7 +791,10 @@ int ntrup_ctx_timing_end(ntrup_ctx* ctx, double* ms, int nstages, int* npipeline
         ms[0] += t[0][1];                                     // sample_short
         ms[3] += t[1][2];                                     // group prefix + reciprocal
         ms[2] += t[3][4];                                     // R/3 retries
-        if (ctx->t_side[c]) {
+        if (ctx->t_side[c] == 3) {
+            ms[1] += t[0][3];                                 // batched R/3 from the start, beside sampling
+            ms[4] += t[2][4] >= 0.f ? t[4][5] : t[2][5];      // back-substitution, from its later input
+        } else if (ctx->t_side[c]) {
             ms[1] += t[1][3];                                 // R/3 main pass, beside the prefix kernel
             ms[4] += t[2][4] >= 0.f ? t[4][5] : t[2][5];      // back-substitution, from its later input
         } else {

@@ -44,42 +44,64 @@ struct R3bArgs {
     int* fb_count;
     int* err;               // |= 1 when a key finds no screened g in 64 draws
     int screen;             // 0: accept the first draw (tests of the fallback path)
+    int* rt_list;           // keys whose first draw failed the screen
+    int* rt_count;
+    uint32_t* rt_scratch;   // their next draws: [draw][word][plane][rt_cap]
+    int rt_cap;
 };
 
-// g mod f for every screened factor f, from the top coefficient down
-// (Horner): r <- r x + g_i, then the coefficient of x^d is folded back with
-// x^d = -(c_0 + ... + c_{d-1} x^{d-1}).  Words are fed from the highest.
+// One Horner step r <- r x + c mod f over F_3 (bitsliced, f = x^d + sum c_j
+// x^j monic with d <= 32): the coefficient leaving degree d - 1 is folded
+// back with x^d = -(c_0 + ... + c_{d-1} x^{d-1}).
+__device__ __forceinline__ void r3_horner_step(uint32_t& rm, uint32_t& rs, uint32_t cm, uint32_t cs, int d,
+                                               uint32_t fm, uint32_t fs) {
+    const uint32_t mask = d == 32 ? 0xFFFFFFFFu : ((1u << d) - 1u);
+    const uint32_t tm = (rm >> (d - 1)) & 1u, ts = (rs >> (d - 1)) & 1u;
+    const uint32_t am = ((rm << 1) | cm) & mask, as = ((rs << 1) | cs) & mask;
+    // add (-t) (c_0 .. c_{d-1}): nonzero where c is and t != 0, negative
+    // where c and -t differ in sign
+    const uint32_t bm = fm & (0u - tm);
+    const uint32_t bs = fs ^ (ts - 1u);
+    rm = (am ^ bm) | (am & bm & ~(as ^ bs));
+    rs = (am & (as ^ bm)) | (~am & bs);
+}
+
+// g mod F for each product F of small factors (one Horner pass over g, words
+// fed from the highest), then that remainder mod each member factor.
 template <int P>
 struct R3Screen {
     using F = R3Factors<P>;
-    uint32_t rm[F::count], rs[F::count];
+    uint32_t rm[F::ngroups], rs[F::ngroups];
     __device__ __forceinline__ void reset() {
 #pragma unroll
-        for (int j = 0; j < F::count; j++) rm[j] = rs[j] = 0u;
+        for (int j = 0; j < F::ngroups; j++) rm[j] = rs[j] = 0u;
     }
     __device__ __forceinline__ void feed_word(uint32_t m, uint32_t s) {
 #pragma unroll
         for (int b = 31; b >= 0; b--) {
-            const uint32_t gm = (m >> b) & 1u, gs = (s >> b) & 1u;
+            const uint32_t cm = (m >> b) & 1u, cs = (s >> b) & 1u;
 #pragma unroll
-            for (int j = 0; j < F::count; j++) {
-                const int d = F::f[j].d;
-                const uint32_t mask = d == 32 ? 0xFFFFFFFFu : ((1u << d) - 1u);
-                const uint32_t tm = (rm[j] >> (d - 1)) & 1u, ts = (rs[j] >> (d - 1)) & 1u;
-                uint32_t am = ((rm[j] << 1) | gm) & mask, as = ((rs[j] << 1) | gs) & mask;
-                // add (-t) (c_0 .. c_{d-1}): nonzero where c is and t != 0,
-                // negative where c and -t differ in sign
-                const uint32_t bm = F::f[j].m & (0u - tm);
-                const uint32_t bs = F::f[j].s ^ (ts - 1u);
-                rm[j] = (am ^ bm) | (am & bm & ~(as ^ bs));
-                rs[j] = (am & (as ^ bm)) | (~am & bs);
-            }
+            for (int j = 0; j < F::ngroups; j++) r3_horner_step(rm[j], rs[j], cm, cs, F::g[j].d, F::g[j].m, F::g[j].s);
         }
     }
-    __device__ __forceinline__ bool nonzero_all() const {
+    // true iff g mod f != 0 for every small factor f
+    __device__ __forceinline__ bool passes() const {
         bool ok = true;
 #pragma unroll
-        for (int j = 0; j < F::count; j++) ok = ok && rm[j] != 0u;
+        for (int j = 0; j < F::ngroups; j++) {
+            if (F::g[j].nmem == 1) {
+                ok = ok && rm[j] != 0u;
+                continue;
+            }
+#pragma unroll
+            for (int e = 0; e < F::g[j].nmem; e++) {
+                const R3Factor f = F::f[F::g[j].mem[e]];
+                uint32_t tm = 0, ts = 0;
+                for (int b = F::g[j].d - 1; b >= 0; b--)
+                    r3_horner_step(tm, ts, (rm[j] >> b) & 1u, (rs[j] >> b) & 1u, f.d, f.m, f.s);
+                ok = ok && tm != 0u;
+            }
+        }
         return ok;
     }
 };
@@ -97,38 +119,107 @@ __global__ __launch_bounds__(256) void r3b_sample_kernel(R3bArgs<P> a) {
     a.gbits[(size_t)(2 * k + 1) * a.n + key] = sw & mw;
 }
 
-// The screen of every key's draw, one lane per key; a draw that fails is
-// replaced by the next (stream 1 + attempt) until one passes.
+constexpr int kR3bRetryDraws = 4;   // draws tried side by side per listed key
+
+// The screen of every key's first draw, one lane per key; keys whose draw
+// fails go to a list.
 template <int P>
 __global__ __launch_bounds__(256) void r3b_screen_kernel(R3bArgs<P> a) {
     constexpr int WN = ceil_div(P, 32);
     const int key = blockIdx.x * blockDim.x + threadIdx.x;
-    if (key >= a.n) return;
-    const uint64_t index = a.first_index + (uint64_t)key;
     const size_t n = (size_t)a.n;
-    int att = 0;
-    if (a.screen) {
-        for (; att < kMaxAttempts; att++) {
+    bool fail = false;
+    if (key < a.n) {
+        if (a.screen) {
+            R3Screen<P> sc;
+            sc.reset();
+            for (int k = WN - 1; k >= 0; k--)
+                sc.feed_word(a.gbits[(size_t)(2 * k) * n + key], a.gbits[(size_t)(2 * k + 1) * n + key]);
+            fail = !sc.passes();
+        }
+        a.attempts[key] = 0;
+    }
+    const unsigned long long m = __ballot(fail);
+    if (m) {
+        const int lane = lane_id();
+        int b0 = 0;
+        if (lane == 0) b0 = atomicAdd(a.rt_count, __popcll(m));
+        b0 = __shfl(b0, 0);
+        if (fail) a.rt_list[b0 + __popcll(m & ((1ull << lane) - 1ull))] = key;
+    }
+}
+
+// Draws 1 .. kR3bRetryDraws of every listed key (as many keys as the scratch
+// holds), one thread per (key, draw, word).
+template <int P>
+__global__ __launch_bounds__(256) void r3b_retry_sample_kernel(R3bArgs<P> a) {
+    constexpr int WN = ceil_div(P, 32);
+    const int count = min(*(volatile int*)a.rt_count, a.rt_cap);
+    const size_t total = (size_t)count * kR3bRetryDraws * WN;
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (size_t)gridDim.x * blockDim.x) {
+        const int i = (int)(t % (size_t)count);
+        const int rest = (int)(t / (size_t)count);
+        const int d = rest % kR3bRetryDraws, k = rest / kR3bRetryDraws;
+        const int key = a.rt_list[i];
+        uint32_t mw, sw;
+        sample_small_word<P>(a.seed, a.first_index + (uint64_t)key, 1 + d, k, mw, sw);
+        const size_t base = ((size_t)(d * WN + k) * 2) * a.rt_cap;
+        a.rt_scratch[base + i] = mw;
+        a.rt_scratch[base + a.rt_cap + i] = sw & mw;
+    }
+}
+
+// The lowest passing draw of every listed key; keys beyond the scratch, or
+// whose kR3bRetryDraws draws all fail, draw on one by one.
+template <int P>
+__global__ __launch_bounds__(256) void r3b_retry_screen_kernel(R3bArgs<P> a) {
+    constexpr int WN = ceil_div(P, 32);
+    const int count = *(volatile int*)a.rt_count;
+    const size_t n = (size_t)a.n;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) {
+        const int key = a.rt_list[i];
+        const uint64_t index = a.first_index + (uint64_t)key;
+        int att = 1;
+        bool done = false;
+        if (i < a.rt_cap) {
+            for (int d = 0; d < kR3bRetryDraws && !done; d++) {
+                R3Screen<P> sc;
+                sc.reset();
+                for (int k = WN - 1; k >= 0; k--) {
+                    const size_t base = ((size_t)(d * WN + k) * 2) * a.rt_cap;
+                    sc.feed_word(a.rt_scratch[base + i], a.rt_scratch[base + a.rt_cap + i]);
+                }
+                if (sc.passes()) {
+                    for (int k = 0; k < WN; k++) {
+                        const size_t base = ((size_t)(d * WN + k) * 2) * a.rt_cap;
+                        a.gbits[(size_t)(2 * k) * n + key] = a.rt_scratch[base + i];
+                        a.gbits[(size_t)(2 * k + 1) * n + key] = a.rt_scratch[base + a.rt_cap + i];
+                    }
+                    att = 1 + d;
+                    done = true;
+                }
+            }
+            if (!done) att = 1 + kR3bRetryDraws;
+        }
+        for (; !done && att < kMaxAttempts; att++) {
             R3Screen<P> sc;
             sc.reset();
             for (int k = WN - 1; k >= 0; k--) {
                 uint32_t mw, sw;
-                if (att == 0) {
-                    mw = a.gbits[(size_t)(2 * k) * n + key];
-                    sw = a.gbits[(size_t)(2 * k + 1) * n + key];
-                } else {
-                    sample_small_word<P>(a.seed, index, att, k, mw, sw);
-                    sw &= mw;
-                    a.gbits[(size_t)(2 * k) * n + key] = mw;
-                    a.gbits[(size_t)(2 * k + 1) * n + key] = sw;
-                }
+                sample_small_word<P>(a.seed, index, att, k, mw, sw);
+                sw &= mw;
+                a.gbits[(size_t)(2 * k) * n + key] = mw;
+                a.gbits[(size_t)(2 * k + 1) * n + key] = sw;
                 sc.feed_word(mw, sw);
             }
-            if (sc.nonzero_all()) break;
+            if (sc.passes()) {
+                done = true;
+                break;
+            }
         }
-        if (att >= kMaxAttempts) atomicOr(a.err, 1);
+        if (!done) atomicOr(a.err, 1);
+        a.attempts[key] = (uint8_t)(done ? att : kMaxAttempts);
     }
-    a.attempts[key] = (uint8_t)(att < kMaxAttempts ? att : kMaxAttempts);
 }
 
 // Reversed Toeplitz bytes of a ternary polynomial from its bitsliced words

@@ -98,3 +98,25 @@ def test_rejection_rates_match_factor_degrees():
     assert abs(rate[653] - 0.03704) < 1e-4
     assert abs(rate[1277] - 0.04951) < 1e-4
     assert rate[761] < 1e-9 and rate[857] < 1e-11
+
+
+@pytest.mark.parametrize("p", [653, 761, 857, 1277])
+def test_screen_groups_are_products_of_members(p):
+    """Each Horner pass of the screen reduces by a product of small factors
+    (degree <= 32); every small factor is a member of exactly one product."""
+    txt = open(HDR).read()
+    body = re.search(r"struct R3Factors<%d> \{(.*?)\n\};" % p, txt, re.S).group(1)
+    small, _ = table()[p]
+    groups = re.findall(r"\{(\d+), 0x([0-9A-F]+)u, 0x([0-9A-F]+)u, (\d+), \{([0-9, ]+)\}\}", body)
+    assert groups
+    seen = []
+    for d, m, s, nmem, mem in groups:
+        d, nmem = int(d), int(nmem)
+        mem = [int(x) for x in mem.split(",")][:nmem]
+        assert d <= 32
+        prod = np.array([1], dtype=np.int64)
+        for i in mem:
+            prod = np.convolve(prod, poly_of(*small[i])) % 3
+        assert np.array_equal(prod, poly_of(d, int(m, 16), int(s, 16)) % 3), (p, d, mem)
+        seen += mem
+    assert sorted(seen) == list(range(len(small)))
