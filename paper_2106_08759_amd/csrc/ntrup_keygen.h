@@ -248,9 +248,8 @@ __device__ __forceinline__ void kg_back_step(const GroupArgs& args, KgWave<P>& L
     const uint8_t* CL = L.TL;   // i == 1: c_1 = t_1
     const uint8_t* CH = L.TH;
     if (i > 1) {
-        mfma_mul<P, true>(L.TL, L.TH, L.HL, L.HH, nullptr, L.UL, L.UH, nullptr);   // c_i = t b_{i-1}
-        wave_sync();
-        mfma_mul<P, false>(L.TL, L.TH, L.HS, nullptr, nullptr, L.TL, L.TH, nullptr); // t <- t 3f_i
+        // c_i = t b_{i-1} and t <- t 3f_i in one pass over the K-steps
+        mfma_mul2<P>(L.TL, L.TH, L.HL, L.HH, L.HS, L.UL, L.UH, L.TL, L.TH);
         wave_sync();
         CL = L.UL;
         CH = L.UH;

@@ -408,4 +408,158 @@ __device__ __forceinline__ void mfma_mul(const uint8_t* TL, const uint8_t* TH, c
     }
 }
 
+
+// Two products sharing the Toeplitz operand a (limbs TL, TH): c1 = a b1 with
+// a big folded operand b1 (HL, HH) and c2 = a b2 with a small one (HS), over
+// the tiles [T0, T1), in one pass over the K-steps (the Toeplitz fragments are
+// read once for both).  Returns both as mfma_tiles does.
+template <int P, int T0, int T1>
+__device__ __forceinline__ void mfma_tiles2(const uint8_t* TL, const uint8_t* TH, const uint8_t* HL,
+                                            const uint8_t* HH, const uint8_t* HS,
+                                            uint32_t (&out1)[MfShape<P>::NT][2], uint32_t (&out2)[MfShape<P>::NT][2]) {
+    using S = MfShape<P>;
+    constexpr int Q = S::Q;
+    constexpr int NTC = T1 - T0;
+    const int lane = lane_id();
+    const int rc = lane & 15, g = lane >> 4;
+    const int s0 = S::Z0 - 16 * g - rc;
+    const int sh = s0 & 3;
+    const uint32_t* tl32 = (const uint32_t*)TL + (s0 >> 2);
+    const uint32_t* th32 = (const uint32_t*)TH + (s0 >> 2);
+    const int hoff = S::HOFF + 16 * (rc - g);
+    mf_v4i a0[NTC], a1[NTC], a2[NTC], s0a[NTC], s1a[NTC];
+#pragma unroll
+    for (int t = 0; t < NTC; t++) {
+        a0[t] = a1[t] = a2[t] = s0a[t] = s1a[t] = mf_v4i{0, 0, 0, 0};
+    }
+    uint32_t nDL[5], nDH[5];
+    mf_v4i nBL[NTC], nBH[NTC], nBS[NTC];
+    auto load_step = [&](int k) {
+#pragma unroll
+        for (int j = 0; j < 5; j++) {
+            nDL[j] = tl32[j - 16 * k];
+            nDH[j] = th32[j - 16 * k];
+        }
+#pragma unroll
+        for (int t = 0; t < NTC; t++) {
+            const int off = hoff + 16 * (16 * (T0 + t) - 4 * k);
+            nBL[t] = *(const mf_v4i*)(HL + off);
+            nBH[t] = *(const mf_v4i*)(HH + off);
+            nBS[t] = *(const mf_v4i*)(HS + off);
+        }
+    };
+    load_step(0);
+#pragma unroll
+    for (int k = 0; k < S::NKS; k++) {
+        if (NTRUP_MF_SCHED) __builtin_amdgcn_sched_barrier(0);
+        uint32_t DL[5], DH[5];
+        mf_v4i BL[NTC], BH[NTC], BS[NTC];
+#pragma unroll
+        for (int j = 0; j < 5; j++) {
+            DL[j] = nDL[j];
+            DH[j] = nDH[j];
+        }
+#pragma unroll
+        for (int t = 0; t < NTC; t++) {
+            BL[t] = nBL[t];
+            BH[t] = nBH[t];
+            BS[t] = nBS[t];
+        }
+        if (k + 1 < S::NKS) load_step(k + 1);
+        mf_v4i tl, th;
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            tl[j] = (int)__builtin_amdgcn_alignbyte(DL[j + 1], DL[j], sh);
+            th[j] = (int)__builtin_amdgcn_alignbyte(DH[j + 1], DH[j], sh);
+        }
+#pragma unroll
+        for (int t = 0; t < NTC; t++) {
+            a0[t] = __builtin_amdgcn_mfma_i32_16x16x64_i8(tl, BL[t], a0[t], 0, 0, 0);
+            a1[t] = __builtin_amdgcn_mfma_i32_16x16x64_i8(tl, BH[t], a1[t], 0, 0, 0);
+            s0a[t] = __builtin_amdgcn_mfma_i32_16x16x64_i8(tl, BS[t], s0a[t], 0, 0, 0);
+            a1[t] = __builtin_amdgcn_mfma_i32_16x16x64_i8(th, BL[t], a1[t], 0, 0, 0);
+            a2[t] = __builtin_amdgcn_mfma_i32_16x16x64_i8(th, BH[t], a2[t], 0, 0, 0);
+            s1a[t] = __builtin_amdgcn_mfma_i32_16x16x64_i8(th, BS[t], s1a[t], 0, 0, 0);
+        }
+    }
+    constexpr int32_t C14 = ((16384 % Q) > Q / 2) ? (16384 % Q) - Q : (16384 % Q);
+#pragma unroll
+    for (int t = 0; t < NTC; t++) {
+        const int i = 256 * (T0 + t) + 16 * rc + 4 * g;
+        int32_t v[4], w[4];
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+            v[e] = freeze<Q>(reduce_rough<Q>(a0[t][e]) + 128 * reduce_rough<Q>(a1[t][e]) +
+                             C14 * reduce_rough<Q>(a2[t][e]));
+            w[e] = freeze<Q>(s0a[t][e] + 128 * s1a[t][e]);
+            v[e] = (i + e < P) ? v[e] : 0;
+            w[e] = (i + e < P) ? w[e] : 0;
+        }
+        out1[T0 + t][0] = (uint32_t)(uint16_t)v[0] | ((uint32_t)(uint16_t)v[1] << 16);
+        out1[T0 + t][1] = (uint32_t)(uint16_t)v[2] | ((uint32_t)(uint16_t)v[3] << 16);
+        out2[T0 + t][0] = (uint32_t)(uint16_t)w[0] | ((uint32_t)(uint16_t)w[1] << 16);
+        out2[T0 + t][1] = (uint32_t)(uint16_t)w[2] | ((uint32_t)(uint16_t)w[3] << 16);
+    }
+}
+
+#ifndef NTRUP_MF_MAXC_PAIR
+#define NTRUP_MF_MAXC_PAIR 3
+#endif
+template <int P, int C>
+__device__ __forceinline__ void mfma_chunks2(const uint8_t* TL, const uint8_t* TH, const uint8_t* HL,
+                                             const uint8_t* HH, const uint8_t* HS,
+                                             uint32_t (&out1)[MfShape<P>::NT][2], uint32_t (&out2)[MfShape<P>::NT][2]) {
+    constexpr int NT = MfShape<P>::NT, NC = ceil_div(NT, NTRUP_MF_MAXC_PAIR);
+    if constexpr (C < NC) {
+        mfma_tiles2<P, C * NT / NC, (C + 1) * NT / NC>(TL, TH, HL, HH, HS, out1, out2);
+        mfma_chunks2<P, C + 1>(TL, TH, HL, HH, HS, out1, out2);
+    }
+}
+
+// The reversed Toeplitz limbs of a product held as mfma_tiles returns it,
+// after the correction of c_0 (see mfma_mul).
+template <int P>
+__device__ __forceinline__ void mfma_fix_store(uint32_t (&out)[MfShape<P>::NT][2], int32_t ap, int32_t bp, uint8_t* TLo,
+                                               uint8_t* THo) {
+    using S = MfShape<P>;
+    constexpr int Q = S::Q;
+    const int lane = lane_id();
+    const int32_t cp = (int32_t)(int16_t)(__builtin_amdgcn_readlane((int)out[S::TP][0], S::LP) & 0xFFFF);
+    const int32_t c0 = freeze<Q>((int32_t)(int16_t)(out[0][0] & 0xFFFFu) - cp + ap * bp);
+    if (lane == 0) out[0][0] = (out[0][0] & 0xFFFF0000u) | (uint32_t)(uint16_t)c0;
+    const int rc = lane & 15, g = lane >> 4;
+#pragma unroll
+    for (int t = 0; t < S::NT; t++) {
+        const int i = 256 * t + 16 * rc + 4 * g;
+        if (i >= P) continue;
+        uint32_t lo = 0, hi = 0;
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+            uint32_t l, h;
+            split_limb((int32_t)(int16_t)((e < 2 ? out[t][0] : out[t][1]) >> (16 * (e & 1))), l, h);
+            lo |= l << (8 * (3 - e));
+            hi |= h << (8 * (3 - e));
+        }
+        *(uint32_t*)(TLo + S::Z0 - i - 3) = lo;
+        *(uint32_t*)(THo + S::Z0 - i - 3) = hi;
+    }
+}
+
+// c1 = a b1 (big b1: HL, HH) to the Toeplitz limbs U1L/U1H and c2 = a b2
+// (small b2: HS) to U2L/U2H, which may be TL/TH themselves (a replaced by
+// c2).  Wave-local like mfma_mul.
+template <int P>
+__device__ __forceinline__ void mfma_mul2(const uint8_t* TL, const uint8_t* TH, const uint8_t* HL, const uint8_t* HH,
+                                          const uint8_t* HS, uint8_t* U1L, uint8_t* U1H, uint8_t* U2L, uint8_t* U2H) {
+    using S = MfShape<P>;
+    const int32_t ap = (int32_t)(int8_t)TL[S::Z0 - (P - 1)] + 128 * (int32_t)(int8_t)TH[S::Z0 - (P - 1)];
+    const int32_t bp1 = (int32_t)(int8_t)HL[S::HOFF + P - 1] + 128 * (int32_t)(int8_t)HH[S::HOFF + P - 1];
+    const int32_t bp2 = (int32_t)(int8_t)HS[S::HOFF + P - 1];
+    uint32_t out1[S::NT][2], out2[S::NT][2];
+    mfma_chunks2<P, 0>(TL, TH, HL, HH, HS, out1, out2);
+    wave_sync();
+    mfma_fix_store<P>(out1, ap, bp1, U1L, U1H);
+    mfma_fix_store<P>(out2, ap, bp2, U2L, U2H);
+}
+
 }  // namespace ntrup
