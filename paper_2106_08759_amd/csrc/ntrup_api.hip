@@ -349,8 +349,8 @@ int enqueue_keygen(ntrup_ctx* ctx, const ntrup_config& cfg, const Seed& seed, ui
         a.count_out = last ? nullptr : w.counters + pass;
         a.spec = pass == 0 ? 1 : cfg.retry_parallel_attempts;
         a.max_rounds = last ? ceil_div(kMaxAttempts, a.spec) : 1;
-        launch_r3<P>(pass == 0 ? cfg.lanes_per_key : cfg.retry_lanes_per_key, n, a, st);
-        if (pass == 0) mark(3, st);
+        launch_r3<P>(pass == 0 ? cfg.lanes_per_key : cfg.retry_lanes_per_key, n, a, sr);
+        if (pass == 0) mark(3, sr);
     }
     mark(4, sr);
     if (r3_first) NTRUP_HIP(ctx, hipEventRecord(ctx->side_join, ss));

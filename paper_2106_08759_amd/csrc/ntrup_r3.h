@@ -113,6 +113,82 @@ __device__ __forceinline__ uint32_t load_output(const uint32_t* vst, int k) {
     return w;
 }
 
+// One-lane form (a whole key in one lane): only the live words are touched.
+// At step j (0-based) of the 2p-1, the steps still to come read only
+// coefficients [0, 2p-1-j) of f and g (each step's control reads coefficient
+// 0, and the new g's coefficient i comes from coefficients i and i+1), and
+// v, r have degree at most j, v at most j+1 after its shift.  So the words of
+// f and g above ceil(min(p+1, 2p-1-j)/32) can be left stale (their bits only
+// ever reach positions that are no longer read) and the words of v and r
+// above ceil((j+2)/32) are still zero.  The 2p-1 steps run in segments of
+// kR3Seg steps, each with the live word counts of its worst step as
+// compile-time constants: about 79% of the word updates of the full loop.
+#ifndef NTRUP_R3_SEG
+#define NTRUP_R3_SEG 96
+#endif
+constexpr int kR3Seg = NTRUP_R3_SEG;
+static_assert(kR3Seg % 3 == 0, "segments of whole three-step trips (2p-1 is a multiple of 3 for every p here)");
+
+template <int W, int NFG, int NVR>
+__device__ __forceinline__ void r3_step_live(uint32_t (&fm)[W], uint32_t (&fs)[W], uint32_t (&gm)[W],
+                                             uint32_t (&gs)[W], uint32_t (&vm)[W], uint32_t (&vs)[W],
+                                             uint32_t (&rm)[W], uint32_t (&rs)[W], int32_t& e) {
+    const uint32_t NZ = (uint32_t)__builtin_amdgcn_sbfe((int)gm[0], 0, 1);
+    const uint32_t NEG = (uint32_t)__builtin_amdgcn_sbfe((int)__builtin_amdgcn_bitop3_b32(gm[0], gs[0], fs[0], kAndXnor),
+                                                         0, 1);
+    const uint32_t SW = NZ & ~(uint32_t)(e >> 31);
+    e = (int32_t)((uint32_t)e ^ SW) + (int32_t)SW + 1;
+#pragma unroll
+    for (int k = 0; k < NFG; k++) {
+        const uint32_t mbf = fm[k] & NZ;
+        const uint32_t xg = xor3(gs[k], NEG, fs[k]), ug = xor3(gs[k], NEG, mbf);
+        const uint32_t ngm = addm(gm[k], mbf, xg), ngs = sel(gm[k], ug, fs[k]);
+        fm[k] = sel(SW, gm[k], fm[k]);
+        fs[k] = sel(SW, gs[k], fs[k]);
+        gm[k] = ngm;
+        gs[k] = ngs;
+    }
+#pragma unroll
+    for (int k = 0; k < NVR; k++) {
+        const uint32_t mbv = vm[k] & NZ;
+        const uint32_t xr = xor3(rs[k], NEG, vs[k]), ur = xor3(rs[k], NEG, mbv);
+        const uint32_t nrm = addm(rm[k], mbv, xr), nrs = sel(rm[k], ur, vs[k]);
+        const uint32_t nvm = sel(SW, rm[k], vm[k]), nvs = sel(SW, rs[k], vs[k]);
+        rm[k] = nrm;
+        rs[k] = nrs;
+        vm[k] = nvm;
+        vs[k] = nvs;
+    }
+#pragma unroll
+    for (int k = 0; k < NFG - 1; k++) {
+        gm[k] = __builtin_amdgcn_alignbit(gm[k + 1], gm[k], 1);
+        gs[k] = __builtin_amdgcn_alignbit(gs[k + 1], gs[k], 1);
+    }
+    gm[NFG - 1] >>= 1;
+    gs[NFG - 1] >>= 1;
+#pragma unroll
+    for (int k = NVR - 1; k > 0; k--) {
+        vm[k] = __builtin_amdgcn_alignbit(vm[k], vm[k - 1], 31);
+        vs[k] = __builtin_amdgcn_alignbit(vs[k], vs[k - 1], 31);
+    }
+    vm[0] <<= 1;
+    vs[0] <<= 1;
+}
+
+template <int P, int SEG, int W>
+__device__ __forceinline__ void r3_live_segments(uint32_t (&fm)[W], uint32_t (&fs)[W], uint32_t (&gm)[W],
+                                                 uint32_t (&gs)[W], uint32_t (&vm)[W], uint32_t (&vs)[W],
+                                                 uint32_t (&rm)[W], uint32_t (&rs)[W], int32_t& e) {
+    constexpr int N = 2 * P - 1, A = SEG * kR3Seg, B = A + kR3Seg < N ? A + kR3Seg : N;
+    constexpr int LFG = P + 1 < N - A ? P + 1 : N - A;     // f, g coefficients read from step A on
+    constexpr int NFG = ceil_div(LFG, 32);
+    constexpr int NVR = ceil_div(B + 1, 32) < W ? ceil_div(B + 1, 32) : W;   // v, r words by step B-1
+    static_assert((B - A) % 3 == 0, "whole trips");
+#pragma unroll 3
+    for (int j = A; j < B; j++) r3_step_live<W, NFG, NVR>(fm, fs, gm, gs, vm, vs, rm, rs, e);
+    if constexpr (B < N) r3_live_segments<P, SEG + 1, W>(fm, fs, gm, gs, vm, vs, rm, rs, e);
+}
+
 // The divstep loop.  In: this lane's W2 words of reversed g (gm, gs).  Out:
 // v words (vm, vs) scaled by f(0)^-1, and the final delta.  h = lane index
 // inside the key (0 or 1); the even lane holds coefficient 0.
@@ -144,9 +220,10 @@ __device__ __forceinline__ int r3_divsteps(typename R3Shape<P, LPK>::Words& gm,
     int32_t e = 0;
     const uint32_t last = (h == LPK - 1) ? 0xFFFFFFFFu : 0u;   // top lane of the key's group
     const uint32_t first = (h == 0) ? 0xFFFFFFFFu : 0u;        // bottom lane
+    if constexpr (LPK == 1) r3_live_segments<P, 0, W2>(fm, fs, gm, gs, vm, vs, rm, rs, e);
     // three steps per trip: the register renaming of the updates needs no moves
 #pragma unroll 3
-    for (int step = 0; step < 2 * P - 1; step++) {
+    for (int step = 0; step < (LPK == 1 ? 0 : 2 * P - 1); step++) {
         // coefficient 0 of f and g lives in bit 0 of word 0 of the group's first
         // lane; f(0) != 0, so only its sign matters
         const uint32_t fs0 = group_first<LPK>(fs[0]);

@@ -99,7 +99,8 @@ def test_resampling_invariance(ctx, p):
     assert sum(ref[i][5] > 1 for i in range(n)) >= 5
     base = ctx.get_config(p)
     try:
-        for lpk, rl, ra, rp in [(2, 2, 1, 0), (4, 8, 2, 1), (8, 8, 8, 2), (1, 4, 4, 0), (2, 8, 4, 3)]:
+        for lpk, rl, ra, rp in [(2, 2, 1, 0), (4, 8, 2, 1), (8, 8, 8, 2), (1, 4, 4, 0), (2, 8, 4, 3),
+                               (1, 1, 2, 1)]:
             ctx.set_config(p, lanes_per_key=lpk, retry_lanes_per_key=rl, retry_parallel_attempts=ra,
                            retry_passes=rp)
             pk, sk = ctx.batch_keygen(p, wl.SEED, 0, n)
@@ -184,3 +185,28 @@ def test_full_size_65536_sampled_and_property(ctx):
         e = np.zeros(761, dtype=one.dtype)
         e[0] = 1
         assert (one == e).all()
+
+
+@pytest.mark.parametrize("p", [653, 761])
+def test_one_lane_form_full_size(ctx, p):
+    """One lane per key updates only the live words of f, g, v and r in each
+    segment of divsteps; at N = 65536 every key equals the four-lane form's
+    (full-width words) and 64 spread keys equal the oracle's."""
+    n = 65536
+    base = ctx.get_config(p)
+    try:
+        ctx.set_config(p, lanes_per_key=4, use_graph=0)
+        pk4, sk4 = ctx.batch_keygen(p, wl.SEED, 0, n)
+        a_pk, a_sk = host(pk4), host(sk4)
+        del pk4, sk4
+        ctx.set_config(p, lanes_per_key=1, retry_lanes_per_key=1)
+        pk1, sk1 = ctx.batch_keygen(p, wl.SEED, 0, n)
+        assert ctx.status() == 0
+        b_pk, b_sk = host(pk1), host(sk1)
+    finally:
+        ctx.set_config(p, **base)
+    assert np.array_equal(a_pk, b_pk) and np.array_equal(a_sk, b_sk)
+    idx = list(np.linspace(0, n - 1, 64).astype(int))
+    ref = oracle_pool.oracle_keys(wl.SEED, p, idx)
+    rpk, rsk = oracle_pool.pk_sk_arrays(ref, idx)
+    assert np.array_equal(b_pk[idx], rpk) and np.array_equal(b_sk[idx], rsk)
