@@ -135,10 +135,16 @@ def group_kernel_ops(p: int, n: int, G: int, W: int) -> dict:
 
 
 def r3_kernel_ops(p: int, keys: int) -> float:
-    """Algorithmic 32-bit lane-ops of the bitsliced R/3 divsteps: per key,
-    2p-1 divsteps x ceil((p+1)/32) words x 18 ops (two F_3 scalar
-    multiply-adds at 5 ops, two 2-plane selects, two 2-plane shifts)."""
-    return float(keys) * (2 * p - 1) * ceil_div(p + 1, 32) * 18
+    """Algorithmic 32-bit lane-ops of the bitsliced R/3 divsteps: per key and
+    divstep j (of 2p-1), 9 ops per live word of the (f, g) pair and 9 per
+    live word of the (v, r) pair (an F_3 scalar multiply-add at 5 ops, a
+    2-plane select, a 2-plane shift).  Live: f and g words holding the
+    min(p+1, 2p-1-j) coefficients the remaining steps read; v and r words
+    holding degree <= j+1.  Layouts with several lanes per key also update
+    the dead words; that work is not counted."""
+    words = ceil_div(p + 1, 32)
+    live = sum(ceil_div(min(p + 1, 2 * p - 1 - j), 32) + min(words, ceil_div(j + 2, 32)) for j in range(2 * p - 1))
+    return float(keys) * 9 * live
 
 
 def short_kernel_ops(p: int, keys: int) -> float:

@@ -38,7 +38,7 @@ import time
 
 GROUP_SIZES = (8, 16, 32, 64, 128)
 SHARES = (1, 2, 4, 8)
-PHASE1_LANES = (2, 4)   # R/3 lanes per key timed jointly with (G, W)
+PHASE1_LANES = (1, 2, 4)   # R/3 lanes per key timed jointly with (G, W)
 KNOBS = ("group_size", "inverse_share", "lanes_per_key", "retry_passes", "retry_lanes_per_key",
          "retry_parallel_attempts", "persistent")
 # (G, W, lanes per key) settings timed for the persistent fused form
@@ -74,7 +74,7 @@ def group_candidates(p: int, n: int):
 
 def r3_candidates(p: int):
     """R/3 knob settings worth timing for degree p."""
-    lpks = (2, 4, 8) if p > 800 else (1, 2, 4, 8)   # one lane per key spills for large p
+    lpks = (1, 2, 4, 8)
     # (retry passes, retry lanes per key, attempts side by side)
     retry = [(1, 8, 4)] if p not in (653, 1277) else [(1, 8, 2), (1, 8, 4), (1, 8, 8), (0, 8, 4), (1, 4, 4)]
     return [{"lanes_per_key": l, "retry_passes": r, "retry_lanes_per_key": rl, "retry_parallel_attempts": ra}
@@ -103,9 +103,10 @@ MODES = ("auto", "eager", "graph")
 
 
 def _key(device_name: str, p: int, n: int, mode: str = "auto") -> str:
-    # v4: entries carry inverse_share, the launch form (eager / graph) and
-    # the kernel form (stage pipeline / persistent fused kernel)
-    return "%s|p=%d|n<=%d|%s|v4" % (device_name, p, bucket(n), mode)
+    # v5: entries carry inverse_share, the launch form (eager / graph) and
+    # the kernel form (stage pipeline / persistent fused kernel); one lane per
+    # key (live-word divsteps) among the phase-1 layouts
+    return "%s|p=%d|n<=%d|%s|v5" % (device_name, p, bucket(n), mode)
 
 
 def load_cache(path: str | None = None) -> dict:

@@ -270,6 +270,11 @@ int enqueue_keygen(ntrup_ctx* ctx, const ntrup_config& cfg, const Seed& seed, ui
                 if constexpr (P != 1277) hipLaunchKernelGGL((keygen_prefix_kernel<P, 8>), grid, blk, 0, sp, g, w.tinv);
                 break;
         }
+        // with a side stream, the back-substitution (which needs only f) runs
+        // there too, and only h = g c and the encoding follow the R/3 stage
+        if (side)
+            hipLaunchKernelGGL((keygen_cinv_kernel<P>), dim3(grid_for(n, cfg.group_size)), dim3(64), 0, sp, g,
+                               (const int16_t*)w.tinv);
     }
     mark(2, sp);
     if (side && !r3_first) NTRUP_HIP(ctx, hipEventRecord(ctx->side_join, ss));
@@ -355,7 +360,9 @@ int enqueue_keygen(ntrup_ctx* ctx, const ntrup_config& cfg, const Seed& seed, ui
     mark(4, sr);
     if (r3_first) NTRUP_HIP(ctx, hipEventRecord(ctx->side_join, ss));
     if (side) NTRUP_HIP(ctx, hipStreamWaitEvent(st, ctx->side_join, 0));
-    if (mfma) {
+    if (mfma && side) {
+        hipLaunchKernelGGL((keygen_h_kernel<P>), dim3((unsigned)n), dim3(64), 0, st, g);
+    } else if (mfma) {
         hipLaunchKernelGGL((keygen_back_kernel<P>), dim3(grid_for(n, cfg.group_size)), dim3(64), 0, st, g,
                            (const int16_t*)w.tinv);
     } else {

@@ -14,6 +14,11 @@
 // keygen_back_kernel<P>: one wave per group:
 //   3. back-substitution from t = 1/P: c_i = t b_{i-1} (= 1/(3f_i)),
 //      t <- t 3f_i, h_i = g_i c_i, then encoding.
+// Or step 3 in two kernels, so that the part that needs only f runs beside
+// the R/3 stage too:
+// keygen_cinv_kernel<P>: one wave per group: c_i and t as above, each c_i
+//   written to HBM over the prefix row b_i (already consumed);
+// keygen_h_kernel<P>: one wave per key: h_i = g_i c_i and encoding.
 // Every product is mfma_mul with the running value as Toeplitz operand.
 //
 // Latency: the next key's operands (the f row, the stored prefix row, the
@@ -257,6 +262,120 @@ __device__ __forceinline__ void kg_back_step(const GroupArgs& args, KgWave<P>& L
     mfma_mul<P, false>(CL, CH, L.HG, nullptr, L.Cb, nullptr, nullptr, nullptr);     // h = g c_i
     wave_sync();
     kg_encode<P>(key, L.Cb, cur, args.pk, args.sk);
+}
+
+// Reversed Toeplitz limbs of a big operand held in registers (the layout of
+// KgRegs::b): TL[Z0 - m] = lo(x_m), TH likewise.  Entries outside [0, p) are
+// left as they are (zero).
+template <int P>
+__device__ __forceinline__ void kg_put_toeplitz16(const uint32_t (&w)[KgShape<P>::NU][2], uint8_t* TL, uint8_t* TH) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int u = 0; u < KgShape<P>::NU; u++) {
+        const int m0 = 4 * lane + 256 * u;
+        if (m0 >= P) continue;
+        uint32_t lo = 0, hi = 0;
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+            uint32_t l, h;
+            split_limb((int32_t)(int16_t)(w[u][e >> 1] >> (16 * (e & 1))), l, h);
+            lo |= l << (8 * (3 - e));
+            hi |= h << (8 * (3 - e));
+        }
+        *(uint32_t*)(TL + MfShape<P>::Z0 - m0 - 3) = lo;
+        *(uint32_t*)(TH + MfShape<P>::Z0 - m0 - 3) = hi;
+    }
+}
+
+// One step of the back-substitution alone, for key kw0 + i - 1 (i >= 1):
+// c_i to the key's row of bscr (which held b_i, read one step earlier),
+// t <- t 3f_i.  On entry TL/TH hold the limbs of t = 1/b_i.
+template <int P>
+__device__ __forceinline__ void kg_cinv_step(const GroupArgs& args, KgWave<P>& L, int kw0, int i, KgRegs<P>& cur,
+                                             KgRegs<P>& nxt) {
+    using S = MfShape<P>;
+    const int key = kw0 + i - 1;
+    int16_t* row = args.bscr + (size_t)key * P;
+    if (i > 1) {
+        kg_put_3f<P>(cur, L.HS);
+        kg_put_b<P>(cur, L.HL, L.HH);
+        kg_load_f<P>(args.f_rows, key - 1, nxt);
+        if (i > 2) kg_load_b<P>(args.bscr, key - 2, nxt);
+        wave_sync();
+        // c_i = t b_{i-1} to HBM and t <- t 3f_i in one pass over the K-steps
+        mfma_mul2_row<P>(L.TL, L.TH, L.HL, L.HH, L.HS, row, L.TL, L.TH);
+        wave_sync();
+    } else {
+        // c_1 = t
+        for (int m = lane_id(); m < P; m += 64)
+            row[m] = (int16_t)((int32_t)(int8_t)L.TL[S::Z0 - m] + 128 * (int32_t)(int8_t)L.TH[S::Z0 - m]);
+    }
+}
+
+// The back-substitution of group `group` from t = 1/P (row trow): every
+// c_i = 1/(3 f_i) of the group to HBM.  One wave.
+template <int P>
+__device__ __forceinline__ void kg_cinv_group(const GroupArgs& args, int group, const int16_t* trow, KgWave<P>& L) {
+    using S = MfShape<P>;
+    const int kw0 = group * args.G;
+    const int gsz = max(0, min(args.G, args.n - kw0));
+    if (gsz <= 0) return;
+    kg_zero<P>(L.HL, S::HLEN);
+    kg_zero<P>(L.HH, S::HLEN);
+    kg_zero<P>(L.HS, S::HLEN);
+    KgRegs<P> ra, rb;
+    kg_load_f<P>(args.f_rows, kw0 + gsz - 1, ra);
+    if (gsz >= 2) kg_load_b<P>(args.bscr, kw0 + gsz - 2, ra);
+    for (int j = lane_id(); j < P; j += 64) L.Bb[j] = trow[j];
+    wave_sync();
+    build_toeplitz<P>(L.Bb, L.TL, L.TH);
+    wave_sync();
+    for (int i = gsz; i >= 1; i -= 2) {
+        kg_cinv_step<P>(args, L, kw0, i, ra, rb);
+        if (i >= 2) kg_cinv_step<P>(args, L, kw0, i - 1, rb, ra);
+    }
+}
+
+template <int P>
+__global__ __launch_bounds__(64, (P < 800 ? 2 : 1)) void keygen_cinv_kernel(GroupArgs args, const int16_t* tinv) {
+    __shared__ KgWave<P> L;
+    // on the side stream beside the R/3 stage, like the prefix kernel
+    __builtin_amdgcn_s_setprio(3);
+    kg_cinv_group<P>(args, (int)blockIdx.x, tinv + (size_t)blockIdx.x * P, L);
+}
+
+// Per-wave LDS of the h kernel.
+template <int P>
+struct KgHWave {
+    using S = MfShape<P>;
+    __attribute__((aligned(16))) uint8_t TL[S::TLEN];   // Toeplitz limbs of c
+    __attribute__((aligned(16))) uint8_t TH[S::TLEN];
+    __attribute__((aligned(16))) uint8_t HG[S::HLEN];   // g
+    __attribute__((aligned(16))) int16_t Cb[RqShape<P>::JP];  // h
+};
+
+// h = g c for one key per wave (c = 1/(3f) from the key's row of bscr), then
+// the encoding of pk and sk.
+template <int P>
+__global__ __launch_bounds__(64) void keygen_h_kernel(GroupArgs args) {
+    using S = MfShape<P>;
+    __shared__ KgHWave<P> L;
+    const int key = (int)blockIdx.x;
+    if (key >= args.n) return;
+    KgRegs<P> r;
+    kg_load_b<P>(args.bscr, key, r);
+    kg_load_f<P>(args.f_rows, key, r);
+    kg_load_bits<P>(args.gbits, args.ibits, args.n, key, r);
+    kg_zero<P>(L.TL, S::TLEN);
+    kg_zero<P>(L.TH, S::TLEN);
+    kg_zero<P>(L.HG, S::HLEN);
+    wave_sync();
+    kg_put_toeplitz16<P>(r.b, L.TL, L.TH);
+    kg_put_g<P>(r, L.HG);
+    wave_sync();
+    mfma_mul<P, false>(L.TL, L.TH, L.HG, nullptr, L.Cb, nullptr, nullptr, nullptr);
+    wave_sync();
+    kg_encode<P>(key, L.Cb, r, args.pk, args.sk);
 }
 
 // Per-wave LDS of the prefix kernel (no c_i or g operands).

@@ -545,6 +545,44 @@ __device__ __forceinline__ void mfma_fix_store(uint32_t (&out)[MfShape<P>::NT][2
     }
 }
 
+// The coefficients of a product held as mfma_tiles returns it, after the
+// correction of c_0, to a global int16 row.
+template <int P>
+__device__ __forceinline__ void mfma_fix_row(uint32_t (&out)[MfShape<P>::NT][2], int32_t ap, int32_t bp, int16_t* row) {
+    using S = MfShape<P>;
+    constexpr int Q = S::Q;
+    const int lane = lane_id();
+    const int32_t cp = (int32_t)(int16_t)(__builtin_amdgcn_readlane((int)out[S::TP][0], S::LP) & 0xFFFF);
+    const int32_t c0 = freeze<Q>((int32_t)(int16_t)(out[0][0] & 0xFFFFu) - cp + ap * bp);
+    if (lane == 0) out[0][0] = (out[0][0] & 0xFFFF0000u) | (uint32_t)(uint16_t)c0;
+    const int rc = lane & 15, g = lane >> 4;
+#pragma unroll
+    for (int t = 0; t < S::NT; t++) {
+        const int i = 256 * t + 16 * rc + 4 * g;
+        if (i >= P) continue;
+#pragma unroll
+        for (int e = 0; e < 4; e++)
+            if (i + e < P) row[i + e] = (int16_t)((e < 2 ? out[t][0] : out[t][1]) >> (16 * (e & 1)));
+    }
+}
+
+// c1 = a b1 (big b1: HL, HH) to the global int16 row row1 and c2 = a b2
+// (small b2: HS) to the Toeplitz limbs U2L/U2H (which may be TL/TH).
+template <int P>
+__device__ __forceinline__ void mfma_mul2_row(const uint8_t* TL, const uint8_t* TH, const uint8_t* HL,
+                                              const uint8_t* HH, const uint8_t* HS, int16_t* row1, uint8_t* U2L,
+                                              uint8_t* U2H) {
+    using S = MfShape<P>;
+    const int32_t ap = (int32_t)(int8_t)TL[S::Z0 - (P - 1)] + 128 * (int32_t)(int8_t)TH[S::Z0 - (P - 1)];
+    const int32_t bp1 = (int32_t)(int8_t)HL[S::HOFF + P - 1] + 128 * (int32_t)(int8_t)HH[S::HOFF + P - 1];
+    const int32_t bp2 = (int32_t)(int8_t)HS[S::HOFF + P - 1];
+    uint32_t out1[S::NT][2], out2[S::NT][2];
+    mfma_chunks2<P, 0>(TL, TH, HL, HH, HS, out1, out2);
+    wave_sync();
+    mfma_fix_row<P>(out1, ap, bp1, row1);
+    mfma_fix_store<P>(out2, ap, bp2, U2L, U2H);
+}
+
 // c1 = a b1 (big b1: HL, HH) to the Toeplitz limbs U1L/U1H and c2 = a b2
 // (small b2: HS) to U2L/U2H, which may be TL/TH themselves (a replaced by
 // c2).  Wave-local like mfma_mul.

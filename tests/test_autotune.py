@@ -10,7 +10,7 @@ def test_candidates_cover_the_knobs():
     assert {c["lanes_per_key"] for c in c761} == {1, 2, 4, 8}
     assert {c["retry_passes"] for c in c761} == {1}
     c1277 = autotune.candidates(1277, 65536)
-    assert {c["lanes_per_key"] for c in c1277} == {2, 4, 8}
+    assert {c["lanes_per_key"] for c in c1277} == {1, 2, 4, 8}
     assert {c["retry_passes"] for c in c1277} == {0, 1}
     assert {c["retry_lanes_per_key"] for c in c1277} == {4, 8}
     assert {c["retry_parallel_attempts"] for c in c1277} == {2, 4, 8}
@@ -39,9 +39,10 @@ def test_cache_roundtrip(tmp_path):
     assert autotune.lookup("dev", 761, 65536, path, mode="graph") is None   # per launch form
 
 
-def test_phase1_times_group_knobs_with_both_lane_counts():
+def test_phase1_times_group_knobs_with_each_lane_count():
     c = autotune.phase1_candidates(761, 65536)
     assert {x["lanes_per_key"] for x in c} == set(autotune.PHASE1_LANES)
+    assert 1 in autotune.PHASE1_LANES   # one lane per key: the live-word divstep form
     # every (G, W) pair appears once per lane count
     pairs = [(x["group_size"], x["inverse_share"]) for x in c]
     assert len(pairs) == len(autotune.PHASE1_LANES) * len(autotune.group_candidates(761, 65536))

@@ -210,3 +210,26 @@ def test_one_lane_form_full_size(ctx, p):
     ref = oracle_pool.oracle_keys(wl.SEED, p, idx)
     rpk, rsk = oracle_pool.pk_sk_arrays(ref, idx)
     assert np.array_equal(b_pk[idx], rpk) and np.array_equal(b_sk[idx], rsk)
+
+
+@pytest.mark.parametrize("p", [653, 761, 857, 1277])
+def test_eager_split_back_substitution(ctx, p):
+    """Eager launches of one job run the back-substitution (c_i = 1/(3f_i),
+    written over the consumed prefix rows) on the side stream beside the R/3
+    stage and h = g c with the encoding after it; every key equals the
+    oracle's for ragged groups, several shares and lane layouts, and the
+    graph form (one fused back-substitution kernel) gives the same bytes."""
+    n = 200
+    ref = oracle_pool.oracle_keys(wl.SEED, p, range(n))
+    rpk, rsk = oracle_pool.pk_sk_arrays(ref, range(n))
+    base = ctx.get_config(p)
+    try:
+        for G, W, L in [(1, 1, 1), (7, 2, 2), (32, 4, 1), (64, 4, 4), (13, 2, 1), (200, 1, 2)]:
+            for graph in (0, 1):
+                ctx.set_config(p, product_engine=1, persistent=0, r3_batch=0, use_graph=graph, group_size=G,
+                               inverse_share=W, lanes_per_key=L)
+                pk, sk = ctx.batch_keygen(p, wl.SEED, 0, n)
+                assert ctx.status() == 0
+                assert np.array_equal(host(pk), rpk) and np.array_equal(host(sk), rsk), (G, W, L, graph)
+    finally:
+        ctx.set_config(p, **base)
