@@ -42,8 +42,19 @@ struct ShortShape {
     static constexpr int EPL = NS / 64;                 // elements per lane
 };
 
+// med3(a, b, 0) = min(a, b) and med3(a, b, ~0) = max(a, b) for unsigned
+// words: one v_med3_u32 does a compare-exchange half whose direction is a
+// per-lane value.
+__device__ __forceinline__ uint32_t med3_u32(uint32_t a, uint32_t b, uint32_t c) {
+    uint32_t r;
+    asm("v_med3_u32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+    return r;
+}
+
 // Bitonic sort of 64*EPL words held blocked across the wave (lane l holds
-// elements [EPL*l, EPL*l + EPL)), ascending.  Branch-free min/max only.
+// elements [EPL*l, EPL*l + EPL)), ascending.  Branch-free: every
+// compare-exchange half is a med3 against 0 (keep the smaller) or ~0 (keep
+// the larger).
 template <int EPL>
 __device__ __forceinline__ void bitonic_sort_wave(uint32_t (&L)[EPL], int lane) {
     constexpr int NS = 64 * EPL;
@@ -52,13 +63,15 @@ __device__ __forceinline__ void bitonic_sort_wave(uint32_t (&L)[EPL], int lane) 
 #pragma unroll
         for (int j = k >> 1; j > 0; j >>= 1) {
             if (j >= EPL) {
-                const int lj = j / EPL;
+                // partner in lane ^ (j / EPL), same slot; the side (lower or
+                // upper of the pair) and the direction depend on the lane only
+                const int lj = j / EPL, i0 = lane * EPL;
+                const bool keep_min = ((i0 & j) == 0) == ((i0 & k) == 0);
+                const uint32_t c = keep_min ? 0u : 0xFFFFFFFFu;
 #pragma unroll
                 for (int e = 0; e < EPL; e++) {
                     const uint32_t o = (uint32_t)__shfl_xor((int)L[e], lj);
-                    const int i = lane * EPL + e;
-                    const bool keep_min = ((i & j) == 0) == ((i & k) == 0);
-                    L[e] = keep_min ? min(L[e], o) : max(L[e], o);
+                    L[e] = med3_u32(L[e], o, c);
                 }
             } else {
 #pragma unroll
@@ -66,10 +79,10 @@ __device__ __forceinline__ void bitonic_sort_wave(uint32_t (&L)[EPL], int lane) 
                     if ((e & j) == 0) {
                         const int e2 = e | j;
                         const bool up = ((lane * EPL + e) & k) == 0;
+                        const uint32_t c = up ? 0u : 0xFFFFFFFFu;
                         const uint32_t a = L[e], b = L[e2];
-                        const uint32_t lo = min(a, b), hi = max(a, b);
-                        L[e] = up ? lo : hi;
-                        L[e2] = up ? hi : lo;
+                        L[e] = med3_u32(a, b, c);
+                        L[e2] = med3_u32(a, b, ~c);
                     }
                 }
             }
