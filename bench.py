@@ -112,21 +112,28 @@ def ceil_div(a, b):
     return -(-a // b)
 
 
-def group_kernel_ops(p: int, n: int, G: int, W: int) -> dict:
-    """Algorithmic int8 matrix-core operations (2 per multiply-add) of the two
-    Montgomery group kernels for n keys.  A ring product is p*p schoolbook
+def group_kernel_ops(p: int, n: int, G: int, W: int, split: bool = False) -> dict:
+    """Algorithmic int8 matrix-core operations (2 per multiply-add) of the
+    Montgomery group stages for n keys.  A ring product is p*p schoolbook
     multiply-adds per pair of int8 limbs: 2 limb pairs when one operand is
     small (3f_i, g_i), 4 when both are residues.  Prefix kernel, per group of
     g keys: g-1 prefix products (small); per W groups: 3(W-1) big products of
     the shared reciprocal (the divstep reciprocal itself runs on the vector
-    ALUs and is not counted).  Back kernel, per group: g-1 products c_i (big),
-    g-1 t_i updates and g products h_i (small)."""
+    ALUs and is not counted).  Back-substitution, per group: g-1 products c_i
+    (big), g-1 t_i updates and g products h_i (small).  split: eager launches
+    with a side stream run the c_i and t_i products there after the prefix
+    kernel (group_prefix), and only the h_i products after the R/3 stage
+    (group_back, keygen_h_kernel)."""
     pre = back = 0.0
     groups = 0
     for start in range(0, n, G):
         g = min(G, n - start)
         pre += (g - 1) * 2 * p * p
-        back += ((g - 1) * 4 + (g - 1) * 2 + g * 2) * p * p
+        if split:
+            pre += ((g - 1) * 4 + (g - 1) * 2) * p * p
+            back += g * 2 * p * p
+        else:
+            back += ((g - 1) * 4 + (g - 1) * 2 + g * 2) * p * p
         groups += 1
     for start in range(0, groups, W):
         w = min(W, groups - start)
@@ -286,7 +293,10 @@ def main():
 
     avg = {k: v / K for k, v in stage_ms.items()}
     assert cfg["product_engine"] == 1, "the roofline below prices the matrix-core group kernel"
-    ops = dict(group_kernel_ops(p, n, cfg["group_size"], cfg["inverse_share"]),
+    # eager single-job launches use the side stream (prefix kernel and
+    # back-substitution beside the R/3 stage); captured graphs run one stream
+    split = not cfg["use_graph"] and not cfg.get("persistent")
+    ops = dict(group_kernel_ops(p, n, cfg["group_size"], cfg["inverse_share"], split),
                r3_main=r3_kernel_ops(p, n), sample_short=short_kernel_ops(p, n))
     # the persistent fused kernel does all of it; priced on its vector-ALU work
     # (R/3 divsteps and sampling), its matrix-core work being the smaller share
@@ -316,7 +326,7 @@ def main():
         dom = max(crit, key=lambda k: avg[k])
     achieved = ops[dom] / (avg[dom] / 1e3)
     kernel_names = {"group_prefix": "keygen_prefix_kernel<%d,%d>" % (p, cfg["inverse_share"]),
-                    "group_back": "keygen_back_kernel<%d>" % p,
+                    "group_back": ("keygen_h_kernel<%d>" if split else "keygen_back_kernel<%d>") % p,
                     "r3_main": "r3_kernel<%d,%d>" % (p, cfg["lanes_per_key"]),
                     "sample_short": "sample_short_kernel<%d>" % p,
                     "fused": "keygen_persistent_kernel<%d,%d>" % (cfg["lanes_per_key"], p)}

@@ -361,7 +361,8 @@ int enqueue_keygen(ntrup_ctx* ctx, const ntrup_config& cfg, const Seed& seed, ui
     if (r3_first) NTRUP_HIP(ctx, hipEventRecord(ctx->side_join, ss));
     if (side) NTRUP_HIP(ctx, hipStreamWaitEvent(st, ctx->side_join, 0));
     if (mfma && side) {
-        hipLaunchKernelGGL((keygen_h_kernel<P>), dim3((unsigned)n), dim3(64), 0, st, g);
+        const unsigned per = grid_for(n, 8);
+        hipLaunchKernelGGL((keygen_h_kernel<P>), dim3(8 * per), dim3(64), 0, st, g, (int)per);
     } else if (mfma) {
         hipLaunchKernelGGL((keygen_back_kernel<P>), dim3(grid_for(n, cfg.group_size)), dim3(64), 0, st, g,
                            (const int16_t*)w.tinv);

@@ -355,12 +355,15 @@ struct KgHWave {
 };
 
 // h = g c for one key per wave (c = 1/(3f) from the key's row of bscr), then
-// the encoding of pk and sk.
+// the encoding of pk and sk.  Workgroups go to the eight XCDs in turn, and
+// the g and 1/g words of 32 consecutive keys share a cache line (key-minor
+// planes), so XCD x takes the contiguous key range [x per, (x+1) per): grid
+// 8 per, block b -> key (b mod 8) per + b / 8.
 template <int P>
-__global__ __launch_bounds__(64) void keygen_h_kernel(GroupArgs args) {
+__global__ __launch_bounds__(64) void keygen_h_kernel(GroupArgs args, int per) {
     using S = MfShape<P>;
     __shared__ KgHWave<P> L;
-    const int key = (int)blockIdx.x;
+    const int key = (int)(blockIdx.x & 7u) * per + (int)(blockIdx.x >> 3);
     if (key >= args.n) return;
     KgRegs<P> r;
     kg_load_b<P>(args.bscr, key, r);
