@@ -46,13 +46,17 @@ struct R3Shape {
 
 // Lane-group helpers.  A key owns LPK consecutive lanes (LPK divides 16, so a
 // group never straddles a DPP row); group_first broadcasts the value of the
-// group's first lane: DPP quad permutes for LPK <= 4, ds_bpermute beyond.
+// group's first lane with DPP moves: a quad permute for LPK <= 4; for LPK = 8
+// the quad broadcast followed by row_shr:4 written into banks 1 and 3 only
+// (lanes 4-7 and 12-15 of each row take the broadcast of the quad below,
+// lanes 0-3 and 8-11 keep their own).
 template <int LPK>
 __device__ __forceinline__ uint32_t group_first(uint32_t x) {
     if (LPK == 1) return x;
     if (LPK == 2) return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0xA0, 0xF, 0xF, true);  // [0,0,2,2]
-    if (LPK == 4) return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x00, 0xF, 0xF, true);  // [0,0,0,0]
-    return (uint32_t)__shfl((int)x, (int)(threadIdx.x & 63) & ~(LPK - 1));
+    const int q = __builtin_amdgcn_mov_dpp((int)x, 0x00, 0xF, 0xF, true);                  // [0,0,0,0]
+    if (LPK == 4) return (uint32_t)q;
+    return (uint32_t)__builtin_amdgcn_update_dpp(q, q, 0x114, 0xF, 0xA, false);             // row_shr:4
 }
 // lane i reads lane i+1 / lane i-1 within its row of 16 (row_shl:1 / row_shr:1);
 // a pair never straddles a row, and the caller masks the lane that must read 0
