@@ -84,7 +84,9 @@ const char *ntrup_strerror(int code);
  *   group_size           Montgomery group size G, 1..1024 (Section 2.2's n)
  *   lanes_per_key        1, 2, 4 or 8 lanes per key for the main R/3 pass
  *                        (more lanes: fewer registers and lower latency per
- *                        key, more cross-lane overhead)
+ *                        key, more cross-lane overhead; one lane per key
+ *                        also skips the words of f, g, v, r that no later
+ *                        divstep reads, about a fifth of the work)
  *   retry_lanes_per_key  1, 2, 4 or 8 lanes per key for the retry passes,
  *                        which are latency-bound (few keys, a full divstep
  *                        run each)
@@ -97,8 +99,10 @@ const char *ntrup_strerror(int code);
  *   use_graph            replay the pipeline from a captured hipGraph when
  *                        the call's arguments repeat; a captured pipeline
  *                        runs its stages on one stream, while eager launches
- *                        of a single job overlap the prefix kernel with the
- *                        R/3 stage on a second stream
+ *                        of a single job run the prefix products, the shared
+ *                        reciprocals and the back-substitution (which need
+ *                        only f) on a second stream beside the R/3 stage, and
+ *                        only h = g/(3f) and the encoding after it
  *   product_engine       R/q products on the vector units (0: v_dot2 Toeplitz
  *                        dot products) or on the int8 matrix cores (1: block
  *                        Toeplitz MFMA with two 7-bit limbs); both exact

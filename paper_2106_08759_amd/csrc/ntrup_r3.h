@@ -1,5 +1,5 @@
 // Per-key reciprocal in R/3 = (Z/3)[x]/(x^p - x - 1) by constant-time
-// divsteps, bitsliced, one key per lane (or per pair of lanes).
+// divsteps, bitsliced, one key per lane or per group of 2, 4 or 8 lanes.
 //
 // KeyGen (OpenSSLNTRU paper, Section 3.1) needs 1/g in R/3 and needs g to be
 // invertible; the paper notes that earlier NTRU Prime software obtained
