@@ -194,13 +194,26 @@ __device__ __forceinline__ void kg_encode(int key, const int16_t* H, const KgReg
                                           uint8_t* sk_out) {
     constexpr int Q = Param<P>::q;
     constexpr int PKB = pk_bytes(P), SKH = sk_half_bytes(P);
+    constexpr int NO = ceil_div(P, 8);   // octets of coefficients: 8 fields of 13 bits = 13 bytes
+    static_assert(8 * NO <= RqShape<P>::JP, "octet reads stay inside the LDS row");
     const int lane = lane_id();
     uint8_t* pk = pk_out + (size_t)key * PKB;
-    for (int b = lane; b < PKB; b += 64) {
-        const int bit = 8 * b, i0 = bit / 13, o = bit - 13 * i0;
-        const uint32_t v0 = (uint32_t)(H[i0] + (Q - 1) / 2);
-        const uint32_t v1 = (i0 + 1 < P) ? (uint32_t)(H[i0 + 1] + (Q - 1) / 2) : 0u;
-        pk[b] = (uint8_t)((v0 | (v1 << 13)) >> o);
+    for (int k = lane; k < NO; k += 64) {
+        const uint4 hv = *(const uint4*)(H + 8 * k);
+        const uint32_t hw[4] = {hv.x, hv.y, hv.z, hv.w};
+        const int c = min(8, P - 8 * k);   // live coefficients of the octet
+        uint32_t u[8];
+#pragma unroll
+        for (int e = 0; e < 8; e++)
+            u[e] = (e < c) ? (uint32_t)((int32_t)(int16_t)(hw[e >> 1] >> (16 * (e & 1))) + (Q - 1) / 2) : 0u;
+        // field e at bits [13e, 13e + 13) of the octet's 104-bit little-endian string
+        const uint32_t w[4] = {u[0] | (u[1] << 13) | (u[2] << 26), (u[2] >> 6) | (u[3] << 7) | (u[4] << 20),
+                               (u[4] >> 12) | (u[5] << 1) | (u[6] << 14) | (u[7] << 27), u[7] >> 5};
+        const int nb = (13 * c + 7) / 8;
+        uint8_t* dst = pk + 13 * k;
+#pragma unroll
+        for (int b = 0; b < 13; b++)
+            if (b < nb) dst[b] = (uint8_t)(w[b >> 2] >> (8 * (b & 3)));
     }
     uint8_t* sk = sk_out + (size_t)key * 2 * SKH;
 #pragma unroll
