@@ -226,7 +226,7 @@ def main():
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(keys shard with no exchange step; see the design notes)", file=sys.stderr)
+              "(keys shard with no exchange step: each GPU would run its own key range)", file=sys.stderr)
         sys.exit(2)
 
     # the CPU oracle runs first, in forked workers, before this process touches the GPU
