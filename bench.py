@@ -225,7 +225,7 @@ def main():
         return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(keys shard with no exchange step: each GPU would run its own key range)", file=sys.stderr)
         sys.exit(2)
 
