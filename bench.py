@@ -416,6 +416,7 @@ def main():
         assert ctx.status() == 0
         pf_ms = e0.elapsed_time(e1) / 5
         extras["persistent_fused"] = {"keys_per_s": round(n / pf_ms * 1e3, 1), "ms": round(pf_ms, 3),
+                                      "speedup_over_plain": round(n / pf_ms * 1e3 / plain, 1),
                                       "config": {k: pcfg[k] for k in ("group_size", "inverse_share", "lanes_per_key")}}
         ctx.set_config(p, **saved)
         # the paper's own form of Algorithm 1 for the R/3 side: g screened for
