@@ -9,14 +9,18 @@ value     keys/s over the timed steps (inputs: a 32-byte seed; outputs stay in
           HBM; no host copies inside the timed region)
 roofline  the dominant kernel's algorithmic integer ops per launch divided by
           its average launch time, measured with HIP events recorded on the
-          launch stream during the timed steps.  Peaks: 78.6 T int32
-          lane-ops/s for the vector-ALU kernels (256 CU x 4 SIMD x 32 lanes x
-          2.4 GHz, the rate of the published fp32 vector peak; R/3 divsteps,
-          Short sampling); 5.0 P int8 ops/s for the Montgomery group kernel,
-          whose R/q products run on the int8 matrix cores.  traffic: HBM bytes
-          per launch from the committed counter summary, null once the kernel
-          sources differ from the ones it was measured on
-cpu_baseline  the CPU oracle (plain C, -O2) on the host cores, bounded sample
+          launch stream during the timed steps.  Peaks: 39.3 T int32
+          lane-ops/s for the vector-ALU kernels (256 CU x 4 SIMD x 16 lanes x
+          2.4 GHz: a wave64 int32 instruction occupies its SIMD for 4 clocks;
+          R/3 divsteps, Short sampling); 5.0 P int8 ops/s for the Montgomery
+          group kernels, whose R/q products run on the int8 matrix cores.
+          traffic / issued: HBM bytes and VALU instructions per launch from the
+          committed counter summary, null once the kernel sources differ from
+          the ones they were measured on
+cpu_baseline  the CPU oracle (plain C, -O2) on the host cores, bounded sample;
+          its keys include 64 spread over the timed workload, against which
+          the timed output is checked byte for byte (no value is printed on a
+          mismatch)
 """
 from __future__ import annotations
 
@@ -30,9 +34,12 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# 256 CUs x 4 SIMDs x 32 lanes per clock x 2.4 GHz: the rate behind the
-# published 157.3 TFLOP/s fp32 vector peak (78.6 T FMA/s), applied to int32
-VALU_PEAK = 256 * 4 * 32 * 2.4e9   # int32 lane-ops per second
+# 256 CUs x 4 SIMDs x 16 lanes per clock x 2.4 GHz: a wave64 int32 VALU
+# instruction occupies its SIMD for 4 clocks.  (The published 157.3 TFLOP/s
+# fp32 vector peak is this rate x 2 flops per FMA x 2 for packed fp32; int32
+# has neither.)  Measured issue rates stay at or below it (calibration in
+# profiles/valu_issue_rate.md).
+VALU_PEAK = 256 * 4 * 16 * 2.4e9   # int32 lane-ops per second = 39.3 T
 I8_MFMA_PEAK = 5.0e15              # dense int8 matrix-core ops per second (2 per multiply-add)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.json")
 
@@ -50,10 +57,11 @@ def sources_digest() -> str:
     return h.hexdigest()
 
 
-def stored_traffic(kernel: str):
-    """HBM bytes per launch of `kernel` from the committed counter summary
-    (FETCH_SIZE and WRITE_SIZE scaled by a plain-copy calibration), or None
-    when there is none or the kernel sources changed since it was taken."""
+def stored_counter(kernel: str, field: str = "bytes_per_launch"):
+    """A per-launch figure of `kernel` from the committed counter summary:
+    bytes_per_launch (FETCH_SIZE and WRITE_SIZE scaled by a plain-copy
+    calibration) or valu_insts (SQ_INSTS_VALU, wave instructions); None when
+    there is none or the kernel sources changed since it was taken."""
     try:
         with open(TRAFFIC_FILE) as fh:
             data = json.load(fh)
@@ -62,7 +70,11 @@ def stored_traffic(kernel: str):
     if data.get("sources_sha256") != sources_digest():
         return None
     entry = data.get("kernels", {}).get(kernel)
-    return None if entry is None else entry["bytes_per_launch"]
+    return None if entry is None else entry.get(field)
+
+
+def stored_traffic(kernel: str):
+    return stored_counter(kernel, "bytes_per_launch")
 
 
 def kernel_key(name: str) -> str:
@@ -71,7 +83,7 @@ def kernel_key(name: str) -> str:
     return base.replace(" ", "")
 
 
-def summarize_counters(directory: str, copy_mib: int, workload: str) -> dict:
+def summarize_counters(directory: str, copy_mib: int, workload: str, steps_per_run: int = 0) -> dict:
     """profiles/hbm_traffic.json from two rocprofv3 --pmc runs of bench.py with
     --calib-copy-mib: <directory>/fetch and <directory>/write, each holding
     pmc_counter_collection.csv (FETCH_SIZE, WRITE_SIZE in KiB per dispatch).
@@ -88,6 +100,13 @@ def summarize_counters(directory: str, copy_mib: int, workload: str) -> dict:
                     continue
                 key = kernel_key(row["Kernel_Name"])
                 per.setdefault(key, {}).setdefault(which, []).append(float(row["Counter_Value"]))
+    sq = os.path.join(directory, "sq", "pmc_counter_collection.csv")
+    if os.path.exists(sq):
+        with open(sq) as fh:
+            for row in csv.DictReader(fh):
+                if row["Counter_Name"] in ("SQ_INSTS_VALU", "SQ_INSTS_MFMA", "SQ_INSTS_SALU", "SQ_INSTS_LDS"):
+                    key = kernel_key(row["Kernel_Name"])
+                    per.setdefault(key, {}).setdefault(row["Counter_Name"], []).append(float(row["Counter_Value"]))
     copy = per.get("__amd_rocclr_copyBuffer")
     if not copy or "fetch" not in copy or "write" not in copy:
         raise SystemExit("no calibration copy in %s (run bench.py with --calib-copy-mib)" % directory)
@@ -101,11 +120,16 @@ def summarize_counters(directory: str, copy_mib: int, workload: str) -> dict:
         f = sum(d["fetch"]) / len(d["fetch"])
         w = sum(d["write"]) / len(d["write"])
         kernels[key] = {"fetch_kib_raw": round(f, 2), "write_kib_raw": round(w, 2),
-                        "bytes_per_launch": int(round((f * fs + w * ws) * 1024))}
+                        "bytes_per_launch": int(round((f * fs + w * ws) * 1024)),
+                        "launches_per_run": len(d["fetch"])}
+        for c, field in (("SQ_INSTS_VALU", "valu_insts"), ("SQ_INSTS_MFMA", "mfma_insts"),
+                         ("SQ_INSTS_SALU", "salu_insts"), ("SQ_INSTS_LDS", "lds_insts")):
+            if c in d:
+                kernels[key][field] = round(sum(d[c]) / len(d[c]), 1)
     return {"sources_sha256": sources_digest(),
             "calibration": {"copy_mib": copy_mib, "fetch_kib": round(cal_f, 2), "write_kib": round(cal_w, 2),
                             "fetch_scale": round(fs, 4), "write_scale": round(ws, 4)},
-            "workload": workload, "kernels": kernels}
+            "workload": workload, "steps_per_run": steps_per_run, "kernels": kernels}
 
 
 def ceil_div(a, b):
@@ -155,39 +179,112 @@ def r3_kernel_ops(p: int, keys: int) -> float:
 
 
 def short_kernel_ops(p: int, keys: int) -> float:
-    """ChaCha20 blocks (20 rounds x 4 quarter-rounds x 12 ops + 32) for the f
-    stream plus the bitonic network's compare-exchanges (2 ops each)."""
-    ns = 1024 if p <= 1024 else 2048
+    """ChaCha20 blocks the f stream needs (ceil(p/16) of 16 words; 20 rounds x
+    4 quarter-rounds x 12 ops + 32 per block) plus the compare-exchanges of
+    the bitonic network on the next power of two of p words (2 ops each)."""
+    ns = 1 << (p - 1).bit_length()
     lg = ns.bit_length() - 1
     ce = ns // 2 * lg * (lg + 1) // 2
-    blocks = ns // 16
+    blocks = ceil_div(p, 16)
     return float(keys) * (blocks * (20 * 4 * 12 + 32) + 2 * ce)
 
 
+def check_indices(n: int, count: int = 64) -> list:
+    """Keys of the timed workload whose bytes are checked against the oracle:
+    the first, the last and evenly spread ones in between."""
+    return sorted({round(i * (n - 1) / (count - 1)) for i in range(count)}) if n > 1 else [0]
+
+
 def _cpu_worker(args):
-    p, start, seconds = args
+    p, start, seconds, check = args
     import oracle
+    _, q, _ = oracle.PARAMS[p]
     t0 = time.perf_counter()
-    done, idx = 0, start
+    keys = {}
+    for i in check:
+        k = oracle.keygen(bytes(range(32)), p, i)
+        keys[i] = (oracle.encode_pk(k["h"], p, q), oracle.encode_sk(k["f"], k["ginv"], p))
+    done, idx = len(check), start
     while time.perf_counter() - t0 < seconds:
         oracle.keygen_range(bytes(range(32)), p, idx, 4)
         idx += 4
         done += 4
-    return done, time.perf_counter() - t0
+    return done, time.perf_counter() - t0, keys
 
 
-def cpu_baseline(p: int, seconds: float) -> dict:
+def host_cpu() -> dict:
+    """CPU model and core counts of this host."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = os.cpu_count() or 1
+    return {"model": model, "nproc": os.cpu_count() or 1, "usable": usable}
+
+
+def cpu_baseline(p: int, seconds: float, check: list) -> tuple:
+    """The oracle timed on this host's cores (one process per core, at most
+    16: the CPU share a one-GPU job is given); the keys at `check` are part of
+    the sample.  Returns (cpu_baseline entry, {index: (pk bytes, sk bytes)})."""
     import oracle
     oracle.build()
-    cores = max(1, min(16, os.cpu_count() or 1))
+    cpu = host_cpu()
+    cores = max(1, min(16, cpu["usable"]))
     t0 = time.perf_counter()
     with mp.get_context("fork").Pool(cores) as pool:
-        res = pool.map(_cpu_worker, [(p, 10_000_000 * i, seconds) for i in range(cores)])
+        res = pool.map(_cpu_worker, [(p, 10_000_000 * (i + 1), seconds, check[i::cores]) for i in range(cores)])
     wall = time.perf_counter() - t0
     keys = sum(r[0] for r in res)
-    return {"value": round(keys / wall, 1), "unit": "keys/s", "cores": cores, "kind": "oracle",
-            "sample": "sntrup%d KeyGen, %d keys over %d processes (disjoint index ranges), %.1f s wall"
-                      % (p, keys, cores, wall)}
+    ref = {}
+    for r in res:
+        ref.update(r[2])
+    return ({"value": round(keys / wall, 1), "unit": "keys/s", "cores": cores, "kind": "oracle",
+             "cpu_model": cpu["model"], "nproc": cpu["nproc"], "usable_cpus": cpu["usable"],
+             "sample": "sntrup%d KeyGen, %d keys over %d processes (the %d checked keys of the timed workload, "
+                       "then disjoint index ranges), %.1f s wall" % (p, keys, cores, len(check), wall)},
+            ref)
+
+
+def calib_valu(iters: int = 20000, reps: int = 5) -> dict:
+    """The vector-ALU probe (csrc/calib_valu.hip): 8 independent add-xor-rotate
+    chains per lane, 24 VALU instructions per step, over 1024 x k one-wave
+    blocks (k waves per SIMD on 256 CUs x 4 SIMDs).  Reports, per k, the mean
+    launch time (HIP events) and the issue rate in lanes per clock per SIMD at
+    2.4 GHz from the source instruction count; the counter run (SQ_INSTS_VALU)
+    of the same command confirms the count."""
+    import ctypes
+    import torch
+    from paper_2106_08759_amd import build
+    L = ctypes.CDLL(build.CALIB_LIB)
+    L.calib_valu.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]
+    ops = L.calib_valu_ops_per_step()
+    out = {"iters": iters, "ops_per_lane_step": ops, "clock_ghz": 2.4, "rates": {}}
+    st = torch.cuda.current_stream()
+    for k in (1, 2, 4, 8):
+        blocks = 1024 * k
+        buf = torch.empty(blocks * 64, dtype=torch.int32, device="cuda")
+        assert L.calib_valu(blocks, iters, buf.data_ptr(), st.cuda_stream) == 0
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            assert L.calib_valu(blocks, iters, buf.data_ptr(), st.cuda_stream) == 0
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        wave_insts = blocks * iters * ops
+        out["rates"][k] = {"ms": round(ms, 4), "wave_insts": wave_insts,
+                           "lanes_per_clk_per_simd": round(wave_insts * 64 / (ms / 1e3) / 1024 / 2.4e9, 2),
+                           "T_lane_ops": round(wave_insts * 64 / (ms / 1e3) / 1e12, 2)}
+    return out
 
 
 def main():
@@ -212,16 +309,26 @@ def main():
                     help="host only: write profiles/hbm_traffic.json from DIR/fetch and DIR/write "
                          "(rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs of this script) and exit")
     ap.add_argument("--workload-note", default="", help="workload line stored with --summarize-counters")
+    ap.add_argument("--counter-steps", type=int, default=3,
+                    help="warmup + timed steps of the counter runs (--summarize-counters)")
+    ap.add_argument("--calib-valu", action="store_true",
+                    help="time the int32 vector-ALU issue-rate probe (libcalib.so) at 1, 2, 4, 8 waves per SIMD "
+                         "and exit")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one device-to-device copy of this many MiB first (HBM counter calibration)")
     args = ap.parse_args()
 
     if args.summarize_counters:
-        data = summarize_counters(args.summarize_counters, args.calib_copy_mib or 256, args.workload_note)
+        data = summarize_counters(args.summarize_counters, args.calib_copy_mib or 256, args.workload_note,
+                                  args.counter_steps)
         with open(TRAFFIC_FILE, "w") as fh:
             json.dump(data, fh, indent=1)
             fh.write("\n")
         print(json.dumps(data["kernels"], indent=1))
+        return
+
+    if args.calib_valu:
+        print(json.dumps(calib_valu()), flush=True)
         return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -229,8 +336,10 @@ def main():
               "(keys shard with no exchange step: each GPU would run its own key range)", file=sys.stderr)
         sys.exit(2)
 
-    # the CPU oracle runs first, in forked workers, before this process touches the GPU
-    cb = None if args.no_cpu_baseline else cpu_baseline(args.p, args.cpu_seconds)
+    # the CPU oracle runs first, in forked workers, before this process touches
+    # the GPU; its sample includes the keys the timed output is checked against
+    check = check_indices(args.n)
+    cb, ref_keys = (None, {}) if args.no_cpu_baseline else cpu_baseline(args.p, args.cpu_seconds, check)
 
     import torch
     import paper_2106_08759_amd as nk
@@ -252,7 +361,7 @@ def main():
     elif args.persistent:
         pers = [r for r in (tuned or {}).get("table", []) if r.get("persistent")]
         pc = {k: v for k, v in min(pers, key=lambda r: r["ms"]).items() if k != "ms"} if pers else \
-            {"group_size": 32, "inverse_share": 2, "lanes_per_key": 2, "persistent": 1}
+            {"group_size": 32, "inverse_share": 2, "lanes_per_key": 2, "persistent": 1, "r3_batch": 0}
         ctx.set_config(p, use_graph=0, r3_batch=0, **pc)
     cfg = ctx.get_config(p)
     prm = nk.params(p)
@@ -288,6 +397,21 @@ def main():
     assert timed == K
     rc = ctx.status()
     assert rc == 0, "keygen status %d" % rc
+    # the timed output: the checked keys byte for byte against the oracle's,
+    # and every key's f of weight w (decoded from sk); no value on a mismatch
+    verified = 0
+    if ref_keys:
+        import numpy as np
+        hpk, hsk = pk[check].cpu().numpy(), sk[check].cpu().numpy()
+        bad = [i for j, i in enumerate(check) if hpk[j].tobytes() != ref_keys[i][0] or hsk[j].tobytes() != ref_keys[i][1]]
+        if bad:
+            print("bench.py: timed output differs from the oracle at keys %s" % bad[:8], file=sys.stderr)
+            sys.exit(1)
+        verified = len(check)
+        f, _ = nk.decode_sk(sk, p)
+        if not (np.count_nonzero(f, axis=1) == prm.w).all():
+            print("bench.py: some timed f is not of weight %d" % prm.w, file=sys.stderr)
+            sys.exit(1)
     ms_per_step = ms / K
     keys_per_s = n * K / (ms / 1e3)
 
@@ -314,15 +438,18 @@ def main():
         ops["r3_main"] = 2.0 * prods * p * p
         peaks["r3_main"] = I8_MFMA_PEAK
         units["r3_main"] = "T int8-op/s"
-    # the dominant kernel is the longest stage on the critical path; in eager
-    # mode the prefix kernel runs beside the R/3 stage, so its wall time is
-    # shared and it is not a candidate
+    # the dominant kernel is the longest stage on the launch stream (the
+    # critical path): in eager launches one of the prefix kernel and the R/3
+    # stage runs on the side stream beside the other, its wall time shared --
+    # the prefix kernel with per-key R/3, the whole R/3 stage with batched R/3
+    # (a chain of five kernels, not one kernel either way)
     if cfg.get("persistent"):
         dom = "fused"
     else:
-        # (the batched R/3 stage is a chain of five kernels, not one: not a candidate)
-        crit = [k for k in ops if k != "fused" and not (k == "group_prefix" and not cfg["use_graph"])
-                and not (k == "r3_main" and cfg.get("r3_batch"))]
+        side = set() if cfg["use_graph"] else {"r3_main"} if cfg.get("r3_batch") else {"group_prefix"}
+        if cfg.get("r3_batch"):
+            side.add("r3_main")
+        crit = [k for k in ops if k != "fused" and k not in side]
         dom = max(crit, key=lambda k: avg[k])
     achieved = ops[dom] / (avg[dom] / 1e3)
     kernel_names = {"group_prefix": "keygen_prefix_kernel<%d,%d>" % (p, cfg["inverse_share"]),
@@ -335,6 +462,22 @@ def main():
                 "peak": round(peaks[dom] / 1e12, 2), "unit": units[dom], "frac": round(achieved / peaks[dom], 4),
                 "traffic": stored_traffic(kernel_names[dom]),
                 "ops_per_launch": ops[dom], "avg_launch_ms": round(avg[dom], 4)}
+    # issued: the VALU instructions the counters saw per launch (x 64 lanes)
+    # over the same launch time; the algorithmic fraction is at most this
+    vi = stored_counter(kernel_names[dom], "valu_insts")
+    if vi is not None and roofline["bound"] == "alu":
+        roofline["issued_frac"] = round(vi * 64 / (avg[dom] / 1e3) / VALU_PEAK, 4)
+    # the whole step: every kernel's VALU instructions per step over the step
+    # time (how full the vector ALUs are across the pipeline)
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            tk = json.load(fh)
+        if tk.get("sources_sha256") == sources_digest() and tk.get("steps_per_run"):
+            per_step = sum(v.get("valu_insts", 0.0) * v.get("launches_per_run", 1)
+                           for v in tk["kernels"].values()) / tk["steps_per_run"]
+            roofline["step_valu_issue_frac"] = round(per_step * 64 / (ms_per_step / 1e3) / VALU_PEAK, 4)
+    except (OSError, ValueError):
+        pass
     stage_fracs = {k: {"ms": round(avg[k], 4),
                        "frac": (round(ops[k] / (avg[k] / 1e3) / peaks[k], 4) if k in ops and avg[k] > 0 else None)}
                    for k in avg}
@@ -384,7 +527,7 @@ def main():
         # the same jobs as one launch of the persistent fused kernel
         saved = {q_: ctx.get_config(q_) for q_ in (653, 761, 857, 1277)}
         for q_ in saved:
-            ctx.set_config(q_, persistent=1, product_engine=1, lanes_per_key=2, group_size=32,
+            ctx.set_config(q_, persistent=1, r3_batch=0, product_engine=1, lanes_per_key=2, group_size=32,
                            inverse_share=2, use_graph=1)
         ctx.batch_keygen_mixed(wl.SEED, jobs, check=True)
         torch.cuda.synchronize()
@@ -403,20 +546,25 @@ def main():
         # autotuner's best persistent setting
         pers = [r for r in (tuned or {}).get("table", []) if r.get("persistent")]
         pcfg = {k: v for k, v in min(pers, key=lambda r: r["ms"]).items() if k != "ms"} if pers else \
-            {"group_size": 32, "inverse_share": 2, "lanes_per_key": 2, "persistent": 1}
+            {"group_size": 32, "inverse_share": 2, "lanes_per_key": 2, "persistent": 1, "r3_batch": 0}
         saved = ctx.get_config(p)
-        ctx.set_config(p, use_graph=0, **pcfg)
-        ctx.batch_keygen(p, wl.SEED, 0, n, pk, sk, check=True)
-        torch.cuda.synchronize()
-        e0.record()
-        for _ in range(5):
-            ctx.batch_keygen(p, wl.SEED, 0, n, pk, sk, check=False)
-        e1.record()
-        torch.cuda.synchronize()
-        assert ctx.status() == 0
-        pf_ms = e0.elapsed_time(e1) / 5
-        extras["persistent_fused"] = {"keys_per_s": round(n / pf_ms * 1e3, 1), "ms": round(pf_ms, 3),
-                                      "speedup_over_plain": round(n / pf_ms * 1e3 / plain, 1),
+        pf = {}
+        for ug in (0, 1):
+            # eager launches, and the form config 3 names: the persistent
+            # kernel captured in a hipGraph and replayed (outer events only)
+            ctx.set_config(p, use_graph=ug, **pcfg)
+            ctx.batch_keygen(p, wl.SEED, 0, n, pk, sk, check=True)
+            torch.cuda.synchronize()
+            e0.record()
+            for _ in range(5):
+                ctx.batch_keygen(p, wl.SEED, 0, n, pk, sk, check=False)
+            e1.record()
+            torch.cuda.synchronize()
+            assert ctx.status() == 0
+            pf[ug] = e0.elapsed_time(e1) / 5
+        extras["persistent_fused"] = {"keys_per_s": round(n / pf[0] * 1e3, 1), "ms": round(pf[0], 3),
+                                      "graph_keys_per_s": round(n / pf[1] * 1e3, 1), "graph_ms": round(pf[1], 3),
+                                      "speedup_over_plain": round(n / min(pf.values()) * 1e3 / plain, 1),
                                       "config": {k: pcfg[k] for k in ("group_size", "inverse_share", "lanes_per_key")}}
         ctx.set_config(p, **saved)
         # the paper's own form of Algorithm 1 for the R/3 side: g screened for
@@ -474,6 +622,8 @@ def main():
                               "eager launches: prefix kernel on a side stream beside the R/3 stage")},
         "roofline": roofline,
         "stages": stage_fracs,
+        "output_GBps": round(n * (prm.pk_bytes + prm.sk_bytes) / (ms_per_step / 1e3) / 1e9, 2),
+        "verified_keys": verified,
         "wall_s": round(wall, 3),
     }
     out.update(extras)
@@ -481,7 +631,7 @@ def main():
         out["autotune"] = {"config": tuned["config"], "use_graph": tuned.get("use_graph"),
                            "eager_ms": tuned.get("eager_ms"), "graph_ms": tuned.get("graph_ms"),
                            "cached": tuned["cached"],
-                           "table_ms": {"%sG%d/W%d/L%d/R%dx%dx%d" % ("P:" if r.get("persistent") else "",
+                           "table_ms": {"%sG%d/W%d/L%d/R%dx%dx%d" % ("P:" if r.get("persistent") else "B:" if r.get("r3_batch") else "",
                                                                      r["group_size"], r["inverse_share"],
                                                                      r["lanes_per_key"], r["retry_passes"],
                                                                      r["retry_lanes_per_key"],

@@ -29,12 +29,18 @@
  *
  * Memory.  Key buffers are DEVICE pointers owned by the caller; the library
  * never frees them.  The context owns a device workspace that it grows on
- * demand (hipMalloc outside of any capture); ntrup_ctx_reserve sizes it in
- * advance so that later calls allocate nothing.
+ * demand (hipMalloc outside of any capture), never beyond the budget given
+ * to ntrup_ctx_create: a call that would need more returns NTRUP_ENOMEM and
+ * allocates nothing.  ntrup_ctx_reserve sizes it in advance so that later
+ * calls allocate nothing.
  *
  * Streams.  hipStream_t is passed as void*; NULL = the default stream.  All
  * keygen entry points are asynchronous: they return after enqueueing.
- * ntrup_ctx_status synchronises a stream and reports key-level failures.
+ * Calls on one context share its workspace, so the context orders them: a
+ * call enqueued on a stream other than the previous call's waits (on the
+ * device, hipStreamWaitEvent) for the previous call to finish.  Calls on
+ * different contexts are independent.  ntrup_ctx_status synchronises a
+ * stream and reports key-level failures.
  *
  * Errors.  0 on success, negative codes below; nothing aborts or prints.
  * A context is used by one host thread at a time.
@@ -52,7 +58,7 @@ extern "C" {
 #define NTRUP_OK 0
 #define NTRUP_EIO (-5)      /* a HIP call failed; see ntrup_last_hip_error */
 #define NTRUP_EAGAIN (-11)  /* some key found no invertible g within 64 draws */
-#define NTRUP_ENOMEM (-12)  /* device allocation failed */
+#define NTRUP_ENOMEM (-12)  /* workspace over the context's budget, or device allocation failed */
 #define NTRUP_EINVAL (-22)  /* bad parameter set, size, pointer or config */
 #define NTRUP_EFAULT (-14)  /* a group product was not a unit (cannot happen in a field) */
 #define NTRUP_ETIME (-62)   /* persistent form: an item's input was not ready within
@@ -66,8 +72,10 @@ typedef struct ntrup_ctx ntrup_ctx;
    output pointer may be NULL.  Returns NTRUP_EINVAL for other p. */
 int ntrup_params(int p, int *q, int *w, size_t *pk_bytes, size_t *sk_bytes);
 
-/* Create a context on HIP device `device`.  *out receives the handle. */
-int ntrup_ctx_create(ntrup_ctx **out, int device);
+/* Create a context on HIP device `device`.  *out receives the handle.
+ * workspace_budget_bytes: the most device workspace the context may ever
+ * hold (0 = no limit); see ntrup_workspace_bytes for what a call needs. */
+int ntrup_ctx_create(ntrup_ctx **out, int device, size_t workspace_budget_bytes);
 int ntrup_ctx_destroy(ntrup_ctx *ctx);
 
 /* Pre-size the workspace for calls of up to n keys of ring degree p. */
@@ -75,6 +83,10 @@ int ntrup_ctx_reserve(ntrup_ctx *ctx, int p, size_t n);
 
 /* Bytes of device workspace currently held. */
 size_t ntrup_ctx_workspace_bytes(const ntrup_ctx *ctx);
+
+/* Bytes of workspace a call of n keys of parameter set p needs (a mixed call
+   needs the sum over its jobs); 0 for an unknown p. */
+size_t ntrup_workspace_bytes(int p, size_t n);
 
 /* Last hipError_t seen by the context (0 if none). */
 int ntrup_last_hip_error(const ntrup_ctx *ctx);
@@ -149,11 +161,18 @@ int ntrup_set_config(ntrup_ctx *ctx, int p, const ntrup_config *cfg);
  *   seed  HOST pointer, 32 bytes (copied into the launch; may be freed after)
  *   pk    device, n * pk_bytes(p) bytes, row-major by key
  *   sk    device, n * sk_bytes(p) bytes, row-major by key
- * n >= 1 and n <= 2^31 - 1.  Asynchronous on `stream`.  Key-level failures
- * (no invertible g in 64 draws, probability < 2^-300 per key) are reported by
+ *   h     optional (NULL = skip), device int16 [n][p]: h = g/(3f) in R/q,
+ *         centered in [-(q-1)/2, (q-1)/2]
+ *   f     optional, device int8 [n][p]: f in Short, coefficients in {-1,0,1}
+ *   ginv  optional, device int8 [n][p]: 1/g in R/3, coefficients in {-1,0,1}
+ * The raw arrays are the key pair's unique values (the parity contract);
+ * pk and sk are this library's encodings of them.  n >= 1 and
+ * n <= 2^31 - 1.  Asynchronous on `stream`.  Key-level failures (no
+ * invertible g in 64 draws: below 2^-277 per key at the worst rejection
+ * rate, 4.95 % for p = 1277; below 2^-304 for p = 653) are reported by
  * ntrup_ctx_status. */
 int ntrup_batch_keygen(ntrup_ctx *ctx, int p, const uint8_t *seed, uint64_t first_index, size_t n,
-                       uint8_t *pk, uint8_t *sk, void *stream);
+                       uint8_t *pk, uint8_t *sk, int16_t *h, int8_t *f, int8_t *ginv, void *stream);
 
 /* The plain form, KeyGen of Section 3.1 one key per launch sequence (group
  * size 1, no batching): same outputs as ntrup_batch_keygen. */
@@ -166,8 +185,11 @@ typedef struct {
     int p;
     uint64_t first_index;
     size_t n;
-    uint8_t *pk; /* device */
-    uint8_t *sk; /* device */
+    uint8_t *pk;   /* device */
+    uint8_t *sk;   /* device */
+    int16_t *h;    /* optional raw outputs as in ntrup_batch_keygen; NULL = skip */
+    int8_t *f;
+    int8_t *ginv;
 } ntrup_job;
 
 int ntrup_batch_keygen_mixed(ntrup_ctx *ctx, const uint8_t *seed, const ntrup_job *jobs, size_t njobs,

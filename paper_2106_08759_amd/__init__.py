@@ -38,7 +38,8 @@ class NtrupError(RuntimeError):
 
 class _Job(ctypes.Structure):
     _fields_ = [("p", ctypes.c_int), ("first_index", ctypes.c_uint64), ("n", ctypes.c_size_t),
-                ("pk", ctypes.c_void_p), ("sk", ctypes.c_void_p)]
+                ("pk", ctypes.c_void_p), ("sk", ctypes.c_void_p),
+                ("h", ctypes.c_void_p), ("f", ctypes.c_void_p), ("ginv", ctypes.c_void_p)]
 
 
 class _Config(ctypes.Structure):
@@ -65,15 +66,16 @@ def lib() -> ctypes.CDLL:
     sig = {
         "ntrup_params": (i32, [i32, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(sz),
                                ctypes.POINTER(sz)]),
-        "ntrup_ctx_create": (i32, [ctypes.POINTER(vp), i32]),
+        "ntrup_ctx_create": (i32, [ctypes.POINTER(vp), i32, sz]),
         "ntrup_ctx_destroy": (i32, [vp]),
         "ntrup_ctx_reserve": (i32, [vp, i32, sz]),
         "ntrup_ctx_workspace_bytes": (sz, [vp]),
+        "ntrup_workspace_bytes": (sz, [i32, sz]),
         "ntrup_last_hip_error": (i32, [vp]),
         "ntrup_strerror": (ctypes.c_char_p, [i32]),
         "ntrup_get_config": (i32, [vp, i32, ctypes.POINTER(_Config)]),
         "ntrup_set_config": (i32, [vp, i32, ctypes.POINTER(_Config)]),
-        "ntrup_batch_keygen": (i32, [vp, i32, ctypes.c_char_p, u64, sz, vp, vp, vp]),
+        "ntrup_batch_keygen": (i32, [vp, i32, ctypes.c_char_p, u64, sz, vp, vp, vp, vp, vp, vp]),
         "ntrup_keygen_plain": (i32, [vp, i32, ctypes.c_char_p, u64, sz, vp, vp, vp]),
         "ntrup_batch_keygen_mixed": (i32, [vp, ctypes.c_char_p, ctypes.POINTER(_Job), sz, vp]),
         "ntrup_ctx_status": (i32, [vp, vp]),
@@ -137,15 +139,21 @@ def _seed_bytes(seed) -> bytes:
     return b
 
 
-class Context:
-    """A device context: workspace, tuned configuration, captured graphs."""
+def workspace_bytes(p: int, n: int) -> int:
+    """Device workspace a call of n keys of parameter set p needs."""
+    return lib().ntrup_workspace_bytes(p, n)
 
-    def __init__(self, device: int = 0):
+
+class Context:
+    """A device context: workspace (at most workspace_budget bytes; 0 = no
+    limit), tuned configuration, captured graphs."""
+
+    def __init__(self, device: int = 0, workspace_budget: int = 0):
         import torch
         self.device = device
         self._torch = torch
         h = ctypes.c_void_p()
-        rc = lib().ntrup_ctx_create(ctypes.byref(h), device)
+        rc = lib().ntrup_ctx_create(ctypes.byref(h), device, workspace_budget)
         if rc:
             raise NtrupError(rc, "ntrup_ctx_create")
         self._h = h
@@ -208,10 +216,16 @@ class Context:
         return lib().ntrup_ctx_status(self._h, _stream(stream))
 
     # ---- key generation ----------------------------------------------------
+    def _raw(self, p: int, n: int):
+        t = self._torch
+        return (self._empty((n, p), t.int16), self._empty((n, p), t.int8), self._empty((n, p), t.int8))
+
     def batch_keygen(self, p: int, seed, first_index: int, n: int, pk=None, sk=None,
-                     stream=None, check: bool = True, plain: bool = False):
+                     stream=None, check: bool = True, plain: bool = False, raw: bool = False):
         """Keys first_index..first_index+n-1: returns (pk, sk) uint8 device tensors
-        of shape [n, pk_bytes] and [n, sk_bytes]."""
+        of shape [n, pk_bytes] and [n, sk_bytes]; with raw=True also the raw
+        centered arrays h (int16), f and 1/g (int8), each [n, p] (raw may also be
+        a tuple of three such tensors to write into)."""
         prm = params(p)
         if pk is None:
             pk = self._empty((n, prm.pk_bytes), self._torch.uint8)
@@ -219,25 +233,38 @@ class Context:
             sk = self._empty((n, prm.sk_bytes), self._torch.uint8)
         assert pk.is_contiguous() and sk.is_contiguous()
         assert pk.numel() >= n * prm.pk_bytes and sk.numel() >= n * prm.sk_bytes
-        fn = lib().ntrup_keygen_plain if plain else lib().ntrup_batch_keygen
-        self._check(fn(self._h, p, _seed_bytes(seed), first_index, n, _ptr(pk), _ptr(sk),
-                       _stream(stream)), "keygen")
+        if plain:
+            assert not raw, "the plain form has no raw outputs"
+            rc = lib().ntrup_keygen_plain(self._h, p, _seed_bytes(seed), first_index, n, _ptr(pk), _ptr(sk),
+                                          _stream(stream))
+            arrays = ()
+        else:
+            arrays = tuple(raw) if isinstance(raw, (tuple, list)) else self._raw(p, n) if raw else ()
+            for a_, dt in zip(arrays, (self._torch.int16, self._torch.int8, self._torch.int8)):
+                assert a_.is_contiguous() and a_.dtype == dt and a_.numel() >= n * p
+            rp = [_ptr(a) for a in arrays] if raw else [None, None, None]
+            rc = lib().ntrup_batch_keygen(self._h, p, _seed_bytes(seed), first_index, n, _ptr(pk), _ptr(sk),
+                                          rp[0], rp[1], rp[2], _stream(stream))
+        self._check(rc, "keygen")
         if check:
             self._check(self.status(stream), "keygen status")
-        return pk, sk
+        return (pk, sk) + tuple(arrays)
 
     def keygen_plain(self, p: int, seed, first_index: int, n: int, **kw):
         return self.batch_keygen(p, seed, first_index, n, plain=True, **kw)
 
-    def batch_keygen_mixed(self, seed, jobs, stream=None, check: bool = True):
-        """jobs: list of (p, first_index, n).  Returns a list of (pk, sk)."""
+    def batch_keygen_mixed(self, seed, jobs, stream=None, check: bool = True, raw: bool = False):
+        """jobs: list of (p, first_index, n).  Returns a list of (pk, sk), or of
+        (pk, sk, h, f, ginv) with raw=True."""
         outs, arr = [], (_Job * len(jobs))()
         for i, (p, first, n) in enumerate(jobs):
             prm = params(p)
             pk = self._empty((n, prm.pk_bytes), self._torch.uint8)
             sk = self._empty((n, prm.sk_bytes), self._torch.uint8)
-            outs.append((pk, sk))
-            arr[i] = _Job(p, first, n, _ptr(pk), _ptr(sk))
+            arrays = self._raw(p, n) if raw else ()
+            outs.append((pk, sk) + tuple(arrays))
+            rp = [_ptr(a) for a in arrays] if raw else [None, None, None]
+            arr[i] = _Job(p, first, n, _ptr(pk), _ptr(sk), rp[0], rp[1], rp[2])
         self._check(lib().ntrup_batch_keygen_mixed(self._h, _seed_bytes(seed), arr, len(jobs),
                                                    _stream(stream)), "keygen_mixed")
         if check:

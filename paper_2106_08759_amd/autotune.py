@@ -14,7 +14,10 @@ Knobs (see ``ntrup_config`` in include/ntrupkg.h):
                  invertible (matters for p = 653, 1277, where the retry
                  passes are latency-bound);
   persistent     the stage pipeline (0) or one persistent fused kernel per
-                 call (1).
+                 call (1);
+  r3_batch       one divstep reciprocal in R/3 per key (0) or the R/3
+                 reciprocals of each Montgomery group batched as in
+                 Algorithm 1 (1).
 
 The group knobs (G, W) and the R/3 knobs act on different kernels, but in
 eager launches the prefix kernel runs beside the R/3 stage and the two compete
@@ -22,7 +25,8 @@ for the same compute units, so the first phase times (G, W) jointly with the
 lanes per key of the R/3 main pass (PHASE1_LANES); the second phase then times
 every R/3 setting (lanes per key, retry knobs) with the chosen (G, W), and
 the persistent fused form (one kernel per call, ``persistent`` = 1) at the
-settings in PERSISTENT_CANDIDATES.  Each candidate runs in the launch form of
+settings in PERSISTENT_CANDIDATES, and the batched-R/3 form (``r3_batch`` =
+1) at the (G, W) settings in R3BATCH_CANDIDATES.  Each candidate runs in the launch form of
 the tuning mode (eager launches, or graph replay: one linear stream per job);
 mode "auto" then compares the two forms.
 The product tiles are fixed by p.
@@ -36,13 +40,16 @@ import json
 import os
 import time
 
-GROUP_SIZES = (8, 16, 32, 64, 128)
+GROUP_SIZES = (8, 16, 32, 64, 128, 256)
 SHARES = (1, 2, 4, 8)
 PHASE1_LANES = (1, 2, 4)   # R/3 lanes per key timed jointly with (G, W)
 KNOBS = ("group_size", "inverse_share", "lanes_per_key", "retry_passes", "retry_lanes_per_key",
-         "retry_parallel_attempts", "persistent")
+         "retry_parallel_attempts", "persistent", "r3_batch")
 # (G, W, lanes per key) settings timed for the persistent fused form
 PERSISTENT_CANDIDATES = ((32, 2, 2), (32, 4, 2), (64, 2, 2), (32, 4, 4), (16, 4, 2))
+# (G, W) settings timed for the batched-R/3 form (its R/3 groups are the
+# Montgomery groups of the R/q stage)
+R3BATCH_CANDIDATES = ((32, 8), (32, 4), (64, 4), (16, 8), (64, 2))
 
 
 def cache_path() -> str:
@@ -103,10 +110,10 @@ MODES = ("auto", "eager", "graph")
 
 
 def _key(device_name: str, p: int, n: int, mode: str = "auto") -> str:
-    # v5: entries carry inverse_share, the launch form (eager / graph) and
-    # the kernel form (stage pipeline / persistent fused kernel); one lane per
-    # key (live-word divsteps) among the phase-1 layouts
-    return "%s|p=%d|n<=%d|%s|v5" % (device_name, p, bucket(n), mode)
+    # v6: entries carry inverse_share, the launch form (eager / graph), the
+    # kernel form (stage pipeline / persistent fused kernel) and the R/3 form
+    # (per key / batched); G up to 256
+    return "%s|p=%d|n<=%d|%s|v6" % (device_name, p, bucket(n), mode)
 
 
 def load_cache(path: str | None = None) -> dict:
@@ -178,6 +185,7 @@ def tune(ctx, p: int, n: int, seed: bytes | None = None, reps: int = 3, force: b
     base = ctx.get_config(p)
     cur = {k: base[k] for k in KNOBS}
     cur["persistent"] = 0
+    cur["r3_batch"] = 0
     ctx.set_config(p, product_engine=1)
     table = []
     # phase 1: the group stage, jointly with the R/3 main pass's lanes per key
@@ -200,6 +208,14 @@ def tune(ctx, p: int, n: int, seed: bytes | None = None, reps: int = 3, force: b
         pc = dict(best, group_size=g_, inverse_share=w_, lanes_per_key=l_, persistent=1)
         pc = {k: pc[k] for k in KNOBS}
         table.append(dict(pc, ms=round(time_config(ctx, p, n, pc, seed, reps, pk, sk, ug), 4)))
+    # phase 2c: batched R/3 reciprocals (Algorithm 1) at a few (G, W)
+    r3b = min((r for r in table if not r["persistent"]), key=lambda r: r["ms"])
+    for g_, w_ in R3BATCH_CANDIDATES:
+        if (g_, w_) not in {(c["group_size"], c["inverse_share"]) for c in group_candidates(p, n)}:
+            continue
+        bc = dict(r3b, group_size=g_, inverse_share=w_, r3_batch=1, persistent=0)
+        bc = {k: bc[k] for k in KNOBS}
+        table.append(dict(bc, ms=round(time_config(ctx, p, n, bc, seed, reps, pk, sk, ug), 4)))
     best = min(table, key=lambda r: r["ms"])
     cfg = {k: best[k] for k in KNOBS}
     # phase 3 (auto): eager launches (stage overlap) or graph replay (one

@@ -1,5 +1,7 @@
 // C ABI of the batched KeyGen library: argument checking, workspace, launch
-// sequencing and hipGraph replay.  See include/ntrupkg.h for the contract.
+// sequencing, stream ordering and hipGraph replay.  See include/ntrupkg.h for
+// the contract.  The kernels live in the per-parameter-set objects
+// (ntrup_pipeline.hip) and the persistent-kernel objects (ntrup_persist.hip).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <string.h>
@@ -9,157 +11,16 @@
 #include <vector>
 
 #include "../../include/ntrupkg.h"
-#include "ntrup_kernels.h"
-#include "ntrup_keygen.h"
+#include "ntrup_host.h"
 #include "ntrup_persist.h"
-#include "ntrup_r3batch.h"
 
 using namespace ntrup;
 
-namespace {
-
-constexpr int kParams[4] = {653, 761, 857, 1277};
-constexpr int kCounterInts = 64;  // [0, 16): list counts; [32]: error bits
-
-int param_slot(int p) {
-    for (int i = 0; i < 4; i++)
-        if (kParams[i] == p) return i;
-    return -1;
-}
-
-size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
-
-// Workspace of one pipeline of n keys of degree p.
-struct Ws {
-    int8_t* f_rows;
-    uint32_t* gbits;
-    uint32_t* ibits;
-    int16_t* bscr;
-    int16_t* tinv;     // reciprocal of each Montgomery group's product
-    uint8_t* attempts;
-    int* lists[2];
-    int* counters;
-    int16_t* qrow;     // persistent form: partial products of the shared reciprocals
-                       // (batched R/3: the group products, int8)
-    int* flags;        // persistent form: dependency counters
-    int8_t* r3rows;    // batched R/3: prefix products [n][p]
-    uint32_t* pgbits;  // batched R/3: group products' bitsliced words [WN][2][groups]
-    uint32_t* pinv;    // batched R/3: their reciprocals [WN][2][groups]
-};
-
-// Dependency counters of a persistent job of n keys (every G >= 1).
-size_t flag_ints(size_t n) { return 4 * n + 64; }
-
-size_t ws_bytes(int p, size_t n) {
-    const size_t wn = (size_t)ceil_div(p, 32);
-    return align256(n * p) + 2 * align256(wn * 2 * n * 4) + 2 * align256(n * p * 2) + align256(n) +
-           2 * align256(n * 4) + align256(kCounterInts * 4) + align256(n * p * 2) + align256(flag_ints(n) * 4) +
-           align256(n * p) + 2 * align256(wn * 2 * n * 4);
-}
-
-Ws carve(void* base, int p, size_t n) {
-    const size_t wn = (size_t)ceil_div(p, 32);
-    char* c = (char*)base;
-    Ws w;
-    w.f_rows = (int8_t*)c;       c += align256(n * p);
-    w.gbits = (uint32_t*)c;      c += align256(wn * 2 * n * 4);
-    w.ibits = (uint32_t*)c;      c += align256(wn * 2 * n * 4);
-    w.bscr = (int16_t*)c;        c += align256(n * p * 2);
-    w.tinv = (int16_t*)c;        c += align256(n * p * 2);   // at most n groups
-    w.attempts = (uint8_t*)c;    c += align256(n);
-    w.lists[0] = (int*)c;        c += align256(n * 4);
-    w.lists[1] = (int*)c;        c += align256(n * 4);
-    w.counters = (int*)c;        c += align256(kCounterInts * 4);
-    w.qrow = (int16_t*)c;        c += align256(n * p * 2);
-    w.flags = (int*)c;           c += align256(flag_ints(n) * 4);
-    w.r3rows = (int8_t*)c;       c += align256(n * p);
-    w.pgbits = (uint32_t*)c;     c += align256(wn * 2 * n * 4);
-    w.pinv = (uint32_t*)c;
-    return w;
-}
-
-// One keygen job as enqueued: parameter set, key range, outputs, the config
-// in force and the job's offset in the context workspace.
-struct JobDesc {
-    int p;
-    uint64_t first_index;
-    size_t n;
-    uint8_t* pk;
-    uint8_t* sk;
-    ntrup_config cfg;
-    size_t ws_off;
-    bool operator==(const JobDesc& o) const {
-        return p == o.p && first_index == o.first_index && n == o.n && pk == o.pk && sk == o.sk &&
-               memcmp(&cfg, &o.cfg, sizeof cfg) == 0 && ws_off == o.ws_off;
-    }
-};
-
-// What a captured graph was built from; a call replays it when all match.
-struct GraphKey {
-    uint32_t seed[8];
-    void* ws;
-    std::vector<JobDesc> jobs;
-    bool operator==(const GraphKey& o) const {
-        return memcmp(seed, o.seed, sizeof seed) == 0 && ws == o.ws && jobs == o.jobs;
-    }
-};
-
-constexpr int kJobStreams = 4;  // concurrent branches of a mixed call
-
-}  // namespace
-
-struct ntrup_ctx {
-    int device = 0;
-    int last_hip_error = 0;
-    void* ws = nullptr;
-    size_t ws_cap = 0;
-    ntrup_config cfg[4];
-    std::vector<int*> last_err;     // error words of the last keygen call
-    hipStream_t cap_stream = nullptr;
-    hipStream_t job_streams[kJobStreams] = {};
-    // side stream of single-job calls: Short sampling and the prefix half of
-    // the group stage run there beside the R/3 stage (they need only f)
-    hipStream_t side_stream = nullptr;
-    hipEvent_t side_fork = nullptr, side_join = nullptr;
-    hipEvent_t graph_done = nullptr;   // after the last graph launch
-    hipEvent_t fork_event = nullptr;
-    std::vector<hipEvent_t> join_events;
-    bool have_graph = false;
-    GraphKey gkey;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    // stage timing: kStages+1 events per recorded pipeline
-    std::vector<hipEvent_t> tev;
-    std::vector<char> t_side;       // pipeline ran its side stream
-    int t_max = 0, t_used = 0;
-};
-
-namespace {
-// sample_short, r3 main pass, r3 retry/final passes, group prefix + reciprocal,
-// group back-substitution + encoding
-constexpr int kStages = 5;
-}
-
-namespace {
-
-int hip_fail(ntrup_ctx* ctx, hipError_t e) {
-    ctx->last_hip_error = (int)e;
-    return NTRUP_EIO;
-}
-
-#define NTRUP_HIP(ctx, expr)                             \
-    do {                                                 \
-        hipError_t e_ = (expr);                          \
-        if (e_ != hipSuccess) return hip_fail(ctx, e_);  \
-    } while (0)
-
-int set_device(ntrup_ctx* ctx) {
-    NTRUP_HIP(ctx, hipSetDevice(ctx->device));
-    return 0;
-}
+namespace ntrup {
 
 int ensure_ws(ntrup_ctx* ctx, size_t bytes) {
     if (bytes <= ctx->ws_cap) return 0;
+    if (ctx->ws_budget && bytes > ctx->ws_budget) return NTRUP_ENOMEM;   // nothing allocated or freed
     if (ctx->ws) {
         NTRUP_HIP(ctx, hipDeviceSynchronize());
         NTRUP_HIP(ctx, hipFree(ctx->ws));
@@ -178,6 +39,19 @@ int ensure_ws(ntrup_ctx* ctx, size_t bytes) {
     return 0;
 }
 
+void launch_zero_ints(int* p, int count, hipStream_t st) {
+    hipLaunchKernelGGL(zero_ints_kernel, dim3(grid_for((size_t)count, 256)), dim3(256), 0, st, p, count);
+}
+
+}  // namespace ntrup
+
+namespace {
+
+int set_device(ntrup_ctx* ctx) {
+    NTRUP_HIP(ctx, hipSetDevice(ctx->device));
+    return 0;
+}
+
 Seed make_seed(const uint8_t* s) {
     Seed k;
     for (int i = 0; i < 8; i++)
@@ -186,203 +60,41 @@ Seed make_seed(const uint8_t* s) {
     return k;
 }
 
-unsigned grid_for(size_t items, size_t per_block) { return (unsigned)((items + per_block - 1) / per_block); }
-
-// R/3 pass over up to n keys with lpk lanes per key and a.spec attempts per
-// key side by side: 64 / (lpk * spec) keys per one-wave block.
-template <int P>
-void launch_r3(int lpk, size_t n, const R3Args& a, hipStream_t st) {
-    const size_t kpb = (size_t)(64 / lpk / a.spec);
-    const dim3 grid(grid_for(n, kpb)), blk(64);
-    switch (lpk) {
-        case 1: hipLaunchKernelGGL((r3_kernel<P, 1>), grid, blk, 0, st, a); break;
-        case 2: hipLaunchKernelGGL((r3_kernel<P, 2>), grid, blk, 0, st, a); break;
-        case 4: hipLaunchKernelGGL((r3_kernel<P, 4>), grid, blk, 0, st, a); break;
-        default: hipLaunchKernelGGL((r3_kernel<P, 8>), grid, blk, 0, st, a); break;
-    }
+// Calls on one context share its workspace.  A call enqueued on a stream
+// other than the previous call's first waits for the previous call's end.
+int order_after_last(ntrup_ctx* ctx, hipStream_t st) {
+    if (ctx->have_last && ctx->last_stream != st) NTRUP_HIP(ctx, hipStreamWaitEvent(st, ctx->call_done, 0));
+    return 0;
 }
 
-// Event slot of stage boundary b of the current timed pipeline, or null.
-hipEvent_t stage_event(ntrup_ctx* ctx, int b) {
-    if (ctx->t_used >= ctx->t_max) return nullptr;
-    return ctx->tev[(size_t)ctx->t_used * (kStages + 1) + b];
-}
-
-// Enqueue the whole KeyGen pipeline of one job on `st`.  side_ok: with the
-// matrix-core engine, the prefix half of the group stage (which needs only
-// f) runs on ctx->side_stream beside the R/3 stage, forked from st after
-// Short sampling and joined before the back-substitution.  Otherwise -- graph
-// capture, the jobs of a mixed call (already concurrent branches), the plain
-// form -- every stage runs on st.  zero_err: also clear the error word (once
-// per API call).
-//
-// Stage events: 0 start; 1 end of sampling; 2 end of the prefix kernel
-// (the product engine 0 records it right after 1); 3 end of the R/3 main
-// pass; 4 end of the R/3 retry passes; 5 end.
-template <int P>
-int enqueue_keygen(ntrup_ctx* ctx, const ntrup_config& cfg, const Seed& seed, uint64_t first_index,
-                   size_t n, uint8_t* pk, uint8_t* sk, const Ws& w, hipStream_t st, bool side_ok, bool zero_err) {
-    const bool mfma = cfg.product_engine == 1;
-    const bool side = side_ok && mfma;
-    hipStream_t ss = side ? ctx->side_stream : st;
-    auto mark = [&](int b, hipStream_t on) {
-        if (hipEvent_t ev = stage_event(ctx, b)) (void)hipEventRecord(ev, on);
-    };
-    GroupArgs g;
-    g.n = (int)n;
-    g.G = cfg.group_size;
-    g.f_rows = w.f_rows;
-    g.gbits = w.gbits;
-    g.ibits = w.ibits;
-    g.bscr = w.bscr;
-    g.pk = pk;
-    g.sk = sk;
-    g.err = w.counters + 32;
-    g.a_in = nullptr;
-    g.c_out = nullptr;
-    const int W = cfg.inverse_share;
-
-    hipLaunchKernelGGL(zero_ints_kernel, dim3(1), dim3(64), 0, st, w.counters, zero_err ? kCounterInts : 16);
-    mark(0, st);
-    // batched R/3 needs no f: its whole stage runs on the side stream from
-    // the start, beside sampling and the prefix kernel (which stay on st)
-    const bool r3_first = side && cfg.r3_batch;
-    hipStream_t sp = r3_first ? st : ss;   // prefix kernel
-    hipStream_t sr = r3_first ? ss : st;   // R/3 stage
-    if (r3_first) {
-        NTRUP_HIP(ctx, hipEventRecord(ctx->side_fork, st));
-        NTRUP_HIP(ctx, hipStreamWaitEvent(ss, ctx->side_fork, 0));
-    }
-    hipLaunchKernelGGL(sample_short_kernel<P>, dim3(grid_for(n, 4)), dim3(256), 0, st, seed, first_index, (int)n,
-                       w.f_rows);
-    mark(1, st);
-    if (side && !r3_first) {
-        NTRUP_HIP(ctx, hipEventRecord(ctx->side_fork, st));
-        NTRUP_HIP(ctx, hipStreamWaitEvent(ss, ctx->side_fork, 0));
-    }
-    if (mfma) {
-        const dim3 grid(grid_for(n, (size_t)cfg.group_size * W)), blk(64 * W);
-        switch (W) {
-            case 1: hipLaunchKernelGGL((keygen_prefix_kernel<P, 1>), grid, blk, 0, sp, g, w.tinv); break;
-            case 2: hipLaunchKernelGGL((keygen_prefix_kernel<P, 2>), grid, blk, 0, sp, g, w.tinv); break;
-            case 4: hipLaunchKernelGGL((keygen_prefix_kernel<P, 4>), grid, blk, 0, sp, g, w.tinv); break;
-            default:
-                if constexpr (P != 1277) hipLaunchKernelGGL((keygen_prefix_kernel<P, 8>), grid, blk, 0, sp, g, w.tinv);
-                break;
-        }
-        // with a side stream, the back-substitution (which needs only f) runs
-        // there too, and only h = g c and the encoding follow the R/3 stage
-        if (side)
-            hipLaunchKernelGGL((keygen_cinv_kernel<P>), dim3(grid_for(n, cfg.group_size)), dim3(64), 0, sp, g,
-                               (const int16_t*)w.tinv);
-    }
-    mark(2, sp);
-    if (side && !r3_first) NTRUP_HIP(ctx, hipEventRecord(ctx->side_join, ss));
-    R3Args a;
-    memset(&a, 0, sizeof a);
-    a.seed = seed;
-    a.first_index = first_index;
-    a.n = (int)n;
-    a.attempts = w.attempts;
-    a.gbits = w.gbits;
-    a.ibits = w.ibits;
-    a.err = w.counters + 32;
-    a.g_in = nullptr;
-    const int R = cfg.retry_passes;
-    if (cfg.r3_batch) {
-        // batched R/3 reciprocals: screen, prefix products, group reciprocals,
-        // back-substitution; groups whose product is not a unit go to the
-        // per-key divstep pass
-        R3bArgs<P> b;
-        b.seed = seed;
-        b.first_index = first_index;
-        b.n = (int)n;
-        b.G = cfg.group_size;
-        b.gbits = w.gbits;
-        b.ibits = w.ibits;
-        b.attempts = w.attempts;
-        b.rows = w.r3rows;
-        b.pj = (int8_t*)w.qrow;
-        b.pinv = w.pinv;
-        b.pok = (const uint8_t*)w.lists[1];
-        b.fb_list = w.lists[0];
-        b.fb_count = w.counters;
-        b.err = w.counters + 32;
-        b.screen = cfg.r3_batch == 1;
-        // retry list: lists[0] and counters[1] (the fallback reuses lists[0]
-        // afterwards, with counters[0]); retry draws in the group-reciprocal
-        // buffers (pgbits, pinv: 2 [WN][2][n] words), which are written later
-        b.rt_list = w.lists[0];
-        b.rt_count = w.counters + 1;
-        b.rt_scratch = w.pgbits;
-        b.rt_cap = (int)(2 * n / kR3bRetryDraws);
-        const unsigned ngroups = grid_for(n, cfg.group_size);
-        hipLaunchKernelGGL((r3b_sample_kernel<P>), dim3(grid_for(n * (size_t)ceil_div(P, 32), 256)), dim3(256), 0, sr,
-                           b);
-        hipLaunchKernelGGL((r3b_screen_kernel<P>), dim3(grid_for(n, 256)), dim3(256), 0, sr, b);
-        if (b.screen) {
-            hipLaunchKernelGGL((r3b_retry_sample_kernel<P>), dim3(256), dim3(256), 0, sr, b);
-            hipLaunchKernelGGL((r3b_retry_screen_kernel<P>), dim3(64), dim3(256), 0, sr, b);
-        }
-        hipLaunchKernelGGL((r3b_prefix_kernel<P>), dim3(ngroups), dim3(64), 0, sr, b);
-        R3Args gi;
-        memset(&gi, 0, sizeof gi);
-        gi.n = (int)ngroups;
-        gi.max_rounds = 1;
-        gi.spec = 1;
-        gi.attempts = (uint8_t*)w.lists[1];
-        gi.gbits = w.pgbits;
-        gi.ibits = w.pinv;
-        gi.err = w.counters + 32;
-        gi.g_in = (const int8_t*)w.qrow;
-        launch_r3<P>(8, ngroups, gi, sr);   // latency-bound: few products, most lanes per product
-        hipLaunchKernelGGL((r3b_back_kernel<P>), dim3(ngroups), dim3(64), 0, sr, b);
-        mark(3, sr);
-        a.list_in = w.lists[0];
-        a.count_in = w.counters;
-        a.list_out = nullptr;
-        a.count_out = nullptr;
-        a.spec = cfg.retry_parallel_attempts;
-        a.max_rounds = ceil_div(kMaxAttempts, a.spec);
-        launch_r3<P>(cfg.retry_lanes_per_key, n, a, sr);
-    }
-    for (int pass = 0; pass <= R + 1 && !cfg.r3_batch; pass++) {
-        const bool last = pass == R + 1;
-        a.list_in = pass == 0 ? nullptr : w.lists[(pass - 1) & 1];
-        a.count_in = pass == 0 ? nullptr : w.counters + (pass - 1);
-        a.list_out = last ? nullptr : w.lists[pass & 1];
-        a.count_out = last ? nullptr : w.counters + pass;
-        a.spec = pass == 0 ? 1 : cfg.retry_parallel_attempts;
-        a.max_rounds = last ? ceil_div(kMaxAttempts, a.spec) : 1;
-        launch_r3<P>(pass == 0 ? cfg.lanes_per_key : cfg.retry_lanes_per_key, n, a, sr);
-        if (pass == 0) mark(3, sr);
-    }
-    mark(4, sr);
-    if (r3_first) NTRUP_HIP(ctx, hipEventRecord(ctx->side_join, ss));
-    if (side) NTRUP_HIP(ctx, hipStreamWaitEvent(st, ctx->side_join, 0));
-    if (mfma && side) {
-        const unsigned per = grid_for(n, 8);
-        hipLaunchKernelGGL((keygen_h_kernel<P>), dim3(8 * per), dim3(64), 0, st, g, (int)per);
-    } else if (mfma) {
-        hipLaunchKernelGGL((keygen_back_kernel<P>), dim3(grid_for(n, cfg.group_size)), dim3(64), 0, st, g,
-                           (const int16_t*)w.tinv);
-    } else {
-        hipLaunchKernelGGL((group_kernel<P, true>), dim3(grid_for(n, cfg.group_size)), dim3(64), 0, st, g);
-    }
-    mark(5, st);
-    if (ctx->t_used < ctx->t_max) ctx->t_side[ctx->t_used++] = r3_first ? 3 : side ? 1 : 0;
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return hip_fail(ctx, e);
+int mark_call_end(ntrup_ctx* ctx, hipStream_t st) {
+    NTRUP_HIP(ctx, hipEventRecord(ctx->call_done, st));
+    ctx->last_stream = st;
+    ctx->have_last = true;
     return 0;
 }
 
 int enqueue_dispatch(ntrup_ctx* ctx, int p, const ntrup_config& cfg, const Seed& seed, uint64_t first_index,
-                     size_t n, uint8_t* pk, uint8_t* sk, const Ws& w, hipStream_t st, bool side_ok, bool zero_err) {
+                     size_t n, uint8_t* pk, uint8_t* sk, const RawOut& raw, const Ws& w, hipStream_t st,
+                     bool side_ok, bool zero_err) {
     switch (p) {
-        case 653: return enqueue_keygen<653>(ctx, cfg, seed, first_index, n, pk, sk, w, st, side_ok, zero_err);
-        case 761: return enqueue_keygen<761>(ctx, cfg, seed, first_index, n, pk, sk, w, st, side_ok, zero_err);
-        case 857: return enqueue_keygen<857>(ctx, cfg, seed, first_index, n, pk, sk, w, st, side_ok, zero_err);
-        case 1277: return enqueue_keygen<1277>(ctx, cfg, seed, first_index, n, pk, sk, w, st, side_ok, zero_err);
+        case 653: return enqueue_keygen<653>(ctx, cfg, seed, first_index, n, pk, sk, raw, w, st, side_ok, zero_err);
+        case 761: return enqueue_keygen<761>(ctx, cfg, seed, first_index, n, pk, sk, raw, w, st, side_ok, zero_err);
+        case 857: return enqueue_keygen<857>(ctx, cfg, seed, first_index, n, pk, sk, raw, w, st, side_ok, zero_err);
+        case 1277:
+            return enqueue_keygen<1277>(ctx, cfg, seed, first_index, n, pk, sk, raw, w, st, side_ok, zero_err);
+    }
+    return NTRUP_EINVAL;
+}
+
+// The raw arrays of a finished job (decoded from pk / sk by its p's object).
+int enqueue_raw(ntrup_ctx* ctx, int p, size_t n, const uint8_t* pk, const uint8_t* sk, const RawOut& raw,
+                hipStream_t st) {
+    switch (p) {
+        case 653: return op_decode_raw<653>(ctx, n, pk, sk, raw, st);
+        case 761: return op_decode_raw<761>(ctx, n, pk, sk, raw, st);
+        case 857: return op_decode_raw<857>(ctx, n, pk, sk, raw, st);
+        case 1277: return op_decode_raw<1277>(ctx, n, pk, sk, raw, st);
     }
     return NTRUP_EINVAL;
 }
@@ -391,35 +103,12 @@ int enqueue_dispatch(ntrup_ctx* ctx, int p, const ntrup_config& cfg, const Seed&
 // Persistent form: every stage of every job as items of one work list, run by
 // one launch of keygen_persistent_kernel (see ntrup_persist.h).
 // ---------------------------------------------------------------------------
-template <int LPK, int... Ps>
-int launch_persistent(ntrup_ctx* ctx, const PLaunch& pl, hipStream_t st) {
-    auto kernel = keygen_persistent_kernel<LPK, Ps...>;
-    int per_cu = 0, cus = 0;
-    NTRUP_HIP(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 64, 0));
-    NTRUP_HIP(ctx, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device));
-    const int grid = std::max(1, std::min(pl.total, std::max(1, per_cu) * cus));
-    hipLaunchKernelGGL(kernel, dim3(grid), dim3(64), 0, st, pl);
-    NTRUP_HIP(ctx, hipGetLastError());
-    return 0;
-}
-
-template <int LPK>
-int launch_persistent_p(ntrup_ctx* ctx, int p, bool mixed, const PLaunch& pl, hipStream_t st) {
-    if (mixed) return launch_persistent<LPK, 653, 761, 857, 1277>(ctx, pl, st);
-    switch (p) {
-        case 653: return launch_persistent<LPK, 653>(ctx, pl, st);
-        case 761: return launch_persistent<LPK, 761>(ctx, pl, st);
-        case 857: return launch_persistent<LPK, 857>(ctx, pl, st);
-        case 1277: return launch_persistent<LPK, 1277>(ctx, pl, st);
-    }
-    return NTRUP_EINVAL;
-}
-
 // The work list of `jobs` (each with cfg.persistent set; the R/3 lanes per
 // key of the first job apply to all): stage counts, dependency counters in
 // each job's workspace (zeroed here), segments in the order S | R and C
 // interleaved in 8 chunks | Q | T | B, job by job within each stage.
-int enqueue_persistent(ntrup_ctx* ctx, const Seed& sd, const std::vector<JobDesc>& jobs, hipStream_t st) {
+int enqueue_persistent(ntrup_ctx* ctx, void* base, const Seed& sd, const std::vector<JobDesc>& jobs,
+                       hipStream_t st) {
     if (jobs.empty() || jobs.size() > (size_t)kPMaxJobs) return NTRUP_EINVAL;
     PLaunch pl;
     memset(&pl, 0, sizeof pl);
@@ -430,7 +119,7 @@ int enqueue_persistent(ntrup_ctx* ctx, const Seed& sd, const std::vector<JobDesc
     for (size_t j = 0; j < jobs.size(); j++) {
         const JobDesc& jd = jobs[j];
         mixed = mixed || jd.p != jobs[0].p;
-        const Ws w = carve((char*)ctx->ws + jd.ws_off, jd.p, jd.n);
+        const Ws w = carve((char*)base + jd.ws_off, jd.p, jd.n);
         PJob& J = pl.jobs[j];
         const int n = (int)jd.n;
         J.p = jd.p;
@@ -466,8 +155,8 @@ int enqueue_persistent(ntrup_ctx* ctx, const Seed& sd, const std::vector<JobDesc
         J.kfinal = J.qdone + J.nq;
         J.rcount = J.kfinal + J.ngroups;
         const int used = J.ns + 2 * J.ngroups + J.nq + 2;   // rcount, then the list's next index (job 0)
-        hipLaunchKernelGGL(zero_ints_kernel, dim3(1), dim3(64), 0, st, w.counters, kCounterInts);
-        hipLaunchKernelGGL(zero_ints_kernel, dim3(grid_for(used, 256)), dim3(256), 0, st, w.flags, used);
+        launch_zero_ints(w.counters, kCounterInts, st);
+        launch_zero_ints(w.flags, used, st);
         if (j == 0) pl.next = J.rcount + 1;
     }
     auto add = [&](int job, int stage, int local0, int count) {
@@ -492,8 +181,14 @@ int enqueue_persistent(ntrup_ctx* ctx, const Seed& sd, const std::vector<JobDesc
     for (int j = 0; j < pl.njobs; j++) add(j, PS_RETRY, 0, pl.jobs[j].nt);
     for (int j = 0; j < pl.njobs; j++) add(j, PS_BACK, 0, pl.jobs[j].ngroups);
     NTRUP_HIP(ctx, hipGetLastError());
-    return lpk == 2 ? launch_persistent_p<2>(ctx, jobs[0].p, mixed, pl, st)
-                    : launch_persistent_p<4>(ctx, jobs[0].p, mixed, pl, st);
+    int r;
+    if (mixed) r = lpk == 2 ? launch_persistent_mixed<2>(ctx, pl, st) : launch_persistent_mixed<4>(ctx, pl, st);
+    else r = lpk == 2 ? launch_persistent_single<2>(ctx, jobs[0].p, pl, st)
+                      : launch_persistent_single<4>(ctx, jobs[0].p, pl, st);
+    if (r) return r;
+    for (const JobDesc& jd : jobs)
+        if (int e = enqueue_raw(ctx, jd.p, jd.n, jd.pk, jd.sk, jd.raw, st)) return e;
+    return 0;
 }
 
 bool valid_config(const ntrup_config& c) {
@@ -514,25 +209,59 @@ int check_job(int p, size_t n, const void* pk, const void* sk) {
     return 0;
 }
 
-template <int P>
-int op_recip_r3(ntrup_ctx* ctx, int lpk, const int8_t* a, int8_t* out, int32_t* ok, size_t n, hipStream_t st) {
-    if (int r = ensure_ws(ctx, ws_bytes(P, n))) return r;
-    const Ws w = carve(ctx->ws, P, n);
-    R3Args ar;
-    memset(&ar, 0, sizeof ar);
-    ar.n = (int)n;
-    ar.max_rounds = 1;
-    ar.spec = 1;
-    ar.attempts = w.attempts;
-    ar.gbits = w.gbits;
-    ar.ibits = w.ibits;
-    ar.err = w.counters + 32;
-    ar.g_in = a;
-    launch_r3<P>(lpk, n, ar, st);
-    hipLaunchKernelGGL(unpack_bits_kernel<P>, dim3(grid_for(n, 256)), dim3(256), 0, st, (int)n, w.ibits, out);
-    hipLaunchKernelGGL(copy_flags_kernel, dim3(grid_for(n, 256)), dim3(256), 0, st, (int)n, w.attempts, ok);
-    NTRUP_HIP(ctx, hipGetLastError());
+
+// Enqueue every job on `st`, its workspace at base + job.ws_off: one job
+// directly; several jobs on the context's job streams between a fork and a
+// join on `st`, so that they run concurrently (and form parallel branches
+// when captured).  side_ok: a single job may fork its side stream (eager
+// launches only: a captured graph stays one linear stream per job).
+int enqueue_jobs(ntrup_ctx* ctx, void* base, const Seed& sd, const std::vector<JobDesc>& jobs, hipStream_t st,
+                 bool side_ok) {
+    bool persistent = jobs.size() <= (size_t)kPMaxJobs;
+    for (const JobDesc& j : jobs) persistent = persistent && j.cfg.persistent;
+    if (persistent) {
+        // one launch for every job; stage events: all of the call in "fused"
+        for (int b = 0; b < kStages; b++)
+            if (hipEvent_t ev = stage_event(ctx, b)) (void)hipEventRecord(ev, st);
+        int r = enqueue_persistent(ctx, base, sd, jobs, st);
+        if (hipEvent_t ev = stage_event(ctx, kStages)) (void)hipEventRecord(ev, st);
+        if (ctx->t_used < ctx->t_max) ctx->t_side[ctx->t_used++] = 2;
+        return r;
+    }
+    if (jobs.size() == 1) {
+        const JobDesc& j = jobs[0];
+        return enqueue_dispatch(ctx, j.p, j.cfg, sd, j.first_index, j.n, j.pk, j.sk, j.raw,
+                                carve((char*)base + j.ws_off, j.p, j.n), st, side_ok, true);
+    }
+    if (!ctx->fork_event) NTRUP_HIP(ctx, hipEventCreateWithFlags(&ctx->fork_event, hipEventDisableTiming));
+    while (ctx->join_events.size() < jobs.size()) {
+        hipEvent_t e;
+        NTRUP_HIP(ctx, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        ctx->join_events.push_back(e);
+    }
+    NTRUP_HIP(ctx, hipEventRecord(ctx->fork_event, st));
+    for (size_t i = 0; i < jobs.size(); i++) {
+        const JobDesc& j = jobs[i];
+        hipStream_t js = ctx->job_streams[i % kJobStreams];
+        NTRUP_HIP(ctx, hipStreamWaitEvent(js, ctx->fork_event, 0));
+        // the jobs already run as concurrent branches: each stays on its own
+        // stream (no second-level fork inside a forked branch)
+        int r = enqueue_dispatch(ctx, j.p, j.cfg, sd, j.first_index, j.n, j.pk, j.sk, j.raw,
+                                 carve((char*)base + j.ws_off, j.p, j.n), js, false, true);
+        if (r) return r;
+        NTRUP_HIP(ctx, hipEventRecord(ctx->join_events[i], js));
+    }
+    for (size_t i = 0; i < jobs.size(); i++) NTRUP_HIP(ctx, hipStreamWaitEvent(st, ctx->join_events[i], 0));
     return 0;
+}
+
+// A single operation that uses the context workspace, ordered after the
+// previous call on another stream and marked as the last call.
+template <class F>
+int ws_call(ntrup_ctx* ctx, hipStream_t st, F&& f) {
+    if (int r = order_after_last(ctx, st)) return r;
+    if (int r = f()) return r;
+    return mark_call_end(ctx, st);
 }
 
 }  // namespace
@@ -560,7 +289,7 @@ const char* ntrup_strerror(int code) {
         case NTRUP_OK: return "ok";
         case NTRUP_EIO: return "HIP call failed";
         case NTRUP_EAGAIN: return "no invertible g within the attempt cap";
-        case NTRUP_ENOMEM: return "device allocation failed";
+        case NTRUP_ENOMEM: return "device workspace over budget or allocation failed";
         case NTRUP_EINVAL: return "invalid argument";
         case NTRUP_EFAULT: return "group product not a unit";
         case NTRUP_ETIME: return "a persistent-kernel item waited too long for its inputs";
@@ -568,7 +297,7 @@ const char* ntrup_strerror(int code) {
     return "unknown error";
 }
 
-int ntrup_ctx_create(ntrup_ctx** out, int device) {
+int ntrup_ctx_create(ntrup_ctx** out, int device, size_t workspace_budget_bytes) {
     if (!out) return NTRUP_EINVAL;
     *out = nullptr;
     int count = 0;
@@ -576,6 +305,8 @@ int ntrup_ctx_create(ntrup_ctx** out, int device) {
     ntrup_ctx* ctx = new (std::nothrow) ntrup_ctx();
     if (!ctx) return NTRUP_ENOMEM;
     ctx->device = device;
+    ctx->ws_budget = workspace_budget_bytes;
+    ctx->last_err.reserve(kJobStreams * 4);
     for (int i = 0; i < 4; i++) ctx->cfg[i] = ntrup_config{32, 2, 8, 4, 1, 1, 1, 4, 0, 0};
     bool ok = set_device(ctx) == 0 && hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking) == hipSuccess;
     for (int i = 0; ok && i < kJobStreams; i++)
@@ -583,7 +314,8 @@ int ntrup_ctx_create(ntrup_ctx** out, int device) {
     ok = ok && hipStreamCreateWithFlags(&ctx->side_stream, hipStreamNonBlocking) == hipSuccess &&
          hipEventCreateWithFlags(&ctx->side_fork, hipEventDisableTiming) == hipSuccess &&
          hipEventCreateWithFlags(&ctx->side_join, hipEventDisableTiming) == hipSuccess &&
-         hipEventCreateWithFlags(&ctx->graph_done, hipEventDisableTiming) == hipSuccess;
+         hipEventCreateWithFlags(&ctx->graph_done, hipEventDisableTiming) == hipSuccess &&
+         hipEventCreateWithFlags(&ctx->call_done, hipEventDisableTiming) == hipSuccess;
     if (!ok) {
         ntrup_ctx_destroy(ctx);
         return NTRUP_EIO;
@@ -605,6 +337,7 @@ int ntrup_ctx_destroy(ntrup_ctx* ctx) {
     if (ctx->side_fork) (void)hipEventDestroy(ctx->side_fork);
     if (ctx->side_join) (void)hipEventDestroy(ctx->side_join);
     if (ctx->graph_done) (void)hipEventDestroy(ctx->graph_done);
+    if (ctx->call_done) (void)hipEventDestroy(ctx->call_done);
     if (ctx->fork_event) (void)hipEventDestroy(ctx->fork_event);
     for (hipEvent_t e : ctx->join_events) (void)hipEventDestroy(e);
     if (ctx->ws) (void)hipFree(ctx->ws);
@@ -620,6 +353,8 @@ int ntrup_ctx_reserve(ntrup_ctx* ctx, int p, size_t n) {
 }
 
 size_t ntrup_ctx_workspace_bytes(const ntrup_ctx* ctx) { return ctx ? ctx->ws_cap : 0; }
+
+size_t ntrup_workspace_bytes(int p, size_t n) { return param_slot(p) < 0 ? 0 : ws_bytes(p, n); }
 
 int ntrup_last_hip_error(const ntrup_ctx* ctx) { return ctx ? ctx->last_hip_error : 0; }
 
@@ -639,13 +374,16 @@ int ntrup_set_config(ntrup_ctx* ctx, int p, const ntrup_config* cfg) {
 }
 
 int ntrup_batch_keygen(ntrup_ctx* ctx, int p, const uint8_t* seed, uint64_t first_index, size_t n, uint8_t* pk,
-                       uint8_t* sk, void* stream) {
+                       uint8_t* sk, int16_t* h, int8_t* f, int8_t* ginv, void* stream) {
     ntrup_job job;
     job.p = p;
     job.first_index = first_index;
     job.n = n;
     job.pk = pk;
     job.sk = sk;
+    job.h = h;
+    job.f = f;
+    job.ginv = ginv;
     return ntrup_batch_keygen_mixed(ctx, seed, &job, 1, stream);
 }
 
@@ -655,6 +393,8 @@ int ntrup_keygen_plain(ntrup_ctx* ctx, int p, const uint8_t* seed, uint64_t firs
     if (int r = check_job(p, n, pk, sk)) return r;
     if (int r = set_device(ctx)) return r;
     if (int r = ensure_ws(ctx, ws_bytes(p, 1))) return r;
+    hipStream_t st = (hipStream_t)stream;
+    if (int r = order_after_last(ctx, st)) return r;
     ntrup_config cfg = ctx->cfg[param_slot(p)];
     cfg.group_size = 1;
     const Seed sd = make_seed(seed);
@@ -662,61 +402,14 @@ int ntrup_keygen_plain(ntrup_ctx* ctx, int p, const uint8_t* seed, uint64_t firs
     ctx->last_err.assign(1, w.counters + 32);
     size_t pkb, skb;
     ntrup_params(p, nullptr, nullptr, &pkb, &skb);
+    const RawOut none{nullptr, nullptr, nullptr};
     for (size_t i = 0; i < n; i++) {
-        int r = enqueue_dispatch(ctx, p, cfg, sd, first_index + i, 1, pk + i * pkb, sk + i * skb, w,
-                                 (hipStream_t)stream, false, i == 0);
+        int r = enqueue_dispatch(ctx, p, cfg, sd, first_index + i, 1, pk + i * pkb, sk + i * skb, none, w, st, false,
+                                 i == 0);
         if (r) return r;
     }
-    return 0;
+    return mark_call_end(ctx, st);
 }
-
-namespace {
-
-// Enqueue every job on `st`: one job directly; several jobs on the context's
-// job streams between a fork and a join on `st`, so that they run
-// concurrently (and form parallel branches when captured).
-// side_ok: a single job may fork its side stream (eager launches only: a
-// captured graph stays one linear stream per job).
-int enqueue_jobs(ntrup_ctx* ctx, const Seed& sd, const std::vector<JobDesc>& jobs, hipStream_t st, bool side_ok) {
-    bool persistent = jobs.size() <= (size_t)kPMaxJobs;
-    for (const JobDesc& j : jobs) persistent = persistent && j.cfg.persistent;
-    if (persistent) {
-        // one launch for every job; stage events: all of the call in "fused"
-        for (int b = 0; b < kStages; b++)
-            if (hipEvent_t ev = stage_event(ctx, b)) (void)hipEventRecord(ev, st);
-        int r = enqueue_persistent(ctx, sd, jobs, st);
-        if (hipEvent_t ev = stage_event(ctx, kStages)) (void)hipEventRecord(ev, st);
-        if (ctx->t_used < ctx->t_max) ctx->t_side[ctx->t_used++] = 2;
-        return r;
-    }
-    if (jobs.size() == 1) {
-        const JobDesc& j = jobs[0];
-        return enqueue_dispatch(ctx, j.p, j.cfg, sd, j.first_index, j.n, j.pk, j.sk,
-                                carve((char*)ctx->ws + j.ws_off, j.p, j.n), st, side_ok, true);
-    }
-    if (!ctx->fork_event) NTRUP_HIP(ctx, hipEventCreateWithFlags(&ctx->fork_event, hipEventDisableTiming));
-    while (ctx->join_events.size() < jobs.size()) {
-        hipEvent_t e;
-        NTRUP_HIP(ctx, hipEventCreateWithFlags(&e, hipEventDisableTiming));
-        ctx->join_events.push_back(e);
-    }
-    NTRUP_HIP(ctx, hipEventRecord(ctx->fork_event, st));
-    for (size_t i = 0; i < jobs.size(); i++) {
-        const JobDesc& j = jobs[i];
-        hipStream_t js = ctx->job_streams[i % kJobStreams];
-        NTRUP_HIP(ctx, hipStreamWaitEvent(js, ctx->fork_event, 0));
-        // the jobs already run as concurrent branches: each stays on its own
-        // stream (no second-level fork inside a forked branch)
-        int r = enqueue_dispatch(ctx, j.p, j.cfg, sd, j.first_index, j.n, j.pk, j.sk,
-                                 carve((char*)ctx->ws + j.ws_off, j.p, j.n), js, false, true);
-        if (r) return r;
-        NTRUP_HIP(ctx, hipEventRecord(ctx->join_events[i], js));
-    }
-    for (size_t i = 0; i < jobs.size(); i++) NTRUP_HIP(ctx, hipStreamWaitEvent(st, ctx->join_events[i], 0));
-    return 0;
-}
-
-}  // namespace
 
 int ntrup_batch_keygen_mixed(ntrup_ctx* ctx, const uint8_t* seed, const ntrup_job* jobs, size_t njobs,
                              void* stream) {
@@ -727,7 +420,7 @@ int ntrup_batch_keygen_mixed(ntrup_ctx* ctx, const uint8_t* seed, const ntrup_jo
     for (size_t j = 0; j < njobs; j++) {
         if (int r = check_job(jobs[j].p, jobs[j].n, jobs[j].pk, jobs[j].sk)) return r;
         jd[j] = JobDesc{jobs[j].p, jobs[j].first_index, jobs[j].n, jobs[j].pk, jobs[j].sk,
-                        ctx->cfg[param_slot(jobs[j].p)], total};
+                        RawOut{jobs[j].h, jobs[j].f, jobs[j].ginv}, ctx->cfg[param_slot(jobs[j].p)], total};
         graph = graph && jd[j].cfg.use_graph;
         total += ws_bytes(jobs[j].p, jobs[j].n);
     }
@@ -737,7 +430,11 @@ int ntrup_batch_keygen_mixed(ntrup_ctx* ctx, const uint8_t* seed, const ntrup_jo
     ctx->last_err.clear();
     for (const JobDesc& j : jd) ctx->last_err.push_back(carve((char*)ctx->ws + j.ws_off, j.p, j.n).counters + 32);
     hipStream_t st = (hipStream_t)stream;
-    if (!graph) return enqueue_jobs(ctx, sd, jd, st, true);
+    if (int r = order_after_last(ctx, st)) return r;
+    if (!graph) {
+        if (int r = enqueue_jobs(ctx, ctx->ws, sd, jd, st, true)) return r;
+        return mark_call_end(ctx, st);
+    }
 
     GraphKey key;
     memcpy(key.seed, sd.k, sizeof key.seed);
@@ -750,7 +447,7 @@ int ntrup_batch_keygen_mixed(ntrup_ctx* ctx, const uint8_t* seed, const ntrup_jo
         if (ctx->graph) { (void)hipGraphDestroy(ctx->graph); ctx->graph = nullptr; }
         ctx->have_graph = false;
         NTRUP_HIP(ctx, hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
-        int r = enqueue_jobs(ctx, sd, jd, ctx->cap_stream, false);
+        int r = enqueue_jobs(ctx, ctx->ws, sd, jd, ctx->cap_stream, false);
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamEndCapture(ctx->cap_stream, &g);
         if (r) { if (g) (void)hipGraphDestroy(g); return r; }
@@ -762,7 +459,7 @@ int ntrup_batch_keygen_mixed(ntrup_ctx* ctx, const uint8_t* seed, const ntrup_jo
     }
     NTRUP_HIP(ctx, hipGraphLaunch(ctx->exec, st));
     NTRUP_HIP(ctx, hipEventRecord(ctx->graph_done, st));
-    return 0;
+    return mark_call_end(ctx, st);
 }
 
 int ntrup_ctx_timing_begin(ntrup_ctx* ctx, int max_pipelines) {
@@ -834,69 +531,41 @@ int ntrup_ctx_status(ntrup_ctx* ctx, void* stream) {
 
 // ---------------------------------------------------------------- single ops
 
+#define NTRUP_BY_P(p, call)                              \
+    switch (p) {                                         \
+        case 653: { constexpr int P = 653; return call; }   \
+        case 761: { constexpr int P = 761; return call; }   \
+        case 857: { constexpr int P = 857; return call; }   \
+        case 1277: { constexpr int P = 1277; return call; } \
+    }                                                    \
+    return NTRUP_EINVAL
+
 int ntrup_op_mul_rq(ntrup_ctx* ctx, int p, const int16_t* a, const int16_t* b, int16_t* c, size_t n, int small_a,
                     void* stream) {
     if (!ctx || param_slot(p) < 0 || !a || !b || !c || n == 0 || n > 0x7FFFFFFF) return NTRUP_EINVAL;
     if (int r = set_device(ctx)) return r;
-    hipStream_t st = (hipStream_t)stream;
-    const dim3 grid((unsigned)n), blk(64);
     const bool mfma = ctx->cfg[param_slot(p)].product_engine == 1;
-#define NTRUP_MUL(PP)                                                                              \
-    case PP:                                                                                       \
-        if (mfma && small_a) hipLaunchKernelGGL((mulm_kernel<PP, false>), grid, blk, 0, st, (int)n, a, b, c); \
-        else if (mfma) hipLaunchKernelGGL((mulm_kernel<PP, true>), grid, blk, 0, st, (int)n, a, b, c);    \
-        else if (small_a) hipLaunchKernelGGL((mul_kernel<PP, false>), grid, blk, 0, st, (int)n, a, b, c); \
-        else hipLaunchKernelGGL((mul_kernel<PP, true>), grid, blk, 0, st, (int)n, a, b, c);               \
-        break;
-    switch (p) { NTRUP_MUL(653) NTRUP_MUL(761) NTRUP_MUL(857) NTRUP_MUL(1277) }
-#undef NTRUP_MUL
-    NTRUP_HIP(ctx, hipGetLastError());
-    return 0;
+    NTRUP_BY_P(p, op_mul_rq<P>(ctx, mfma, a, b, c, n, small_a != 0, (hipStream_t)stream));
 }
 
 int ntrup_op_mul_r3(ntrup_ctx* ctx, int p, const int8_t* a, const int8_t* b, int8_t* c, size_t n, void* stream) {
     if (!ctx || param_slot(p) < 0 || !a || !b || !c || n == 0 || n > 0x7FFFFFFF) return NTRUP_EINVAL;
     if (int r = set_device(ctx)) return r;
-    hipStream_t st = (hipStream_t)stream;
-    const dim3 grid((unsigned)n), blk(64);
-    switch (p) {
-        case 653: hipLaunchKernelGGL(mul3_kernel<653>, grid, blk, 0, st, (int)n, a, b, c); break;
-        case 761: hipLaunchKernelGGL(mul3_kernel<761>, grid, blk, 0, st, (int)n, a, b, c); break;
-        case 857: hipLaunchKernelGGL(mul3_kernel<857>, grid, blk, 0, st, (int)n, a, b, c); break;
-        case 1277: hipLaunchKernelGGL(mul3_kernel<1277>, grid, blk, 0, st, (int)n, a, b, c); break;
-    }
-    NTRUP_HIP(ctx, hipGetLastError());
-    return 0;
+    NTRUP_BY_P(p, op_mul_r3<P>(ctx, a, b, c, n, (hipStream_t)stream));
 }
 
 int ntrup_op_recip_rq(ntrup_ctx* ctx, int p, const int16_t* a, int16_t* out, int32_t* ok, size_t n, void* stream) {
     if (!ctx || param_slot(p) < 0 || !a || !out || !ok || n == 0 || n > 0x7FFFFFFF) return NTRUP_EINVAL;
     if (int r = set_device(ctx)) return r;
-    hipStream_t st = (hipStream_t)stream;
-    const dim3 grid((unsigned)n), blk(64);
-    switch (p) {
-        case 653: hipLaunchKernelGGL(recip_q_kernel<653>, grid, blk, 0, st, (int)n, a, out, ok); break;
-        case 761: hipLaunchKernelGGL(recip_q_kernel<761>, grid, blk, 0, st, (int)n, a, out, ok); break;
-        case 857: hipLaunchKernelGGL(recip_q_kernel<857>, grid, blk, 0, st, (int)n, a, out, ok); break;
-        case 1277: hipLaunchKernelGGL(recip_q_kernel<1277>, grid, blk, 0, st, (int)n, a, out, ok); break;
-    }
-    NTRUP_HIP(ctx, hipGetLastError());
-    return 0;
+    NTRUP_BY_P(p, op_recip_rq<P>(ctx, a, out, ok, n, (hipStream_t)stream));
 }
-
 
 int ntrup_op_recip_r3(ntrup_ctx* ctx, int p, const int8_t* a, int8_t* out, int32_t* ok, size_t n, void* stream) {
     if (!ctx || param_slot(p) < 0 || !a || !out || !ok || n == 0 || n > 0x7FFFFFFF) return NTRUP_EINVAL;
     if (int r = set_device(ctx)) return r;
     const int lpk = ctx->cfg[param_slot(p)].lanes_per_key;
     hipStream_t st = (hipStream_t)stream;
-    switch (p) {
-        case 653: return op_recip_r3<653>(ctx, lpk, a, out, ok, n, st);
-        case 761: return op_recip_r3<761>(ctx, lpk, a, out, ok, n, st);
-        case 857: return op_recip_r3<857>(ctx, lpk, a, out, ok, n, st);
-        case 1277: return op_recip_r3<1277>(ctx, lpk, a, out, ok, n, st);
-    }
-    return NTRUP_EINVAL;
+    return ws_call(ctx, st, [&]() -> int { NTRUP_BY_P(p, op_recip_r3<P>(ctx, lpk, a, out, ok, n, st)); });
 }
 
 int ntrup_op_batch_inv_rq(ntrup_ctx* ctx, int p, const int16_t* a, int16_t* out, size_t n, size_t group_size,
@@ -905,30 +574,10 @@ int ntrup_op_batch_inv_rq(ntrup_ctx* ctx, int p, const int16_t* a, int16_t* out,
         group_size > 1024)
         return NTRUP_EINVAL;
     if (int r = set_device(ctx)) return r;
-    if (int r = ensure_ws(ctx, ws_bytes(p, n))) return r;
-    const Ws w = carve(ctx->ws, p, n);
-    hipStream_t st = (hipStream_t)stream;
-    GroupArgs g;
-    memset(&g, 0, sizeof g);
-    g.n = (int)n;
-    g.G = (int)group_size;
-    g.bscr = w.bscr;
-    g.err = w.counters + 32;
-    g.a_in = a;
-    g.c_out = out;
-    ctx->last_err.assign(1, w.counters + 32);
-    hipLaunchKernelGGL(zero_ints_kernel, dim3(1), dim3(64), 0, st, w.counters, kCounterInts);
-    const dim3 grid(grid_for(n, group_size)), blk(64);
     const bool mfma = ctx->cfg[param_slot(p)].product_engine == 1;
-#define NTRUP_INV(PP)                                                                      \
-    case PP:                                                                               \
-        if (mfma) hipLaunchKernelGGL((group_mfma_kernel<PP>), grid, blk, 0, st, g); \
-        else hipLaunchKernelGGL((group_kernel<PP, false>), grid, blk, 0, st, g);           \
-        break;
-    switch (p) { NTRUP_INV(653) NTRUP_INV(761) NTRUP_INV(857) NTRUP_INV(1277) }
-#undef NTRUP_INV
-    NTRUP_HIP(ctx, hipGetLastError());
-    return 0;
+    hipStream_t st = (hipStream_t)stream;
+    return ws_call(ctx, st,
+                   [&]() -> int { NTRUP_BY_P(p, op_batch_inv_rq<P>(ctx, mfma, a, out, n, group_size, st)); });
 }
 
 int ntrup_op_sample(ntrup_ctx* ctx, int p, const uint8_t* seed, uint64_t first_index, size_t n, int attempt,
@@ -938,19 +587,9 @@ int ntrup_op_sample(ntrup_ctx* ctx, int p, const uint8_t* seed, uint64_t first_i
         return NTRUP_EINVAL;
     if (int r = set_device(ctx)) return r;
     const Seed sd = make_seed(seed);
-    hipStream_t st = (hipStream_t)stream;
-    const unsigned gw = grid_for(n * (size_t)ceil_div(p, 32), 256);
-#define NTRUP_SAMPLE(PP)                                                                                      \
-    case PP:                                                                                                  \
-        if (f) hipLaunchKernelGGL(sample_short_kernel<PP>, dim3(grid_for(n, 4)), dim3(256), 0, st, sd,        \
-                                  first_index, (int)n, f);                                                    \
-        if (g) hipLaunchKernelGGL(sample_small_kernel<PP>, dim3(gw), dim3(256), 0, st, sd, first_index, (int)n, \
-                                  attempt, g);                                                                \
-        break;
-    switch (p) { NTRUP_SAMPLE(653) NTRUP_SAMPLE(761) NTRUP_SAMPLE(857) NTRUP_SAMPLE(1277) }
-#undef NTRUP_SAMPLE
-    NTRUP_HIP(ctx, hipGetLastError());
-    return 0;
+    NTRUP_BY_P(p, op_sample<P>(ctx, sd, first_index, n, attempt, f, g, (hipStream_t)stream));
 }
+
+#undef NTRUP_BY_P
 
 }  // extern "C"

@@ -643,12 +643,36 @@ __global__ __launch_bounds__(256) void sample_small_kernel(Seed seed, uint64_t f
         rows[(size_t)key * P + 32 * k + e] = (int8_t)(((m >> e) & 1u) * (1 - 2 * ((s >> e) & 1u)));
 }
 
-__global__ void copy_flags_kernel(int n, const uint8_t* src, int32_t* dst) {
+// Optional raw outputs of KeyGen from its encoded key pair: h (int16), f and
+// 1/g (int8), centered, [n][p] each; one thread per coefficient, any pointer
+// may be null.  The inverse of the pk / sk encodings of kg_encode.
+template <int P>
+__global__ __launch_bounds__(256) void decode_raw_kernel(int n, const uint8_t* pk, const uint8_t* sk, int16_t* h,
+                                                         int8_t* f, int8_t* ginv) {
+    constexpr int Q = Param<P>::q, PKB = pk_bytes(P), SKH = sk_half_bytes(P);
+    const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (size_t)n * P) return;
+    const size_t key = t / P;
+    const int i = (int)(t - key * P);
+    if (h) {
+        const uint8_t* b = pk + key * PKB;
+        const int bit = 13 * i, by = bit >> 3;
+        uint32_t v = b[by] | ((uint32_t)b[by + 1] << 8);   // 13 * i + 12 < 13 p: by + 1 < PKB
+        if (by + 2 < PKB) v |= (uint32_t)b[by + 2] << 16;
+        h[t] = (int16_t)((int32_t)((v >> (bit & 7)) & 0x1FFFu) - (Q - 1) / 2);
+    }
+    const uint8_t* s = sk + key * 2 * SKH;
+    if (f) f[t] = (int8_t)((int32_t)((s[i >> 2] >> (2 * (i & 3))) & 3u) - 1);
+    if (ginv) ginv[t] = (int8_t)((int32_t)((s[SKH + (i >> 2)] >> (2 * (i & 3))) & 3u) - 1);
+}
+
+// (static: every object of the library that launches them holds its own copy)
+static __global__ __attribute__((unused)) void copy_flags_kernel(int n, const uint8_t* src, int32_t* dst) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) dst[i] = src[i];
 }
 
-__global__ void zero_ints_kernel(int* p, int count) {
+static __global__ __attribute__((unused)) void zero_ints_kernel(int* p, int count) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < count) p[i] = 0;
 }

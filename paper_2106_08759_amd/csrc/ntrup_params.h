@@ -45,7 +45,8 @@ NTRUP_HD int32_t mul24(int32_t a, int32_t b) {
 // x - q * floor(x * m / 2^32) with m = floor(2^32/q).  For |x| < 2^31 the
 // result lies in (-q/2, 3q/2); for |x| < 2^28 in (-q/16, 17q/16).  The
 // quotient estimate is below 2^23 in magnitude, so q * t is a 24-bit multiply.
-// Checked exhaustively over all int32 inputs by the host test of this header.
+// Checked exhaustively over all int32 inputs (and the 24-bit multiply over
+// its operand ranges) by tests/reduce_check.cpp, built with g++ on the host.
 template <int Q>
 NTRUP_HD int32_t reduce_rough(int32_t x) {
     constexpr int32_t m = barrett_m(Q);

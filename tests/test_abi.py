@@ -45,8 +45,12 @@ def test_params_and_errors_without_gpu(lib):
         assert (prm.q, prm.w, prm.pk_bytes, prm.sk_bytes) == (q, w, pkb, skb)
     assert lib.ntrup_params(760, None, None, None, None) == nk.NTRUP_EINVAL
     # null context / bad arguments are rejected before any device work
-    assert lib.ntrup_batch_keygen(None, 761, bytes(32), 0, 1, 1, 1, None) == nk.NTRUP_EINVAL
-    assert lib.ntrup_ctx_create(None, 0) == nk.NTRUP_EINVAL
+    assert lib.ntrup_batch_keygen(None, 761, bytes(32), 0, 1, 1, 1, None, None, None, None) == nk.NTRUP_EINVAL
+    assert lib.ntrup_ctx_create(None, 0, 0) == nk.NTRUP_EINVAL
+    # workspace needed per call: grows with n, unknown p needs none
+    assert nk.workspace_bytes(761, 1) > 0
+    assert nk.workspace_bytes(761, 65536) > 60000 * nk.workspace_bytes(761, 1) // 2
+    assert nk.workspace_bytes(760, 1) == 0
     assert lib.ntrup_strerror(nk.NTRUP_EAGAIN).decode().startswith("no invertible")
 
 

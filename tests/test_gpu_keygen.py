@@ -233,3 +233,62 @@ def test_eager_split_back_substitution(ctx, p):
                 assert np.array_equal(host(pk), rpk) and np.array_equal(host(sk), rsk), (G, W, L, graph)
     finally:
         ctx.set_config(p, **base)
+
+
+# The configurations bench.py times at N = 65536 (the autotuner picks among
+# them): the per-key R/3 form with the eager split back-substitution
+# (G = 128, W = 1, one lane per key) and the batched-R/3 form (G = 32, W = 4
+# or 8).
+TIMED_CONFIGS = [
+    dict(group_size=128, inverse_share=1, lanes_per_key=1, retry_passes=1, retry_lanes_per_key=8,
+         retry_parallel_attempts=4, use_graph=0, persistent=0, r3_batch=0, product_engine=1),
+    dict(group_size=32, inverse_share=4, lanes_per_key=1, retry_passes=1, retry_lanes_per_key=8,
+         retry_parallel_attempts=4, use_graph=0, persistent=0, r3_batch=1, product_engine=1),
+    dict(group_size=32, inverse_share=8, lanes_per_key=1, retry_passes=1, retry_lanes_per_key=8,
+         retry_parallel_attempts=4, use_graph=0, persistent=0, r3_batch=1, product_engine=1),
+]
+
+
+@pytest.fixture(scope="module")
+def graph_g32_65536(ctx):
+    """Every key of the N = 65536 sntrup761 batch from the G = 32 graph path."""
+    base = ctx.get_config(761)
+    try:
+        ctx.set_config(761, group_size=32, inverse_share=4, lanes_per_key=2, use_graph=1, persistent=0,
+                       r3_batch=0, product_engine=1)
+        pk, sk = ctx.batch_keygen(761, wl.SEED, 0, 65536)
+        return host(pk), host(sk)
+    finally:
+        ctx.set_config(761, **base)
+
+
+@pytest.mark.parametrize("cfg", TIMED_CONFIGS, ids=["perkey_G128_W1_L1_eager", "r3batch_G32_W4_eager",
+                                                     "r3batch_G32_W8_eager"])
+def test_timed_config_65536(ctx, graph_g32_65536, cfg):
+    """The launch bench.py times: eager calls at N = 65536 with the tuned
+    knobs.  256 keys spread over the range equal the oracle's bytes and raw
+    arrays; every key equals the G = 32 graph path's; the timed loop's
+    repeated calls (same buffers, no sync between) give the same bytes."""
+    import torch
+    n = 65536
+    base = ctx.get_config(761)
+    try:
+        ctx.set_config(761, **cfg)
+        pk, sk, h, f, ginv = ctx.batch_keygen(761, wl.SEED, 0, n, raw=True)
+        for _ in range(3):   # as in the timed region: back-to-back calls into the same buffers
+            ctx.batch_keygen(761, wl.SEED, 0, n, pk, sk, check=False)
+        torch.cuda.synchronize()
+        assert ctx.status() == 0
+    finally:
+        ctx.set_config(761, **base)
+    gpk, gsk = host(pk), host(sk)
+    idx = list(np.linspace(0, n - 1, 256).astype(int))
+    ref = oracle_pool.oracle_keys(wl.SEED, 761, idx)
+    rpk, rsk = oracle_pool.pk_sk_arrays(ref, idx)
+    assert np.array_equal(gpk[idx], rpk) and np.array_equal(gsk[idx], rsk)
+    hh, ff, gg = host(h), host(f), host(ginv)
+    for j, i in enumerate(idx):
+        assert np.array_equal(hh[i], ref[i][2]) and np.array_equal(ff[i], ref[i][3]) and \
+            np.array_equal(gg[i], ref[i][4]), i
+    apk, ask = graph_g32_65536
+    assert np.array_equal(gpk, apk) and np.array_equal(gsk, ask)
