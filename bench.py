@@ -253,37 +253,43 @@ def cpu_baseline(p: int, seconds: float, check: list) -> tuple:
             ref)
 
 
+CALIB_KINDS = {0: "arx (add, xor, rotate)", 1: "v_add_u32", 2: "v_bitop3_b32", 3: "v_alignbit_b32", 4: "v_mad_u32_u24"}
+
+
 def calib_valu(iters: int = 20000, reps: int = 5) -> dict:
-    """The vector-ALU probe (csrc/calib_valu.hip): 8 independent add-xor-rotate
-    chains per lane, 24 VALU instructions per step, over 1024 x k one-wave
-    blocks (k waves per SIMD on 256 CUs x 4 SIMDs).  Reports, per k, the mean
-    launch time (HIP events) and the issue rate in lanes per clock per SIMD at
-    2.4 GHz from the source instruction count; the counter run (SQ_INSTS_VALU)
-    of the same command confirms the count."""
+    """The vector-ALU probes (csrc/calib_valu.hip): 8 independent chains per
+    lane of one instruction kind (or the add-xor-rotate mix), over 1024 x k
+    one-wave blocks (k waves per SIMD on 256 CUs x 4 SIMDs).  Reports, per
+    kind and k, the mean launch time (HIP events) and the issue rate in lanes
+    per clock per SIMD at 2.4 GHz from the instruction count; the counter run
+    (SQ_INSTS_VALU) of the same command confirms the count."""
     import ctypes
     import torch
     from paper_2106_08759_amd import build
     L = ctypes.CDLL(build.CALIB_LIB)
-    L.calib_valu.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]
-    ops = L.calib_valu_ops_per_step()
-    out = {"iters": iters, "ops_per_lane_step": ops, "clock_ghz": 2.4, "rates": {}}
+    L.calib_valu.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]
+    out = {"iters": iters, "clock_ghz": 2.4, "kinds": {}}
     st = torch.cuda.current_stream()
-    for k in (1, 2, 4, 8):
-        blocks = 1024 * k
-        buf = torch.empty(blocks * 64, dtype=torch.int32, device="cuda")
-        assert L.calib_valu(blocks, iters, buf.data_ptr(), st.cuda_stream) == 0
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(reps):
-            assert L.calib_valu(blocks, iters, buf.data_ptr(), st.cuda_stream) == 0
-        e1.record()
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / reps
-        wave_insts = blocks * iters * ops
-        out["rates"][k] = {"ms": round(ms, 4), "wave_insts": wave_insts,
-                           "lanes_per_clk_per_simd": round(wave_insts * 64 / (ms / 1e3) / 1024 / 2.4e9, 2),
-                           "T_lane_ops": round(wave_insts * 64 / (ms / 1e3) / 1e12, 2)}
+    for kind, name in CALIB_KINDS.items():
+        ops = L.calib_valu_ops_per_step(kind)
+        rates = {}
+        for k in (1, 2, 4, 8):
+            blocks = 1024 * k
+            buf = torch.empty(blocks * 64, dtype=torch.int32, device="cuda")
+            assert L.calib_valu(kind, blocks, iters, buf.data_ptr(), st.cuda_stream) == 0
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                assert L.calib_valu(kind, blocks, iters, buf.data_ptr(), st.cuda_stream) == 0
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            wave_insts = blocks * iters * ops
+            rates[k] = {"ms": round(ms, 4), "wave_insts": wave_insts,
+                        "lanes_per_clk_per_simd": round(wave_insts * 64 / (ms / 1e3) / 1024 / 2.4e9, 2),
+                        "T_lane_ops": round(wave_insts * 64 / (ms / 1e3) / 1e12, 2)}
+        out["kinds"][name] = {"ops_per_lane_step": ops, "rates": rates}
     return out
 
 
@@ -631,11 +637,11 @@ def main():
         out["autotune"] = {"config": tuned["config"], "use_graph": tuned.get("use_graph"),
                            "eager_ms": tuned.get("eager_ms"), "graph_ms": tuned.get("graph_ms"),
                            "cached": tuned["cached"],
-                           "table_ms": {"%sG%d/W%d/L%d/R%dx%dx%d" % ("P:" if r.get("persistent") else "B:" if r.get("r3_batch") else "",
-                                                                     r["group_size"], r["inverse_share"],
-                                                                     r["lanes_per_key"], r["retry_passes"],
-                                                                     r["retry_lanes_per_key"],
-                                                                     r["retry_parallel_attempts"]): r["ms"]
+                           "table_ms": {"%sG%d/W%d/L%d/R%dx%dx%d%s" % (
+                               "P:" if r.get("persistent") else "B:" if r.get("r3_batch") else "",
+                               r["group_size"], r["inverse_share"], r["lanes_per_key"], r["retry_passes"],
+                               r["retry_lanes_per_key"], r["retry_parallel_attempts"],
+                               "" if r.get("recip_jump", 1) else "/plain-recip"): r["ms"]
                                         for r in tuned.get("table", [])}}
     if cb is not None:
         out["cpu_baseline"] = cb

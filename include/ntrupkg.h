@@ -140,7 +140,14 @@ const char *ntrup_strerror(int code);
  *                        divsteps).  Same keys either way.  Requires
  *                        product_engine 1 and persistent 0.  2: the same
  *                        without the screen, so that every group holding a
- *                        non-unit g takes the fallback (for its tests).    */
+ *                        non-unit g takes the fallback (for its tests).
+ *   recip_jump           the shared R/q reciprocal of the prefix kernel (and
+ *                        ntrup_op_recip_rq) by 0: the plain loop of 2p - 1
+ *                        constant-time divsteps over the full polynomials;
+ *                        1: jump divsteps -- 48 steps at a time on the low 64
+ *                        coefficients, building their 2x2 transition matrix,
+ *                        which is then applied to the full polynomials on the
+ *                        int8 matrix cores.  Same result.                  */
 typedef struct {
     int group_size;
     int lanes_per_key;
@@ -152,6 +159,7 @@ typedef struct {
     int inverse_share;
     int persistent;
     int r3_batch;
+    int recip_jump;
 } ntrup_config;
 
 int ntrup_get_config(const ntrup_ctx *ctx, int p, ntrup_config *cfg);

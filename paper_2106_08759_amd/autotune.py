@@ -17,7 +17,9 @@ Knobs (see ``ntrup_config`` in include/ntrupkg.h):
                  call (1);
   r3_batch       one divstep reciprocal in R/3 per key (0) or the R/3
                  reciprocals of each Montgomery group batched as in
-                 Algorithm 1 (1).
+                 Algorithm 1 (1);
+  recip_jump     the shared R/q reciprocal by the plain divstep loop (0) or
+                 by jump divsteps on the matrix cores (1).
 
 The group knobs (G, W) and the R/3 knobs act on different kernels, but in
 eager launches the prefix kernel runs beside the R/3 stage and the two compete
@@ -44,7 +46,7 @@ GROUP_SIZES = (8, 16, 32, 64, 128, 256)
 SHARES = (1, 2, 4, 8)
 PHASE1_LANES = (1, 2, 4)   # R/3 lanes per key timed jointly with (G, W)
 KNOBS = ("group_size", "inverse_share", "lanes_per_key", "retry_passes", "retry_lanes_per_key",
-         "retry_parallel_attempts", "persistent", "r3_batch")
+         "retry_parallel_attempts", "persistent", "r3_batch", "recip_jump")
 # (G, W, lanes per key) settings timed for the persistent fused form
 PERSISTENT_CANDIDATES = ((32, 2, 2), (32, 4, 2), (64, 2, 2), (32, 4, 4), (16, 4, 2))
 # (G, W) settings timed for the batched-R/3 form (its R/3 groups are the
@@ -113,7 +115,8 @@ def _key(device_name: str, p: int, n: int, mode: str = "auto") -> str:
     # v6: entries carry inverse_share, the launch form (eager / graph), the
     # kernel form (stage pipeline / persistent fused kernel) and the R/3 form
     # (per key / batched); G up to 256
-    return "%s|p=%d|n<=%d|%s|v6" % (device_name, p, bucket(n), mode)
+    # v7: and the R/q reciprocal's form (plain / jump divsteps)
+    return "%s|p=%d|n<=%d|%s|v7" % (device_name, p, bucket(n), mode)
 
 
 def load_cache(path: str | None = None) -> dict:
@@ -186,6 +189,7 @@ def tune(ctx, p: int, n: int, seed: bytes | None = None, reps: int = 3, force: b
     cur = {k: base[k] for k in KNOBS}
     cur["persistent"] = 0
     cur["r3_batch"] = 0
+    cur["recip_jump"] = 1
     ctx.set_config(p, product_engine=1)
     table = []
     # phase 1: the group stage, jointly with the R/3 main pass's lanes per key
@@ -217,6 +221,13 @@ def tune(ctx, p: int, n: int, seed: bytes | None = None, reps: int = 3, force: b
         bc = {k: bc[k] for k in KNOBS}
         table.append(dict(bc, ms=round(time_config(ctx, p, n, bc, seed, reps, pk, sk, ug), 4)))
     best = min(table, key=lambda r: r["ms"])
+    # phase 2d: the plain divstep loop for the shared R/q reciprocal at the
+    # chosen setting (the persistent form always runs the plain loop)
+    if not best["persistent"]:
+        pc = {k: best[k] for k in KNOBS}
+        pc["recip_jump"] = 0
+        table.append(dict(pc, ms=round(time_config(ctx, p, n, pc, seed, reps, pk, sk, ug), 4)))
+        best = min(table, key=lambda r: r["ms"])
     cfg = {k: best[k] for k in KNOBS}
     # phase 3 (auto): eager launches (stage overlap) or graph replay (one
     # linear stream, no launch overhead) for the chosen knobs

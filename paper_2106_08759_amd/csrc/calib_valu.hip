@@ -1,10 +1,15 @@
-// Issue-rate probe for the int32 vector ALU (measurement only; not part of
-// the KeyGen library).  Every lane runs 8 independent add-xor-rotate chains
-// (the ChaCha20 quarter-round pattern): each step's three operations depend
-// on the previous step's results in a way no algebraic rewrite folds away
-// (additions mod 2^32 and xors do not commute, the rotate amounts differ per
-// chain), so the instruction count the hardware counters report (SQ_INSTS_VALU)
-// is what actually issued.  Timed over grids of 1, 2, 4 or 8 waves per SIMD.
+// Issue-rate probes for the int32 vector ALU (measurement only; not part of
+// the KeyGen library).  Each probe runs 8 independent two-register chains per
+// lane in which every step's operations depend on the previous step's
+// results and no algebraic rewrite removes one (nonlinear mixes, or funnel
+// shifts of two different registers); the hardware counters (SQ_INSTS_VALU)
+// confirm the instruction count.  Kinds:
+//   0 arx     add, xor, rotate (the ChaCha20 quarter-round pattern)
+//   1 add     v_add_u32 pairs in a Fibonacci pattern (a += b; b += a)
+//   2 bitop3  v_bitop3_b32 with the majority function (a = maj(a, b, c) ...)
+//   3 align   v_alignbit_b32 of two registers (a = alignbit(a, b, s) ...)
+//   4 mad24   v_mad_u32_u24 (a = a * b + c on 24-bit operands)
+// Timed over grids of 1, 2, 4 or 8 waves per SIMD.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -15,35 +20,69 @@ __device__ __forceinline__ uint32_t rotl(uint32_t x) {
     return __builtin_amdgcn_alignbit(x, x, 32 - R);
 }
 
+__device__ __forceinline__ uint32_t maj3(uint32_t a, uint32_t b, uint32_t c) {
+    uint32_t r;
+    asm volatile("v_bitop3_b32 %0, %1, %2, %3 bitop3:0xe8" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+    return r;
+}
+
+template <int KIND>
 __global__ __launch_bounds__(64) void valu_chain_kernel(uint32_t* out, int iters) {
     const uint32_t t = blockIdx.x * 64u + threadIdx.x;
-    uint32_t a0 = t, a1 = t ^ 0x9E3779B9u, a2 = t * 3u, a3 = t + 7u, a4 = ~t, a5 = t ^ 0x7F4A7C15u, a6 = t << 3,
-             a7 = t + 0x6A09E667u;
-    uint32_t b0 = 1u, b1 = 2u, b2 = 3u, b3 = 5u, b4 = 7u, b5 = 11u, b6 = 13u, b7 = 17u;
-    for (int i = 0; i < iters; i++) {
-#define NTRUP_STEP(A, B, R) \
-    A += B;                 \
-    B = rotl<R>(B ^ A);
-        NTRUP_STEP(a0, b0, 7) NTRUP_STEP(a1, b1, 8) NTRUP_STEP(a2, b2, 9) NTRUP_STEP(a3, b3, 11)
-        NTRUP_STEP(a4, b4, 12) NTRUP_STEP(a5, b5, 13) NTRUP_STEP(a6, b6, 16) NTRUP_STEP(a7, b7, 5)
-#undef NTRUP_STEP
+    uint32_t a[8], b[8];
+#pragma unroll
+    for (int k = 0; k < 8; k++) {
+        a[k] = t * (2u * k + 1u) + 0x9E3779B9u * k;
+        b[k] = (t ^ (0x7F4A7C15u * (k + 1))) | 1u;
     }
-    out[t] = a0 ^ a1 ^ a2 ^ a3 ^ a4 ^ a5 ^ a6 ^ a7 ^ b0 ^ b1 ^ b2 ^ b3 ^ b4 ^ b5 ^ b6 ^ b7;
+    for (int i = 0; i < iters; i++) {
+#pragma unroll
+        for (int k = 0; k < 8; k++) {
+            if constexpr (KIND == 0) {
+                a[k] += b[k];
+                b[k] = rotl<7>(b[k] ^ a[k]);
+            } else if constexpr (KIND == 1) {
+                a[k] += b[k];
+                b[k] += a[k];
+            } else if constexpr (KIND == 2) {
+                a[k] = maj3(a[k], b[k], a[(k + 1) & 7]);
+                b[k] = maj3(b[k], a[k], b[(k + 3) & 7]);
+            } else if constexpr (KIND == 3) {
+                a[k] = __builtin_amdgcn_alignbit(a[k], b[k], 3 + 2 * k);
+                b[k] = __builtin_amdgcn_alignbit(b[k], a[k], 29 - 2 * k);
+            } else {
+                a[k] = __umul24(a[k], b[k]) + 0x5bd1e995u;
+                b[k] = __umul24(b[k], a[k]) + 0x1b873593u;
+            }
+        }
+    }
+    uint32_t x = 0;
+#pragma unroll
+    for (int k = 0; k < 8; k++) x ^= a[k] ^ b[k];
+    out[t] = x;
 }
 
 }  // namespace
 
 extern "C" {
 
-// Launch `blocks` one-wave blocks of `iters` chain steps each on `stream`;
-// out: device, blocks * 64 words.  Returns a hipError_t.
-int calib_valu(int blocks, int iters, uint32_t* out, void* stream) {
-    if (blocks <= 0 || iters <= 0 || !out) return (int)hipErrorInvalidValue;
-    hipLaunchKernelGGL(valu_chain_kernel, dim3((unsigned)blocks), dim3(64), 0, (hipStream_t)stream, out, iters);
+// Launch probe `kind` (0..4) over `blocks` one-wave blocks of `iters` steps
+// each on `stream`; out: device, blocks * 64 words.  Returns a hipError_t.
+int calib_valu(int kind, int blocks, int iters, uint32_t* out, void* stream) {
+    if (blocks <= 0 || iters <= 0 || !out || kind < 0 || kind > 4) return (int)hipErrorInvalidValue;
+    const hipStream_t st = (hipStream_t)stream;
+    switch (kind) {
+        case 0: hipLaunchKernelGGL(valu_chain_kernel<0>, dim3((unsigned)blocks), dim3(64), 0, st, out, iters); break;
+        case 1: hipLaunchKernelGGL(valu_chain_kernel<1>, dim3((unsigned)blocks), dim3(64), 0, st, out, iters); break;
+        case 2: hipLaunchKernelGGL(valu_chain_kernel<2>, dim3((unsigned)blocks), dim3(64), 0, st, out, iters); break;
+        case 3: hipLaunchKernelGGL(valu_chain_kernel<3>, dim3((unsigned)blocks), dim3(64), 0, st, out, iters); break;
+        default: hipLaunchKernelGGL(valu_chain_kernel<4>, dim3((unsigned)blocks), dim3(64), 0, st, out, iters); break;
+    }
     return (int)hipGetLastError();
 }
 
-// Source-level VALU operations per lane and chain step (add, xor, rotate).
-int calib_valu_ops_per_step(void) { return 3 * 8; }
+// VALU instructions per lane and step of probe `kind` (8 chains x 3 for the
+// add-xor-rotate mix, 8 x 2 otherwise).
+int calib_valu_ops_per_step(int kind) { return kind == 0 ? 24 : 16; }
 
 }

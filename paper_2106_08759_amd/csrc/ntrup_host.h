@@ -192,7 +192,7 @@ int op_mul_rq(ntrup_ctx* ctx, bool mfma, const int16_t* a, const int16_t* b, int
 template <int P>
 int op_mul_r3(ntrup_ctx* ctx, const int8_t* a, const int8_t* b, int8_t* c, size_t n, hipStream_t st);
 template <int P>
-int op_recip_rq(ntrup_ctx* ctx, const int16_t* a, int16_t* out, int32_t* ok, size_t n, hipStream_t st);
+int op_recip_rq(ntrup_ctx* ctx, bool jump, const int16_t* a, int16_t* out, int32_t* ok, size_t n, hipStream_t st);
 template <int P>
 int op_recip_r3(ntrup_ctx* ctx, int lpk, const int8_t* a, int8_t* out, int32_t* ok, size_t n, hipStream_t st);
 template <int P>

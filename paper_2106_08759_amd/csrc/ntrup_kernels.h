@@ -20,9 +20,11 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
 #include <utility>
 
 #include "ntrup_chacha.h"
+#include "ntrup_jump.h"
 #include "ntrup_mfma.h"
 #include "ntrup_params.h"
 #include "ntrup_r3.h"
@@ -606,14 +608,19 @@ __global__ __launch_bounds__(64) void mulm_kernel(int n, const int16_t* a, const
     mfma_mul<P, BIG>(L.TL, L.TH, L.HL, L.HH, nullptr, nullptr, nullptr, c + (size_t)e * P);
 }
 
-template <int P>
+// R/q reciprocals of n rows: by the plain divstep loop (J = false) or by
+// jump divsteps on the matrix cores (J = true).
+template <int P, bool J>
 __global__ __launch_bounds__(64) void recip_q_kernel(int n, const int16_t* a, int16_t* out, int32_t* ok) {
     __shared__ GroupLds<P> L;
+    __shared__ typename std::conditional<J, JumpLds<P>, char>::type JL;
     const int e = blockIdx.x;
     if (e >= n) return;
     load_row16<P>(a + (size_t)e * P, L.Bb);
     __syncthreads();
-    const int r = recip_wave<P>(L.Bb, L.Bb, L.Pk);
+    int r;
+    if constexpr (J) r = recip_jump_wave<P>(L.Bb, L.Bb, JL);
+    else r = recip_wave<P>(L.Bb, L.Bb, L.Pk);
     for (int j = lane_id(); j < P; j += 64) out[(size_t)e * P + j] = L.Bb[j];
     if (lane_id() == 0) ok[e] = r;
 }

@@ -33,6 +33,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "ntrup_kernels.h"
 #include "ntrup_mfma.h"
 #include "ntrup_params.h"
@@ -442,9 +444,13 @@ __device__ __forceinline__ void kg_prefix_chain(const GroupArgs& args, int kw0, 
 // t = 1/P_w of every group to tinv (int16 [groups][p]).  The other waves end
 // after the prefix barrier, so their registers serve other work (the R/3
 // stage runs beside this kernel) while wave 0 runs the reciprocal.
-template <int P, int W>
+//
+// J: the shared reciprocal by jump divsteps on the matrix cores
+// (recip_jump_wave) instead of the plain divstep loop (recip_wave).
+template <int P, int W, bool J>
 __global__ __launch_bounds__(64 * W, (P < 800 ? 2 : 1)) void keygen_prefix_kernel(GroupArgs args, int16_t* tinv) {
     __shared__ KgPrefixWave<P> LW[W];
+    __shared__ typename std::conditional<J, JumpLds<P>, char>::type JL;
     const int wave = (int)(threadIdx.x >> 6);
     KgPrefixWave<P>& L = LW[wave];
     const int n = args.n;
@@ -462,7 +468,9 @@ __global__ __launch_bounds__(64 * W, (P < 800 ? 2 : 1)) void keygen_prefix_kerne
     if (wave != 0) return;   // no barrier follows: wave 0 finishes alone
 
     if (W == 1) {
-        const int ok = recip_wave<P>(L.Bb, L.Bb, L.ST);
+        int ok;
+        if constexpr (J) ok = recip_jump_wave<P>(L.Bb, L.Bb, JL);
+        else ok = recip_wave<P>(L.Bb, L.Bb, L.ST);
         if (!ok && lane_id() == 0) atomicOr(args.err, 2);
     } else {
         // Q_{w-1} -> LW[w].Cb, Q_{W-1} -> LW[0].Cb; the Hankel arrays are
@@ -477,7 +485,9 @@ __global__ __launch_bounds__(64 * W, (P < 800 ? 2 : 1)) void keygen_prefix_kerne
                               nullptr);
         }
         wave_sync();
-        const int ok = recip_wave<P>(LW[0].Cb, LW[0].Cb, L.ST);
+        int ok;
+        if constexpr (J) ok = recip_jump_wave<P>(LW[0].Cb, LW[0].Cb, JL);
+        else ok = recip_wave<P>(LW[0].Cb, LW[0].Cb, L.ST);
         if (!ok && lane_id() == 0) atomicOr(args.err, 2);
         for (int w = W - 1; w >= 1; w--) {
             wave_sync();

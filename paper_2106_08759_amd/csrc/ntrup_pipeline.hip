@@ -32,6 +32,27 @@ void launch_r3(int lpk, size_t n, const R3Args& a, hipStream_t st) {
     }
 }
 
+// The prefix kernel with W waves per workgroup; jump: its shared reciprocal
+// by jump divsteps.
+template <int P, bool J>
+void launch_prefix_j(int W, dim3 grid, hipStream_t st, const GroupArgs& g, int16_t* tinv) {
+    const dim3 blk(64 * W);
+    switch (W) {
+        case 1: hipLaunchKernelGGL((keygen_prefix_kernel<P, 1, J>), grid, blk, 0, st, g, tinv); break;
+        case 2: hipLaunchKernelGGL((keygen_prefix_kernel<P, 2, J>), grid, blk, 0, st, g, tinv); break;
+        case 4: hipLaunchKernelGGL((keygen_prefix_kernel<P, 4, J>), grid, blk, 0, st, g, tinv); break;
+        default:
+            if constexpr (P != 1277) hipLaunchKernelGGL((keygen_prefix_kernel<P, 8, J>), grid, blk, 0, st, g, tinv);
+            break;
+    }
+}
+
+template <int P>
+void launch_prefix(int W, bool jump, dim3 grid, hipStream_t st, const GroupArgs& g, int16_t* tinv) {
+    if (jump) launch_prefix_j<P, true>(W, grid, st, g, tinv);
+    else launch_prefix_j<P, false>(W, grid, st, g, tinv);
+}
+
 }  // namespace
 
 // The optional raw arrays of a job, decoded from its encoded keys.
@@ -99,15 +120,7 @@ int enqueue_keygen(ntrup_ctx* ctx, const ntrup_config& cfg, const Seed& seed, ui
         NTRUP_HIP(ctx, hipStreamWaitEvent(ss, ctx->side_fork, 0));
     }
     if (mfma) {
-        const dim3 grid(grid_for(n, (size_t)cfg.group_size * W)), blk(64 * W);
-        switch (W) {
-            case 1: hipLaunchKernelGGL((keygen_prefix_kernel<P, 1>), grid, blk, 0, sp, g, w.tinv); break;
-            case 2: hipLaunchKernelGGL((keygen_prefix_kernel<P, 2>), grid, blk, 0, sp, g, w.tinv); break;
-            case 4: hipLaunchKernelGGL((keygen_prefix_kernel<P, 4>), grid, blk, 0, sp, g, w.tinv); break;
-            default:
-                if constexpr (P != 1277) hipLaunchKernelGGL((keygen_prefix_kernel<P, 8>), grid, blk, 0, sp, g, w.tinv);
-                break;
-        }
+        launch_prefix<P>(W, cfg.recip_jump != 0, dim3(grid_for(n, (size_t)cfg.group_size * W)), sp, g, w.tinv);
         // with a side stream, the back-substitution (which needs only f) runs
         // there too, and only h = g c and the encoding follow the R/3 stage
         if (side)
@@ -235,8 +248,9 @@ int op_mul_r3(ntrup_ctx* ctx, const int8_t* a, const int8_t* b, int8_t* c, size_
 }
 
 template <int P>
-int op_recip_rq(ntrup_ctx* ctx, const int16_t* a, int16_t* out, int32_t* ok, size_t n, hipStream_t st) {
-    hipLaunchKernelGGL(recip_q_kernel<P>, dim3((unsigned)n), dim3(64), 0, st, (int)n, a, out, ok);
+int op_recip_rq(ntrup_ctx* ctx, bool jump, const int16_t* a, int16_t* out, int32_t* ok, size_t n, hipStream_t st) {
+    if (jump) hipLaunchKernelGGL((recip_q_kernel<P, true>), dim3((unsigned)n), dim3(64), 0, st, (int)n, a, out, ok);
+    else hipLaunchKernelGGL((recip_q_kernel<P, false>), dim3((unsigned)n), dim3(64), 0, st, (int)n, a, out, ok);
     NTRUP_HIP(ctx, hipGetLastError());
     return 0;
 }
@@ -301,7 +315,7 @@ template int op_decode_raw<NTRUP_P>(ntrup_ctx*, size_t, const uint8_t*, const ui
 template int op_mul_rq<NTRUP_P>(ntrup_ctx*, bool, const int16_t*, const int16_t*, int16_t*, size_t, bool,
                                 hipStream_t);
 template int op_mul_r3<NTRUP_P>(ntrup_ctx*, const int8_t*, const int8_t*, int8_t*, size_t, hipStream_t);
-template int op_recip_rq<NTRUP_P>(ntrup_ctx*, const int16_t*, int16_t*, int32_t*, size_t, hipStream_t);
+template int op_recip_rq<NTRUP_P>(ntrup_ctx*, bool, const int16_t*, int16_t*, int32_t*, size_t, hipStream_t);
 template int op_recip_r3<NTRUP_P>(ntrup_ctx*, int, const int8_t*, int8_t*, int32_t*, size_t, hipStream_t);
 template int op_batch_inv_rq<NTRUP_P>(ntrup_ctx*, bool, const int16_t*, int16_t*, size_t, size_t, hipStream_t);
 template int op_sample<NTRUP_P>(ntrup_ctx*, const Seed&, uint64_t, size_t, int, int8_t*, int8_t*, hipStream_t);

@@ -292,3 +292,24 @@ def test_timed_config_65536(ctx, graph_g32_65536, cfg):
             np.array_equal(gg[i], ref[i][4]), i
     apk, ask = graph_g32_65536
     assert np.array_equal(gpk, apk) and np.array_equal(gsk, ask)
+
+
+@pytest.mark.parametrize("p", [653, 761, 857, 1277])
+def test_recip_forms_bit_exact(ctx, p):
+    """The shared R/q reciprocal of the prefix kernel by the plain divstep
+    loop (recip_jump = 0) and by jump divsteps (1): the oracle's keys for
+    every W (one reciprocal shared by W groups) and ragged groups, eager and
+    graph launches."""
+    n = 150
+    ref = oracle_pool.oracle_keys(wl.SEED, p, range(n))
+    rpk, rsk = oracle_pool.pk_sk_arrays(ref, range(n))
+    base = ctx.get_config(p)
+    try:
+        for jump in (0, 1):
+            for W, G, graph in ((1, 13, 0), (2, 7, 1), (4, 16, 0)):
+                ctx.set_config(p, product_engine=1, persistent=0, r3_batch=0, recip_jump=jump, inverse_share=W,
+                               group_size=G, use_graph=graph)
+                pk, sk = ctx.batch_keygen(p, wl.SEED, 0, n)
+                assert np.array_equal(host(pk), rpk) and np.array_equal(host(sk), rsk), (jump, W, G, graph)
+    finally:
+        ctx.set_config(p, **base)

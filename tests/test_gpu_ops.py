@@ -111,8 +111,11 @@ def test_mul_engines_agree_on_many(ctx, p):
     assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
 
 
+@pytest.mark.parametrize("jump", [0, 1])
 @pytest.mark.parametrize("p", P_ALL)
-def test_recip_rq_matches_oracle(ctx, p):
+def test_recip_rq_matches_oracle(ctx, p, jump):
+    """The plain divstep loop (jump = 0) and jump divsteps on the matrix cores
+    (jump = 1): random units, 1, x, 0 (not a unit), the extreme elements."""
     _, q, _ = wl.PQW[p]
     a = wl.random_rq(p, 5, tag=5)
     a[3] = 0
@@ -120,9 +123,14 @@ def test_recip_rq_matches_oracle(ctx, p):
     a[4] = 0
     a[4, 1] = 1          # x
     z = np.zeros((1, p), dtype=np.int16)  # 0 is not a unit
-    a = np.concatenate([a, z, wl.extreme_rq(p)[:1]])
-    out, ok = ctx.recip_rq(p, dev(a))
-    out, ok = host(out), host(ok)
+    a = np.concatenate([a, z, wl.extreme_rq(p)])
+    base = ctx.get_config(p)
+    try:
+        ctx.set_config(p, recip_jump=jump)
+        out, ok = ctx.recip_rq(p, dev(a))
+        out, ok = host(out), host(ok)
+    finally:
+        ctx.set_config(p, **base)
     for i in range(len(a)):
         ref = oracle.inv_mod(a[i], p, q)
         assert ok[i] == (ref is not None), (p, i)
