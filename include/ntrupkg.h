@@ -63,6 +63,7 @@ extern "C" {
 #define NTRUP_EFAULT (-14)  /* a group product was not a unit (cannot happen in a field) */
 #define NTRUP_ETIME (-62)   /* persistent form: an item's input was not ready within
                                its bounded wait (about 0.1 s); outputs are invalid */
+#define NTRUP_ERANGE (-34)  /* ntrup_batch_keygen_noalloc: n exceeds its static scratch */
 
 #define NTRUP_MAX_ATTEMPTS 64
 
@@ -202,6 +203,23 @@ typedef struct {
 
 int ntrup_batch_keygen_mixed(ntrup_ctx *ctx, const uint8_t *seed, const ntrup_job *jobs, size_t njobs,
                              void *stream);
+
+/* The same keys as ntrup_batch_keygen, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): this call allocates nothing -- no
+ * hipMalloc, hipFree or allocating library routine.  Its workspace is a
+ * static device array of 32 MiB linked into the library (one copy per GPU
+ * the library runs on, held until the process ends), so n is limited to
+ * ntrup_workspace_bytes(p, n) <= 32 MiB (about 4,800 sntrup761 keys, 2,900
+ * sntrup1277 keys); a larger n returns NTRUP_ERANGE and enqueues nothing.
+ * The context supplies the tuning config (graph replay is not used: launches
+ * are enqueued on `stream` alone, so the call may itself be captured) and
+ * ntrup_ctx_status reports its key-level failures.  Every call on one GPU
+ * shares that array: calls that overlap on one GPU (other streams, other
+ * contexts, other host threads) race and must be ordered by the caller.
+ * Arguments, outputs and errors as for ntrup_batch_keygen. */
+int ntrup_batch_keygen_noalloc(ntrup_ctx *ctx, int p, const uint8_t *seed, uint64_t first_index, size_t n,
+                               uint8_t *pk, uint8_t *sk, int16_t *h, int8_t *f, int8_t *ginv, void *stream);
 
 /* Synchronise `stream` and report the last keygen call on this context:
  * 0, NTRUP_EAGAIN, NTRUP_EFAULT or NTRUP_EIO. */

@@ -24,6 +24,8 @@ NTRUP_ENOMEM = -12
 NTRUP_EINVAL = -22
 NTRUP_EFAULT = -14
 NTRUP_ETIME = -62
+NTRUP_ERANGE = -34
+NOALLOC_SCRATCH_BYTES = 32 << 20   # the static scratch of ntrup_batch_keygen_noalloc
 
 
 class NtrupError(RuntimeError):
@@ -77,6 +79,7 @@ def lib() -> ctypes.CDLL:
         "ntrup_set_config": (i32, [vp, i32, ctypes.POINTER(_Config)]),
         "ntrup_batch_keygen": (i32, [vp, i32, ctypes.c_char_p, u64, sz, vp, vp, vp, vp, vp, vp]),
         "ntrup_keygen_plain": (i32, [vp, i32, ctypes.c_char_p, u64, sz, vp, vp, vp]),
+        "ntrup_batch_keygen_noalloc": (i32, [vp, i32, ctypes.c_char_p, u64, sz, vp, vp, vp, vp, vp, vp]),
         "ntrup_batch_keygen_mixed": (i32, [vp, ctypes.c_char_p, ctypes.POINTER(_Job), sz, vp]),
         "ntrup_ctx_status": (i32, [vp, vp]),
         "ntrup_ctx_timing_begin": (i32, [vp, i32]),
@@ -142,6 +145,18 @@ def _seed_bytes(seed) -> bytes:
 def workspace_bytes(p: int, n: int) -> int:
     """Device workspace a call of n keys of parameter set p needs."""
     return lib().ntrup_workspace_bytes(p, n)
+
+
+def noalloc_max_keys(p: int) -> int:
+    """Largest n that ntrup_batch_keygen_noalloc takes for parameter set p."""
+    lo, hi = 0, 1 << 24
+    while lo < hi:
+        m = (lo + hi + 1) // 2
+        if workspace_bytes(p, m) <= NOALLOC_SCRATCH_BYTES:
+            lo = m
+        else:
+            hi = m - 1
+    return lo
 
 
 class Context:
@@ -251,6 +266,23 @@ class Context:
         if check:
             self._check(self.status(stream), "keygen status")
         return (pk, sk) + tuple(arrays)
+
+    def batch_keygen_noalloc(self, p: int, seed, first_index: int, n: int, pk, sk, raw=None, stream=None,
+                             check: bool = True):
+        """ntrup_batch_keygen_noalloc: the keys of batch_keygen with the
+        library's static scratch as workspace (nothing allocated by the call).
+        pk, sk (and raw = (h, f, ginv), optional) are caller-allocated device
+        tensors."""
+        prm = params(p)
+        assert pk.is_contiguous() and sk.is_contiguous()
+        assert pk.numel() >= n * prm.pk_bytes and sk.numel() >= n * prm.sk_bytes
+        rp = [_ptr(a) for a in raw] if raw is not None else [None, None, None]
+        self._check(lib().ntrup_batch_keygen_noalloc(self._h, p, _seed_bytes(seed), first_index, n, _ptr(pk),
+                                                     _ptr(sk), rp[0], rp[1], rp[2], _stream(stream)),
+                    "keygen_noalloc")
+        if check:
+            self._check(self.status(stream), "keygen status")
+        return pk, sk
 
     def keygen_plain(self, p: int, seed, first_index: int, n: int, **kw):
         return self.batch_keygen(p, seed, first_index, n, plain=True, **kw)

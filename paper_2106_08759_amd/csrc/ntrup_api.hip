@@ -7,6 +7,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -46,6 +47,32 @@ void launch_zero_ints(int* p, int count, hipStream_t st) {
 }  // namespace ntrup
 
 namespace {
+
+// Device scratch of ntrup_batch_keygen_noalloc: the workspace of its calls,
+// linked into the library (each GPU the library runs on holds one copy until
+// the process ends).  Host code never passes `scratch` itself to a kernel or
+// a copy: it is a host-side stand-in; scratch_ptr[d] is device d's address of
+// it, taken with hipGetSymbolAddress once per device.
+constexpr size_t kScratchBytes = (size_t)32 << 20;
+static __device__ __align__(256) uint8_t scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mu;
+void* scratch_ptr[kMaxDevices] = {};
+
+// Device `ctx->device`'s address of the scratch array (that device current).
+int scratch_for(ntrup_ctx* ctx, void** out) {
+    if (ctx->device < 0 || ctx->device >= kMaxDevices) return NTRUP_EINVAL;
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (!scratch_ptr[ctx->device]) {
+        void* ptr = nullptr;
+        NTRUP_HIP(ctx, hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) return NTRUP_EIO;
+        scratch_ptr[ctx->device] = ptr;
+    }
+    *out = scratch_ptr[ctx->device];
+    return 0;
+}
 
 int set_device(ntrup_ctx* ctx) {
     NTRUP_HIP(ctx, hipSetDevice(ctx->device));
@@ -294,6 +321,7 @@ const char* ntrup_strerror(int code) {
         case NTRUP_EINVAL: return "invalid argument";
         case NTRUP_EFAULT: return "group product not a unit";
         case NTRUP_ETIME: return "a persistent-kernel item waited too long for its inputs";
+        case NTRUP_ERANGE: return "n too large for the static scratch of the allocation-free entry point";
     }
     return "unknown error";
 }
@@ -307,6 +335,7 @@ int ntrup_ctx_create(ntrup_ctx** out, int device, size_t workspace_budget_bytes)
     if (!ctx) return NTRUP_ENOMEM;
     ctx->device = device;
     ctx->ws_budget = workspace_budget_bytes;
+    ctx->one_job.reserve(1);
     ctx->last_err.reserve(kJobStreams * 4);
     for (int i = 0; i < 4; i++) ctx->cfg[i] = ntrup_config{32, 2, 8, 4, 1, 1, 1, 4, 0, 0, 1};
     bool ok = set_device(ctx) == 0 && hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking) == hipSuccess;
@@ -461,6 +490,25 @@ int ntrup_batch_keygen_mixed(ntrup_ctx* ctx, const uint8_t* seed, const ntrup_jo
     NTRUP_HIP(ctx, hipGraphLaunch(ctx->exec, st));
     NTRUP_HIP(ctx, hipEventRecord(ctx->graph_done, st));
     return mark_call_end(ctx, st);
+}
+
+int ntrup_batch_keygen_noalloc(ntrup_ctx* ctx, int p, const uint8_t* seed, uint64_t first_index, size_t n,
+                               uint8_t* pk, uint8_t* sk, int16_t* h, int8_t* f, int8_t* ginv, void* stream) {
+    if (!ctx || !seed) return NTRUP_EINVAL;
+    if (int r = check_job(p, n, pk, sk)) return r;
+    if (ws_bytes(p, n) > kScratchBytes) return NTRUP_ERANGE;
+    if (int r = set_device(ctx)) return r;
+    void* base = nullptr;
+    if (int r = scratch_for(ctx, &base)) return r;
+    // eager launches on the caller's stream only: no graph of our own (its
+    // instantiation allocates) and no side stream, so that a caller may
+    // capture the call into a graph of its own
+    // (host vectors reserved at context creation: no host allocation either)
+    std::vector<JobDesc>& jd = ctx->one_job;
+    jd.assign(1, JobDesc{p, first_index, n, pk, sk, RawOut{h, f, ginv}, ctx->cfg[param_slot(p)], 0});
+    jd[0].cfg.use_graph = 0;
+    ctx->last_err.assign(1, carve(base, p, n).counters + 32);
+    return enqueue_jobs(ctx, base, make_seed(seed), jd, (hipStream_t)stream, false);
 }
 
 int ntrup_ctx_timing_begin(ntrup_ctx* ctx, int max_pipelines) {

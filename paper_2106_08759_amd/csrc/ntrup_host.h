@@ -126,6 +126,7 @@ struct ntrup_ctx {
     size_t ws_budget = 0;           // 0: unbounded; else the most workspace the context may hold
     ntrup_config cfg[4];
     std::vector<int*> last_err;     // error words of the last keygen call
+    std::vector<ntrup::JobDesc> one_job;   // the job list of ntrup_batch_keygen_noalloc
     hipStream_t cap_stream = nullptr;
     hipStream_t job_streams[ntrup::kJobStreams] = {};
     // side stream of single-job calls: the prefix half of the group stage
