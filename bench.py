@@ -41,7 +41,7 @@ sys.path.insert(0, ROOT)
 # profiles/valu_issue_rate.md).
 VALU_PEAK = 256 * 4 * 16 * 2.4e9   # int32 lane-ops per second = 39.3 T
 I8_MFMA_PEAK = 5.0e15              # dense int8 matrix-core ops per second (2 per multiply-add)
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "kernel_counters.json")
 
 
 def sources_digest() -> str:
@@ -83,10 +83,12 @@ def kernel_key(name: str) -> str:
     return base.replace(" ", "")
 
 
-def summarize_counters(directory: str, copy_mib: int, workload: str, steps_per_run: int = 0) -> dict:
-    """profiles/hbm_traffic.json from two rocprofv3 --pmc runs of bench.py with
+def summarize_counters(directory: str, copy_mib: int, workload: str, steps_per_run: int = 0,
+                       config: dict | None = None) -> dict:
+    """profiles/kernel_counters.json from rocprofv3 --pmc runs of bench.py with
     --calib-copy-mib: <directory>/fetch and <directory>/write, each holding
-    pmc_counter_collection.csv (FETCH_SIZE, WRITE_SIZE in KiB per dispatch).
+    pmc_counter_collection.csv (FETCH_SIZE, WRITE_SIZE in KiB per dispatch),
+    and optionally <directory>/sq (SQ_INSTS_* per dispatch).
     The plain device copy of copy_mib MiB reads and writes copy_mib MiB; the
     ratio of that to what the counters report for it scales every kernel.
     Host-only: reads CSV files, runs nothing on the GPU."""
@@ -129,7 +131,7 @@ def summarize_counters(directory: str, copy_mib: int, workload: str, steps_per_r
     return {"sources_sha256": sources_digest(),
             "calibration": {"copy_mib": copy_mib, "fetch_kib": round(cal_f, 2), "write_kib": round(cal_w, 2),
                             "fetch_scale": round(fs, 4), "write_scale": round(ws, 4)},
-            "workload": workload, "steps_per_run": steps_per_run, "kernels": kernels}
+            "workload": workload, "config": config or {}, "steps_per_run": steps_per_run, "kernels": kernels}
 
 
 def ceil_div(a, b):
@@ -312,11 +314,13 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the plain-form and N=1024 side measurements")
     ap.add_argument("--summarize-counters", metavar="DIR", default=None,
-                    help="host only: write profiles/hbm_traffic.json from DIR/fetch and DIR/write "
+                    help="host only: write profiles/kernel_counters.json from DIR/fetch, DIR/write, DIR/sq "
                          "(rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs of this script) and exit")
     ap.add_argument("--workload-note", default="", help="workload line stored with --summarize-counters")
     ap.add_argument("--counter-steps", type=int, default=3,
                     help="warmup + timed steps of the counter runs (--summarize-counters)")
+    ap.add_argument("--counter-config", default="",
+                    help="JSON of the configuration the counter runs used (stored with --summarize-counters)")
     ap.add_argument("--calib-valu", action="store_true",
                     help="time the int32 vector-ALU issue-rate probe (libcalib.so) at 1, 2, 4, 8 waves per SIMD "
                          "and exit")
@@ -326,7 +330,7 @@ def main():
 
     if args.summarize_counters:
         data = summarize_counters(args.summarize_counters, args.calib_copy_mib or 256, args.workload_note,
-                                  args.counter_steps)
+                                  args.counter_steps, json.loads(args.counter_config) if args.counter_config else None)
         with open(TRAFFIC_FILE, "w") as fh:
             json.dump(data, fh, indent=1)
             fh.write("\n")
@@ -622,6 +626,7 @@ def main():
                        p, n, cfg["group_size"], ", batched R/3 reciprocals" if cfg.get("r3_batch") else ""),
                    "p": p, "q": prm.q, "w": prm.w, "n_keys": n, "group_size": cfg["group_size"],
                    "inverse_share": cfg["inverse_share"], "lanes_per_key": cfg["lanes_per_key"],
+                   "r3_batch": cfg["r3_batch"], "recip_jump": cfg["recip_jump"],
                    "product_engine": "int8 matrix cores" if cfg["product_engine"] == 1 else "v_dot2",
                    "launch": ("one persistent fused kernel per call" if cfg.get("persistent") else
                               "one captured hipGraph per call (stages on one stream)" if cfg["use_graph"] else

@@ -120,12 +120,56 @@ __device__ __forceinline__ void sample_short_key(const Seed& seed, uint64_t inde
     }
 }
 
+// f of four keys per 256-thread block.  A key needs only NB = ceil(p/16)
+// ChaCha20 blocks (48 at p = 761, against the 64 that one block per lane of a
+// sorting wave would compute), so the block's threads compute the 4 NB blocks
+// first -- one per thread, the threads past them (a whole wave at
+// p = 761) skip -- and pass the words through LDS to the sorting wave of
+// their key.  LDS rows are EPL + 1 words per lane slot, so that both the
+// writes (one ChaCha block per thread) and the reads (one slot per lane) hit
+// 64 different banks.
 template <int P>
 __global__ __launch_bounds__(256) void sample_short_kernel(Seed seed, uint64_t first_index, int n,
                                                            int8_t* __restrict__ f_rows) {
-    const int key = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    constexpr int W = Param<P>::w;
+    constexpr int EPL = ShortShape<P>::EPL;
+    constexpr int SL = EPL + 1;                 // words per lane slot in LDS
+    constexpr int NB = ceil_div(P, 16);         // ChaCha20 blocks per key
+    constexpr int KPB = 4;                      // keys per workgroup (one wave each)
+    static_assert(16 * NB <= 64 * EPL && EPL % 16 == 0, "a key's words fit its sorting network");
+    __shared__ uint32_t words[KPB][64 * SL];
+    const int key0 = blockIdx.x * KPB;
+    const int tid = threadIdx.x;
+    for (int b = tid; b < KPB * NB; b += 64 * KPB) {
+        const int k = b / NB, blk = b - k * NB;
+        if (key0 + k < n) {
+            uint32_t r[16];
+            chacha_block(seed, first_index + (uint64_t)(key0 + k), P, 0, (uint32_t)blk, r);
+            // element i = 16 blk + e sits in lane slot i / EPL at offset i % EPL
+            uint32_t* dst = &words[k][(16 * blk / EPL) * SL + (16 * blk) % EPL];
+#pragma unroll
+            for (int e = 0; e < 16; e++) dst[e] = r[e];
+        }
+    }
+    __syncthreads();
+    const int wave = tid >> 6, lane = tid & 63;
+    const int key = key0 + wave;
     if (key >= n) return;  // whole wave
-    sample_short_key<P>(seed, first_index + (uint64_t)key, f_rows + (size_t)key * P);
+    uint32_t L[EPL];
+#pragma unroll
+    for (int e = 0; e < EPL; e++) {
+        const int i = lane * EPL + e;
+        const uint32_t x = (i < P) ? words[wave][lane * SL + e] : 0u;
+        const uint32_t v = (i < W) ? 2u * (x & 1u) : 1u;
+        L[e] = (i < P) ? ((x & ~3u) | v) : 0xFFFFFFFFu;
+    }
+    bitonic_sort_wave<EPL>(L, lane);
+    int8_t* row = f_rows + (size_t)key * P;
+#pragma unroll
+    for (int e = 0; e < EPL; e++) {
+        const int i = lane * EPL + e;
+        if (i < P) row[i] = (int8_t)((int)(L[e] & 3u) - 1);
+    }
 }
 
 // ----------------------------------------------------------------------------
