@@ -167,6 +167,19 @@ def group_kernel_ops(p: int, n: int, G: int, W: int, split: bool = False) -> dic
     return {"group_prefix": 2 * pre, "group_back": 2 * back}
 
 
+def tree_kernel_ops(p: int, n: int, G: int) -> dict:
+    """Algorithmic int8 matrix-core operations (2 per multiply-add) of the
+    tree form for n keys in groups of G = 2^k: per group, G/2 leaf-pair
+    products (small x small, 1 limb pair), G/2 - 1 inner up-sweep and G - 2
+    inner down-sweep products (big x big, 4 limb pairs), G leaf products
+    c_i = t a_sibling (small x big, 2 limb pairs) -- 3G - 3 in all -- and
+    the h_i products (group_back)."""
+    pre = 0.0
+    for start in range(0, n, G):
+        pre += (G // 2 * 1 + (G // 2 - 1 + G - 2) * 4 + G * 2) * p * p
+    return {"group_prefix": 2 * pre, "group_back": 2.0 * n * 2 * p * p}
+
+
 def r3_kernel_ops(p: int, keys: int) -> float:
     """Algorithmic 32-bit lane-ops of the bitsliced R/3 divsteps: per key and
     divstep j (of 2p-1), 9 ops per live word of the (f, g) pair and 9 per
@@ -372,7 +385,7 @@ def main():
         pers = [r for r in (tuned or {}).get("table", []) if r.get("persistent")]
         pc = {k: v for k, v in min(pers, key=lambda r: r["ms"]).items() if k != "ms"} if pers else \
             {"group_size": 32, "inverse_share": 2, "lanes_per_key": 2, "persistent": 1, "r3_batch": 0}
-        ctx.set_config(p, use_graph=0, r3_batch=0, **pc)
+        ctx.set_config(p, **dict(pc, use_graph=0, r3_batch=0))
     cfg = ctx.get_config(p)
     prm = nk.params(p)
     ctx.reserve(p, n)
@@ -430,7 +443,9 @@ def main():
     # eager single-job launches use the side stream (prefix kernel and
     # back-substitution beside the R/3 stage); captured graphs run one stream
     split = not cfg["use_graph"] and not cfg.get("persistent")
-    ops = dict(group_kernel_ops(p, n, cfg["group_size"], cfg["inverse_share"], split),
+    tree = cfg.get("group_form") == 1
+    ops = dict(tree_kernel_ops(p, n, cfg["group_size"]) if tree else
+               group_kernel_ops(p, n, cfg["group_size"], cfg["inverse_share"], split),
                r3_main=r3_kernel_ops(p, n), sample_short=short_kernel_ops(p, n))
     # the persistent fused kernel does all of it; priced on its vector-ALU work
     # (R/3 divsteps and sampling), its matrix-core work being the smaller share
@@ -462,8 +477,10 @@ def main():
         crit = [k for k in ops if k != "fused" and k not in side]
         dom = max(crit, key=lambda k: avg[k])
     achieved = ops[dom] / (avg[dom] / 1e3)
-    kernel_names = {"group_prefix": "keygen_prefix_kernel<%d,%d>" % (p, cfg["inverse_share"]),
-                    "group_back": ("keygen_h_kernel<%d>" if split else "keygen_back_kernel<%d>") % p,
+    jump = "true" if cfg["recip_jump"] & 1 else "false"
+    kernel_names = {"group_prefix": ("keygen_tree_kernel<%d,%s>" % (p, jump) if tree else
+                                     "keygen_prefix_kernel<%d,%d,%s>" % (p, cfg["inverse_share"], jump)),
+                    "group_back": ("keygen_h_kernel<%d>" if split or tree else "keygen_back_kernel<%d>") % p,
                     "r3_main": "r3_kernel<%d,%d>" % (p, cfg["lanes_per_key"]),
                     "sample_short": "sample_short_kernel<%d>" % p,
                     "fused": "keygen_persistent_kernel<%d,%d>" % (cfg["lanes_per_key"], p)}
@@ -626,7 +643,7 @@ def main():
                        p, n, cfg["group_size"], ", batched R/3 reciprocals" if cfg.get("r3_batch") else ""),
                    "p": p, "q": prm.q, "w": prm.w, "n_keys": n, "group_size": cfg["group_size"],
                    "inverse_share": cfg["inverse_share"], "lanes_per_key": cfg["lanes_per_key"],
-                   "r3_batch": cfg["r3_batch"], "recip_jump": cfg["recip_jump"],
+                   "r3_batch": cfg["r3_batch"], "recip_jump": cfg["recip_jump"], "group_form": cfg["group_form"],
                    "product_engine": "int8 matrix cores" if cfg["product_engine"] == 1 else "v_dot2",
                    "launch": ("one persistent fused kernel per call" if cfg.get("persistent") else
                               "one captured hipGraph per call (stages on one stream)" if cfg["use_graph"] else
@@ -646,7 +663,9 @@ def main():
                                "P:" if r.get("persistent") else "B:" if r.get("r3_batch") else "",
                                r["group_size"], r["inverse_share"], r["lanes_per_key"], r["retry_passes"],
                                r["retry_lanes_per_key"], r["retry_parallel_attempts"],
-                               "" if r.get("recip_jump", 1) else "/plain-recip"): r["ms"]
+                               {0: "/plain-recips", 1: "", 2: "/jump-r3-only", 3: "/jump-r3"}[r.get("recip_jump", 1)]
+                               + ("/tree" if r.get("group_form") else "")):
+                               r["ms"]
                                         for r in tuned.get("table", [])}}
     if cb is not None:
         out["cpu_baseline"] = cb

@@ -142,13 +142,24 @@ const char *ntrup_strerror(int code);
  *                        product_engine 1 and persistent 0.  2: the same
  *                        without the screen, so that every group holding a
  *                        non-unit g takes the fallback (for its tests).
- *   recip_jump           the shared R/q reciprocal of the prefix kernel (and
- *                        ntrup_op_recip_rq) by 0: the plain loop of 2p - 1
- *                        constant-time divsteps over the full polynomials;
- *                        1: jump divsteps -- 48 steps at a time on the low 64
+ *   recip_jump           bit 0: the shared R/q reciprocal of the prefix
+ *                        kernel (and ntrup_op_recip_rq); bit 1: with r3_batch,
+ *                        the R/3 reciprocals of the group products -- by jump
+ *                        divsteps (bit set: 48 steps at a time on the low 64
  *                        coefficients, building their 2x2 transition matrix,
- *                        which is then applied to the full polynomials on the
- *                        int8 matrix cores.  Same result.                  */
+ *                        which is then applied to the full polynomials on
+ *                        the int8 matrix cores) or by the plain loop of
+ *                        2p - 1 constant-time divsteps over the full
+ *                        polynomials (bit clear; bitsliced in R/3).  Same
+ *                        result.
+ *   group_form           0: each Montgomery group a chain (prefix products,
+ *                        the shared reciprocal, back-substitution: about 3G
+ *                        dependent products on one wave); 1: a product tree
+ *                        over the group's G = 2^k keys (2 <= G <= 256), the
+ *                        same 3G - 3 products in 2k dependent levels shared by
+ *                        the 8 waves of a workgroup, one reciprocal per
+ *                        group (inverse_share unused).  Requires
+ *                        product_engine 1 and persistent 0.  Same keys.    */
 typedef struct {
     int group_size;
     int lanes_per_key;
@@ -161,6 +172,7 @@ typedef struct {
     int persistent;
     int r3_batch;
     int recip_jump;
+    int group_form;
 } ntrup_config;
 
 int ntrup_get_config(const ntrup_ctx *ctx, int p, ntrup_config *cfg);
@@ -210,7 +222,7 @@ int ntrup_batch_keygen_mixed(ntrup_ctx *ctx, const uint8_t *seed, const ntrup_jo
  * hipMalloc, hipFree or allocating library routine.  Its workspace is a
  * static device array of 32 MiB linked into the library (one copy per GPU
  * the library runs on, held until the process ends), so n is limited to
- * ntrup_workspace_bytes(p, n) <= 32 MiB (about 4,800 sntrup761 keys, 2,900
+ * ntrup_workspace_bytes(p, n) <= 32 MiB (3,900 sntrup761 keys, 2,290
  * sntrup1277 keys); a larger n returns NTRUP_ERANGE and enqueues nothing.
  * The context supplies the tuning config (graph replay is not used: launches
  * are enqueued on `stream` alone, so the call may itself be captured) and

@@ -49,7 +49,8 @@ class _Config(ctypes.Structure):
                 ("retry_lanes_per_key", ctypes.c_int), ("retry_parallel_attempts", ctypes.c_int),
                 ("retry_passes", ctypes.c_int), ("use_graph", ctypes.c_int),
                 ("product_engine", ctypes.c_int), ("inverse_share", ctypes.c_int),
-                ("persistent", ctypes.c_int), ("r3_batch", ctypes.c_int), ("recip_jump", ctypes.c_int)]
+                ("persistent", ctypes.c_int), ("r3_batch", ctypes.c_int), ("recip_jump", ctypes.c_int),
+                ("group_form", ctypes.c_int)]
 
 
 _lib = None
@@ -200,7 +201,7 @@ class Context:
                 "retry_parallel_attempts": c.retry_parallel_attempts, "retry_passes": c.retry_passes,
                 "use_graph": c.use_graph, "product_engine": c.product_engine,
                 "inverse_share": c.inverse_share, "persistent": c.persistent, "r3_batch": c.r3_batch,
-                "recip_jump": c.recip_jump}
+                "recip_jump": c.recip_jump, "group_form": c.group_form}
 
     def set_config(self, p: int, **kw):
         cur = self.get_config(p)
@@ -208,7 +209,7 @@ class Context:
         c = _Config(cur["group_size"], cur["lanes_per_key"], cur["retry_lanes_per_key"],
                     cur["retry_parallel_attempts"], cur["retry_passes"], cur["use_graph"],
                     cur["product_engine"], cur["inverse_share"], cur["persistent"], cur["r3_batch"],
-                    cur["recip_jump"])
+                    cur["recip_jump"], cur["group_form"])
         self._check(lib().ntrup_set_config(self._h, p, ctypes.byref(c)), "ntrup_set_config")
 
     def reserve(self, p: int, n: int):

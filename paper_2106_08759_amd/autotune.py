@@ -18,8 +18,11 @@ Knobs (see ``ntrup_config`` in include/ntrupkg.h):
   r3_batch       one divstep reciprocal in R/3 per key (0) or the R/3
                  reciprocals of each Montgomery group batched as in
                  Algorithm 1 (1);
-  recip_jump     the shared R/q reciprocal by the plain divstep loop (0) or
-                 by jump divsteps on the matrix cores (1).
+  recip_jump     the shared R/q reciprocal (bit 0) and the batched-R/3
+                 group reciprocals (bit 1) by the plain divstep loop (bit
+                 clear) or by jump divsteps on the matrix cores (bit set);
+  group_form     the R/q batch inversion of a group as a chain (0) or as a
+                 product tree over the waves of a workgroup (1).
 
 The group knobs (G, W) and the R/3 knobs act on different kernels, but in
 eager launches the prefix kernel runs beside the R/3 stage and the two compete
@@ -46,12 +49,14 @@ GROUP_SIZES = (8, 16, 32, 64, 128, 256)
 SHARES = (1, 2, 4, 8)
 PHASE1_LANES = (1, 2, 4)   # R/3 lanes per key timed jointly with (G, W)
 KNOBS = ("group_size", "inverse_share", "lanes_per_key", "retry_passes", "retry_lanes_per_key",
-         "retry_parallel_attempts", "persistent", "r3_batch", "recip_jump")
+         "retry_parallel_attempts", "persistent", "r3_batch", "recip_jump", "group_form")
 # (G, W, lanes per key) settings timed for the persistent fused form
 PERSISTENT_CANDIDATES = ((32, 2, 2), (32, 4, 2), (64, 2, 2), (32, 4, 4), (16, 4, 2))
 # (G, W) settings timed for the batched-R/3 form (its R/3 groups are the
 # Montgomery groups of the R/q stage)
-R3BATCH_CANDIDATES = ((32, 8), (32, 4), (64, 4), (16, 8), (64, 2))
+R3BATCH_CANDIDATES = ((32, 8), (32, 4), (64, 4), (16, 8), (64, 2), (64, 8), (128, 2), (128, 1))
+# group sizes timed for the tree form (group_form = 1) of the R/q batch inversion
+TREE_SIZES = (16, 32, 64, 128)
 
 
 def cache_path() -> str:
@@ -115,8 +120,9 @@ def _key(device_name: str, p: int, n: int, mode: str = "auto") -> str:
     # v6: entries carry inverse_share, the launch form (eager / graph), the
     # kernel form (stage pipeline / persistent fused kernel) and the R/3 form
     # (per key / batched); G up to 256
-    # v7: and the R/q reciprocal's form (plain / jump divsteps)
-    return "%s|p=%d|n<=%d|%s|v7" % (device_name, p, bucket(n), mode)
+    # v8: and the reciprocals' forms (plain / jump divsteps), the group form
+    # (chain / tree)
+    return "%s|p=%d|n<=%d|%s|v8" % (device_name, p, bucket(n), mode)
 
 
 def load_cache(path: str | None = None) -> dict:
@@ -190,6 +196,7 @@ def tune(ctx, p: int, n: int, seed: bytes | None = None, reps: int = 3, force: b
     cur["persistent"] = 0
     cur["r3_batch"] = 0
     cur["recip_jump"] = 1
+    cur["group_form"] = 0
     ctx.set_config(p, product_engine=1)
     table = []
     # phase 1: the group stage, jointly with the R/3 main pass's lanes per key
@@ -221,12 +228,24 @@ def tune(ctx, p: int, n: int, seed: bytes | None = None, reps: int = 3, force: b
         bc = {k: bc[k] for k in KNOBS}
         table.append(dict(bc, ms=round(time_config(ctx, p, n, bc, seed, reps, pk, sk, ug), 4)))
     best = min(table, key=lambda r: r["ms"])
-    # phase 2d: the plain divstep loop for the shared R/q reciprocal at the
-    # chosen setting (the persistent form always runs the plain loop)
+    # phase 2c': the tree form of the R/q batch inversion at a few group sizes
+    # (with the best R/3 form so far: its batched groups are the same size)
+    tb = min((r for r in table if not r["persistent"]), key=lambda r: r["ms"])
+    for g_ in TREE_SIZES:
+        if g_ > max(16, n):
+            continue
+        tc = dict(tb, group_size=g_, inverse_share=1, group_form=1, persistent=0)
+        tc = {k: tc[k] for k in KNOBS}
+        table.append(dict(tc, ms=round(time_config(ctx, p, n, tc, seed, reps, pk, sk, ug), 4)))
+    best = min(table, key=lambda r: r["ms"])
+    # phase 2d: the reciprocal forms at the chosen setting: both plain, and
+    # with batched R/3 also jump divsteps for its group reciprocals (the
+    # persistent form always runs the plain loops)
     if not best["persistent"]:
-        pc = {k: best[k] for k in KNOBS}
-        pc["recip_jump"] = 0
-        table.append(dict(pc, ms=round(time_config(ctx, p, n, pc, seed, reps, pk, sk, ug), 4)))
+        for rj in ((0, 3) if best["r3_batch"] else (0,)):
+            pc = {k: best[k] for k in KNOBS}
+            pc["recip_jump"] = rj
+            table.append(dict(pc, ms=round(time_config(ctx, p, n, pc, seed, reps, pk, sk, ug), 4)))
         best = min(table, key=lambda r: r["ms"])
     cfg = {k: best[k] for k in KNOBS}
     # phase 3 (auto): eager launches (stage overlap) or graph replay (one

@@ -229,7 +229,10 @@ bool valid_config(const ntrup_config& c) {
            (c.persistent == 0 ||
             (c.persistent == 1 && c.product_engine == 1 && (c.lanes_per_key == 2 || c.lanes_per_key == 4))) &&
            (c.r3_batch == 0 || ((c.r3_batch == 1 || c.r3_batch == 2) && c.product_engine == 1 && c.persistent == 0)) &&
-           (c.recip_jump == 0 || c.recip_jump == 1);
+           (c.recip_jump >= 0 && c.recip_jump <= 3) &&
+           (c.group_form == 0 || (c.group_form == 1 && c.product_engine == 1 && c.persistent == 0 &&
+                                  c.group_size >= 2 && c.group_size <= kTreeRows &&
+                                  (c.group_size & (c.group_size - 1)) == 0));
 }
 
 int check_job(int p, size_t n, const void* pk, const void* sk) {
@@ -337,7 +340,7 @@ int ntrup_ctx_create(ntrup_ctx** out, int device, size_t workspace_budget_bytes)
     ctx->ws_budget = workspace_budget_bytes;
     ctx->one_job.reserve(1);
     ctx->last_err.reserve(kJobStreams * 4);
-    for (int i = 0; i < 4; i++) ctx->cfg[i] = ntrup_config{32, 2, 8, 4, 1, 1, 1, 4, 0, 0, 1};
+    for (int i = 0; i < 4; i++) ctx->cfg[i] = ntrup_config{32, 2, 8, 4, 1, 1, 1, 4, 0, 0, 1, 0};
     bool ok = set_device(ctx) == 0 && hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking) == hipSuccess;
     for (int i = 0; ok && i < kJobStreams; i++)
         ok = hipStreamCreateWithFlags(&ctx->job_streams[i], hipStreamNonBlocking) == hipSuccess;
@@ -606,7 +609,7 @@ int ntrup_op_mul_r3(ntrup_ctx* ctx, int p, const int8_t* a, const int8_t* b, int
 int ntrup_op_recip_rq(ntrup_ctx* ctx, int p, const int16_t* a, int16_t* out, int32_t* ok, size_t n, void* stream) {
     if (!ctx || param_slot(p) < 0 || !a || !out || !ok || n == 0 || n > 0x7FFFFFFF) return NTRUP_EINVAL;
     if (int r = set_device(ctx)) return r;
-    const bool jump = ctx->cfg[param_slot(p)].recip_jump != 0;
+    const bool jump = (ctx->cfg[param_slot(p)].recip_jump & 1) != 0;
     NTRUP_BY_P(p, op_recip_rq<P>(ctx, jump, a, out, ok, n, (hipStream_t)stream));
 }
 

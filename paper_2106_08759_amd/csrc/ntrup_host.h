@@ -23,6 +23,8 @@ constexpr int kJobStreams = 4;    // concurrent branches of a mixed call
 // sample_short, r3 main pass, r3 retry/final passes, group prefix + reciprocal,
 // group back-substitution + encoding
 constexpr int kStages = 5;
+// tree form: node rows past the last key of a ragged last group (G <= 256)
+constexpr int kTreeRows = 256;
 
 inline int param_slot(int p) {
     for (int i = 0; i < 4; i++)
@@ -46,6 +48,7 @@ struct Ws {
                        // (batched R/3: the group products, int8)
     int* flags;        // persistent form: dependency counters
     int8_t* r3rows;    // batched R/3: prefix products [n][p]
+    int16_t* trow;     // tree form: the nodes' t values [n + kTreeRows][p] (bscr holds their b)
     uint32_t* pgbits;  // batched R/3: group products' bitsliced words [WN][2][groups]
     uint32_t* pinv;    // batched R/3: their reciprocals [WN][2][groups]
 };
@@ -55,9 +58,10 @@ inline size_t flag_ints(size_t n) { return 4 * n + 64; }
 
 inline size_t ws_bytes(int p, size_t n) {
     const size_t wn = (size_t)ceil_div(p, 32);
-    return align256(n * p) + 2 * align256(wn * 2 * n * 4) + 2 * align256(n * p * 2) + align256(n) +
-           2 * align256(n * 4) + align256(kCounterInts * 4) + align256(n * p * 2) + align256(flag_ints(n) * 4) +
-           align256(n * p) + 2 * align256(wn * 2 * n * 4);
+    return align256(n * p) + 2 * align256(wn * 2 * n * 4) + align256((n + kTreeRows) * p * 2) +
+           align256(n * p * 2) + align256(n) + 2 * align256(n * 4) + align256(kCounterInts * 4) +
+           align256(n * p * 2) + align256(flag_ints(n) * 4) + align256(n * p) + 2 * align256(wn * 2 * n * 4) +
+           align256((n + kTreeRows) * p * 2);
 }
 
 inline Ws carve(void* base, int p, size_t n) {
@@ -67,7 +71,7 @@ inline Ws carve(void* base, int p, size_t n) {
     w.f_rows = (int8_t*)c;       c += align256(n * p);
     w.gbits = (uint32_t*)c;      c += align256(wn * 2 * n * 4);
     w.ibits = (uint32_t*)c;      c += align256(wn * 2 * n * 4);
-    w.bscr = (int16_t*)c;        c += align256(n * p * 2);
+    w.bscr = (int16_t*)c;        c += align256((n + kTreeRows) * p * 2);
     w.tinv = (int16_t*)c;        c += align256(n * p * 2);   // at most n groups
     w.attempts = (uint8_t*)c;    c += align256(n);
     w.lists[0] = (int*)c;        c += align256(n * 4);
@@ -77,7 +81,8 @@ inline Ws carve(void* base, int p, size_t n) {
     w.flags = (int*)c;           c += align256(flag_ints(n) * 4);
     w.r3rows = (int8_t*)c;       c += align256(n * p);
     w.pgbits = (uint32_t*)c;     c += align256(wn * 2 * n * 4);
-    w.pinv = (uint32_t*)c;
+    w.pinv = (uint32_t*)c;       c += align256(wn * 2 * n * 4);
+    w.trow = (int16_t*)c;
     return w;
 }
 

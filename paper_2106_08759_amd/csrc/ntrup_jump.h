@@ -1,4 +1,4 @@
-// Reciprocal in R/q by jump divsteps on one wave: the recursive form of the
+// Reciprocal in R/q (or R/3) by jump divsteps on one wave: the recursive form of the
 // constant-time divsteps (Bernstein and Yang; the gcd that Section 3.1 uses,
 // whose jump-div-step variant Appendix D times for n = 1), one level deep.
 //
@@ -26,7 +26,11 @@
 // x^p - x - 1 reversed, g the input reversed, v = 0, r = 1, delta = 1; the
 // input is a unit iff delta = 0 at the end, and 1/a has coefficient i equal
 // to v_{p-i} / f0.  tests/test_jump_divsteps.py models this schedule on the
-// CPU against the oracle.
+// CPU against the oracle.  The same code inverts in R/3 (modulus 3, one
+// int8 limb per coefficient, one MFMA per pair of operands): the group
+// products of the batched R/3 stage.  (With modulus 3 every value the
+// reduction helpers see stays below 2^8 in magnitude, so their 24-bit
+// quotient bound holds there too.)
 //
 // Layouts (LDS, one wave): each polynomial X in {f, g, v, r} is kept as two
 // zero-padded byte arrays, HL[kJumpHOff + m] = lo(X_m), HH = hi(X_m) for
@@ -53,7 +57,6 @@ constexpr int kJumpHOff = 48;  // Hankel blocks j >= -3 read zeros below X_0
 
 template <int P>
 struct JumpShape {
-    static constexpr int Q = Param<P>::q;
     static constexpr int NT = ceil_div(P + 1 + kJumpN, 256);   // output tiles: f' needs outputs up to p + n
     static constexpr int HLEN = kJumpHOff + 256 * NT;
     static constexpr int NJUMP = ceil_div(2 * P - 1, kJumpN);
@@ -90,8 +93,8 @@ __device__ __forceinline__ void jump_put4(uint8_t* HL, uint8_t* HH, int m, const
 
 // Accumulates the product of U entry `ue` (Toeplitz limbs TL, TH) with X
 // (Hankel limbs XL, XH) into the per-tile accumulators (lo lo, lo hi + hi lo,
-// hi hi).
-template <int P>
+// hi hi); with one limb (LIMBS = 1, residues mod 3) only lo lo.
+template <int P, int LIMBS>
 __device__ __forceinline__ void jump_mac(const uint8_t* TL, const uint8_t* TH, const uint8_t* XL,
                                          const uint8_t* XH, mf_v4i (&a0)[JumpShape<P>::NT],
                                          mf_v4i (&a1)[JumpShape<P>::NT], mf_v4i (&a2)[JumpShape<P>::NT]) {
@@ -121,22 +124,26 @@ __device__ __forceinline__ void jump_mac(const uint8_t* TL, const uint8_t* TH, c
         const mf_v4i bl = *(const mf_v4i*)(xl + 256 * t);
         const mf_v4i bh = *(const mf_v4i*)(xh + 256 * t);
         a0[t] = __builtin_amdgcn_mfma_i32_16x16x64_i8(tl, bl, a0[t], 0, 0, 0);
-        a1[t] = __builtin_amdgcn_mfma_i32_16x16x64_i8(tl, bh, a1[t], 0, 0, 0);
-        a1[t] = __builtin_amdgcn_mfma_i32_16x16x64_i8(th, bl, a1[t], 0, 0, 0);
-        a2[t] = __builtin_amdgcn_mfma_i32_16x16x64_i8(th, bh, a2[t], 0, 0, 0);
+        if (LIMBS == 2) {
+            a1[t] = __builtin_amdgcn_mfma_i32_16x16x64_i8(tl, bh, a1[t], 0, 0, 0);
+            a1[t] = __builtin_amdgcn_mfma_i32_16x16x64_i8(th, bl, a1[t], 0, 0, 0);
+            a2[t] = __builtin_amdgcn_mfma_i32_16x16x64_i8(th, bh, a2[t], 0, 0, 0);
+        }
     }
 }
 
-// One output polynomial of a jump: Y = (U[ia] X0 + U[ib] X1), shifted down by
-// `shift` coefficients (n for f and g, 0 for v and r); its coefficients
-// 0..p go to the Hankel limbs YL, YH (the rest stay zero), coefficients below
-// 64 also to `low` when given, and all of them to `vout` (int16) when given.
-template <int P>
+// One output polynomial of a jump: Y = (U[ia] X0 + U[ib] X1) mod M, shifted
+// down by `shift` coefficients (n for f and g, 0 for v and r); its
+// coefficients 0..p go to the Hankel limbs YL, YH (the rest stay zero),
+// coefficients below 64 also to `low` when given, and all of them to `vout`
+// (int16) when given.
+template <int P, int M>
 __device__ __forceinline__ void jump_output(JumpLds<P>& L, int ia, int ib, const uint8_t* X0L, const uint8_t* X0H,
                                             const uint8_t* X1L, const uint8_t* X1H, int shift, uint8_t* YL,
                                             uint8_t* YH, int32_t* low, int16_t* vout) {
     using S = JumpShape<P>;
-    constexpr int Q = S::Q;
+    constexpr int Q = M;
+    constexpr int LIMBS = M == 3 ? 1 : 2;
     // 2^14 mod q, centered
     constexpr int32_t C14 = ((16384 % Q) > Q / 2) ? (16384 % Q) - Q : (16384 % Q);
     mf_v4i a0[S::NT], a1[S::NT], a2[S::NT];
@@ -146,8 +153,8 @@ __device__ __forceinline__ void jump_output(JumpLds<P>& L, int ia, int ib, const
         a1[t] = mf_v4i{0, 0, 0, 0};
         a2[t] = mf_v4i{0, 0, 0, 0};
     }
-    jump_mac<P>(L.T[ia][0], L.T[ia][1], X0L, X0H, a0, a1, a2);
-    jump_mac<P>(L.T[ib][0], L.T[ib][1], X1L, X1H, a0, a1, a2);
+    jump_mac<P, LIMBS>(L.T[ia][0], L.T[ia][1], X0L, X0H, a0, a1, a2);
+    jump_mac<P, LIMBS>(L.T[ib][0], L.T[ib][1], X1L, X1H, a0, a1, a2);
     const int lane = lane_id();
     const int rc = lane & 15, gq = lane >> 4;
 #pragma unroll
@@ -157,7 +164,7 @@ __device__ __forceinline__ void jump_output(JumpLds<P>& L, int ia, int ib, const
 #pragma unroll
         for (int e = 0; e < 4; e++) {
             // |a0| + 128 |a1| + |C14| |a2| < 2^31: at most 98 limb products per output
-            const int32_t s = a0[t][e] + 128 * a1[t][e] + C14 * a2[t][e];
+            const int32_t s = LIMBS == 1 ? a0[t][e] : a0[t][e] + 128 * a1[t][e] + C14 * a2[t][e];
             y[e] = (m + e <= P) ? freeze<Q>(s) : 0;
         }
         if (m >= 0 && m <= P) {
@@ -174,13 +181,14 @@ __device__ __forceinline__ void jump_output(JumpLds<P>& L, int ia, int ib, const
     }
 }
 
-// Reciprocal of the centered element Bin (LDS, p int16 entries) in R/q by
-// jump divsteps.  Writes the centered reciprocal to OUT (LDS, may alias Bin).
+// Reciprocal of the centered element Bin (LDS, p entries) in R/M, M = q
+// (R/q, residues as two 7-bit limbs) or M = 3 (R/3, one limb), by jump
+// divsteps.  Writes the centered reciprocal to OUT (LDS, may alias Bin).
 // Returns 1 iff Bin is a unit.  One wave; L is its own.
-template <int P>
-__device__ int recip_jump_wave(const int16_t* Bin, int16_t* OUT, JumpLds<P>& L) {
+template <int P, int M = Param<P>::q, typename T = int16_t>
+__device__ int recip_jump_wave(const T* Bin, T* OUT, JumpLds<P>& L) {
     using S = JumpShape<P>;
-    constexpr int Q = S::Q;
+    constexpr int Q = M;
     const int lane = lane_id();
     // both Hankel sets and the Toeplitz arrays start zeroed
     {
@@ -260,14 +268,14 @@ __device__ int recip_jump_wave(const int16_t* Bin, int16_t* OUT, JumpLds<P>& L) 
         uint8_t(*Hc)[2][S::HLEN] = L.H[cur];
         uint8_t(*Hn)[2][S::HLEN] = L.H[nxt];
         if (jmp + 1 < S::NJUMP) {
-            jump_output<P>(L, 0, 1, Hc[0][0], Hc[0][1], Hc[1][0], Hc[1][1], kJumpN, Hn[0][0], Hn[0][1], L.low[0],
+            jump_output<P, M>(L, 0, 1, Hc[0][0], Hc[0][1], Hc[1][0], Hc[1][1], kJumpN, Hn[0][0], Hn[0][1], L.low[0],
                            nullptr);
-            jump_output<P>(L, 2, 3, Hc[0][0], Hc[0][1], Hc[1][0], Hc[1][1], kJumpN, Hn[1][0], Hn[1][1], L.low[1],
+            jump_output<P, M>(L, 2, 3, Hc[0][0], Hc[0][1], Hc[1][0], Hc[1][1], kJumpN, Hn[1][0], Hn[1][1], L.low[1],
                            nullptr);
-            jump_output<P>(L, 0, 1, Hc[2][0], Hc[2][1], Hc[3][0], Hc[3][1], 0, Hn[2][0], Hn[2][1], nullptr, nullptr);
-            jump_output<P>(L, 2, 3, Hc[2][0], Hc[2][1], Hc[3][0], Hc[3][1], 0, Hn[3][0], Hn[3][1], nullptr, nullptr);
+            jump_output<P, M>(L, 0, 1, Hc[2][0], Hc[2][1], Hc[3][0], Hc[3][1], 0, Hn[2][0], Hn[2][1], nullptr, nullptr);
+            jump_output<P, M>(L, 2, 3, Hc[2][0], Hc[2][1], Hc[3][0], Hc[3][1], 0, Hn[3][0], Hn[3][1], nullptr, nullptr);
         } else {
-            jump_output<P>(L, 0, 1, Hc[2][0], Hc[2][1], Hc[3][0], Hc[3][1], 0, Hn[2][0], Hn[2][1], nullptr, L.v);
+            jump_output<P, M>(L, 0, 1, Hc[2][0], Hc[2][1], Hc[3][0], Hc[3][1], 0, Hn[2][0], Hn[2][1], nullptr, L.v);
             fend = __builtin_amdgcn_readfirstlane(F);
         }
         wave_sync();
@@ -290,7 +298,7 @@ __device__ int recip_jump_wave(const int16_t* Bin, int16_t* OUT, JumpLds<P>& L) 
 #pragma unroll
     for (int k = 0; k < ceil_div(P, 64); k++) {
         const int i = lane + 64 * k;
-        if (i < P) OUT[i] = (int16_t)res[k];
+        if (i < P) OUT[i] = (T)res[k];
     }
     wave_sync();
     return delta == 0;

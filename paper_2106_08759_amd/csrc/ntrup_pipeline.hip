@@ -9,12 +9,15 @@
 #include "ntrup_kernels.h"
 #include "ntrup_keygen.h"
 #include "ntrup_r3batch.h"
+#include "ntrup_tree.h"
 
 #ifndef NTRUP_P
 #error "compile with -DNTRUP_P=653, 761, 857 or 1277"
 #endif
 
 namespace ntrup {
+
+static_assert(kTreeRows >= kTreeMaxG, "node rows of a ragged last tree group fit the workspace");
 
 namespace {
 
@@ -119,8 +122,18 @@ int enqueue_keygen(ntrup_ctx* ctx, const ntrup_config& cfg, const Seed& seed, ui
         NTRUP_HIP(ctx, hipEventRecord(ctx->side_fork, st));
         NTRUP_HIP(ctx, hipStreamWaitEvent(ss, ctx->side_fork, 0));
     }
-    if (mfma) {
-        launch_prefix<P>(W, cfg.recip_jump != 0, dim3(grid_for(n, (size_t)cfg.group_size * W)), sp, g, w.tinv);
+    const bool tree = mfma && cfg.group_form == 1;
+    if (tree) {
+        // one workgroup per group: b and t of the tree's nodes in bscr and
+        // trow, c_i = 1/(3 f_i) to the key rows of tinv
+        if (cfg.recip_jump & 1)
+            hipLaunchKernelGGL((keygen_tree_kernel<P, true>), dim3(grid_for(n, cfg.group_size)), dim3(64 * kTreeWaves),
+                               0, sp, g, w.trow, w.tinv);
+        else
+            hipLaunchKernelGGL((keygen_tree_kernel<P, false>), dim3(grid_for(n, cfg.group_size)),
+                               dim3(64 * kTreeWaves), 0, sp, g, w.trow, w.tinv);
+    } else if (mfma) {
+        launch_prefix<P>(W, (cfg.recip_jump & 1) != 0, dim3(grid_for(n, (size_t)cfg.group_size * W)), sp, g, w.tinv);
         // with a side stream, the back-substitution (which needs only f) runs
         // there too, and only h = g c and the encoding follow the R/3 stage
         if (side)
@@ -186,7 +199,14 @@ int enqueue_keygen(ntrup_ctx* ctx, const ntrup_config& cfg, const Seed& seed, ui
         gi.ibits = w.pinv;
         gi.err = w.counters + 32;
         gi.g_in = (const int8_t*)w.qrow;
-        launch_r3<P>(8, ngroups, gi, sr);   // latency-bound: few products, most lanes per product
+        // the group products' reciprocals: latency-bound (few products), by
+        // jump divsteps on the matrix cores or the bitsliced divsteps at the
+        // most lanes per product
+        if (cfg.recip_jump & 2)
+            hipLaunchKernelGGL((r3_recip_jump_kernel<P>), dim3(ngroups), dim3(64), 0, sr, (int)ngroups,
+                               (const int8_t*)w.qrow, w.pinv, (uint8_t*)w.lists[1]);
+        else
+            launch_r3<P>(8, ngroups, gi, sr);
         hipLaunchKernelGGL((r3b_back_kernel<P>), dim3(ngroups), dim3(64), 0, sr, b);
         mark(3, sr);
         a.list_in = w.lists[0];
@@ -211,7 +231,13 @@ int enqueue_keygen(ntrup_ctx* ctx, const ntrup_config& cfg, const Seed& seed, ui
     mark(4, sr);
     if (r3_first) NTRUP_HIP(ctx, hipEventRecord(ctx->side_join, ss));
     if (side) NTRUP_HIP(ctx, hipStreamWaitEvent(st, ctx->side_join, 0));
-    if (mfma && side) {
+    if (tree) {
+        // h = g c with c from the tree's key rows
+        GroupArgs gh = g;
+        gh.bscr = w.tinv;
+        const unsigned per = grid_for(n, 8);
+        hipLaunchKernelGGL((keygen_h_kernel<P>), dim3(8 * per), dim3(64), 0, st, gh, (int)per);
+    } else if (mfma && side) {
         const unsigned per = grid_for(n, 8);
         hipLaunchKernelGGL((keygen_h_kernel<P>), dim3(8 * per), dim3(64), 0, st, g, (int)per);
     } else if (mfma) {

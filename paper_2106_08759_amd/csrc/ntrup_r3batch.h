@@ -22,6 +22,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "ntrup_jump.h"
 #include "ntrup_keygen.h"
 #include "ntrup_mfma.h"
 #include "ntrup_r3_factors.h"
@@ -396,6 +397,40 @@ __global__ __launch_bounds__(64) void r3b_back_kernel(R3bArgs<P> a) {
             }
         }
     }
+}
+
+// Reciprocals in R/3 of n rows of int8 coefficients in {-1, 0, 1} (the group
+// products) by jump divsteps over F_3 (recip_jump_wave with M = 3: one int8
+// limb per coefficient), one wave per row.  Writes the reciprocal's bitsliced
+// words to ibits ([WN][2][n]: plane 0 the nonzero mask, plane 1 the mask of
+// -1), two words per ballot over 64 coefficients, and ok[i] = 1 iff row i is
+// a unit (0 otherwise; its words are then meaningless).
+template <int P>
+__global__ __launch_bounds__(64) void r3_recip_jump_kernel(int n, const int8_t* rows, uint32_t* ibits, uint8_t* ok) {
+    constexpr int WN = ceil_div(P, 32);
+    __shared__ JumpLds<P> JL;
+    __shared__ int8_t X[round_up(P, 64)];
+    const int e = blockIdx.x;
+    if (e >= n) return;
+    const int lane = lane_id();
+    for (int i = lane; i < P; i += 64) X[i] = rows[(size_t)e * P + i];
+    wave_sync();
+    const int unit = recip_jump_wave<P, 3, int8_t>(X, X, JL);
+    for (int base = 0; base < P; base += 64) {
+        const int i = base + lane;
+        const int c = (i < P) ? (int)X[i] : 0;
+        const uint64_t nz = __ballot(c != 0), neg = __ballot(c < 0);
+        if (lane == 0) {
+            const int k = base / 32;
+            ibits[(size_t)(2 * k) * n + e] = (uint32_t)nz;
+            ibits[(size_t)(2 * k + 1) * n + e] = (uint32_t)neg;
+            if (k + 1 < WN) {
+                ibits[(size_t)(2 * k + 2) * n + e] = (uint32_t)(nz >> 32);
+                ibits[(size_t)(2 * k + 3) * n + e] = (uint32_t)(neg >> 32);
+            }
+        }
+    }
+    if (lane == 0) ok[e] = unit ? (uint8_t)1 : (uint8_t)0;
 }
 
 // c = a b in R/3 (int8 rows, centered), for the kernel tests.

@@ -46,3 +46,61 @@ def test_group_ops_split_moves_work_only():
         b = bench.group_kernel_ops(p, n, G, W, split=True)
         assert a["group_prefix"] + a["group_back"] == b["group_prefix"] + b["group_back"]
         assert b["group_back"] == 2 * 2 * n * p * p      # h_i: 2 limb pairs, 2 ops per multiply-add
+
+
+def _mf_pairs(p):
+    """(tile, K-step) pairs of one matrix-core product in R/q (ntrup_mfma.h)."""
+    nd = (p + 14) // 16 + 1
+    nks = cdiv(nd, 4)
+    nt = cdiv(cdiv(p, 16), 16)
+    return nt * nks
+
+
+def _jump_mfmas(p):
+    """MFMAs of one jump-divstep reciprocal in R/q: eight products of two limb
+    pairs per full jump and output tile, two products for the last one."""
+    ntj = cdiv(p + 1 + 48, 256)
+    nj = cdiv(2 * p - 1, 48)
+    return (nj - 1) * 4 * 2 * ntj * 4 + 2 * ntj * 4
+
+
+def expected_group_mfmas(p, n, G, W, jump):
+    """MFMA instructions per launch of the prefix, back-substitution and h
+    kernels of the eager split path, counting 3g - 3 R/q products per group of
+    g keys (Section 2.2's batchInv): g - 1 prefix products (small x big, two
+    limb MFMAs per pair), g - 1 back products c_i (big x big, four) and g - 1
+    t updates (small x big, two); 3 (W - 1) big products per W groups sharing
+    one reciprocal; one small x big product h_i per key."""
+    pairs = _mf_pairs(p)
+    groups = [min(G, n - s) for s in range(0, n, G)]
+    blocks = cdiv(len(groups), W)
+    prefix = sum((g - 1) * 2 * pairs for g in groups) + blocks * (3 * (W - 1) * 4 * pairs
+                                                                   + (_jump_mfmas(p) if jump & 1 else 0))
+    back = sum((g - 1) * 6 * pairs for g in groups)
+    return prefix, back, n * 2 * pairs
+
+
+def test_batchinv_products_per_group_from_counters():
+    """Section 2.2 / Section 1: batchInv of n elements takes 3n - 3
+    multiplications and one inversion (93 for n = 32).  The committed
+    hardware counters of the benchmark's group kernels (SQ_INSTS_MFMA per
+    launch, profiles/kernel_counters.json) equal exactly the MFMA count of
+    3G - 3 products per group (plus the shared reciprocals and h)."""
+    import json
+    facts = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_facts.json")))
+    bic = facts["batchinv_counts"]
+    assert bic["mults_per_n"] == "3n-3" and 3 * 32 - 3 == bic["n32_mults"]
+    path = os.path.join(os.path.dirname(__file__), "..", "profiles", "kernel_counters.json")
+    data = json.load(open(path))
+    cfg = data["config"]
+    p, n, G, W = cfg["p"], cfg["n_keys"], cfg["group_size"], cfg["inverse_share"]
+    prefix, back, h = expected_group_mfmas(p, n, G, W, cfg["recip_jump"])
+    k = data["kernels"]
+    assert k["keygen_prefix_kernel<%d,%d,%s>" % (p, W, "true" if cfg["recip_jump"] & 1 else "false")]["mfma_insts"] \
+        == prefix
+    assert k["keygen_cinv_kernel<%d>" % p]["mfma_insts"] == back
+    assert k["keygen_h_kernel<%d>" % p]["mfma_insts"] == h
+    # per group of G keys: (G-1) small + (G-1) (big + small) = 3G - 3 products
+    pairs = _mf_pairs(p)
+    per_group = ((G - 1) * 2 * pairs + (G - 1) * 6 * pairs) // (2 * pairs)   # in small-product units
+    assert per_group == 4 * (G - 1)   # 3G - 3 products, the G - 1 big ones at twice the MFMAs

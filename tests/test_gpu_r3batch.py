@@ -56,26 +56,32 @@ def run(ctx, p, first, n, **cfg):
         ctx.set_config(p, **base)
 
 
+@pytest.mark.parametrize("jump", [1, 3])
 @pytest.mark.parametrize("p", [653, 761, 857, 1277])
-def test_keys_bit_exact(ctx, p):
+def test_keys_bit_exact(ctx, p, jump):
+    """Group reciprocals in R/3 by bitsliced divsteps (recip_jump bit 1
+    clear) or by jump divsteps on the matrix cores (set)."""
     n = 200
     ref = oracle_pool.oracle_keys(wl.SEED, p, range(n))
     rpk, rsk = oracle_pool.pk_sk_arrays(ref, range(n))
     for G in (1, 7, 32, 64):
-        pk, sk = run(ctx, p, 0, n, r3_batch=1, group_size=G)
+        pk, sk = run(ctx, p, 0, n, r3_batch=1, group_size=G, recip_jump=jump)
         assert np.array_equal(pk, rpk) and np.array_equal(sk, rsk), (p, G)
 
 
+@pytest.mark.parametrize("jump", [1, 3])
 @pytest.mark.parametrize("p", [653, 1277])
-def test_fallback_path(ctx, p):
+def test_fallback_path(ctx, p, jump):
     """Screen off: about a quarter to a half of the groups of 8 hold a g that
-    is not a unit; they take the per-key divstep pass from their first draw."""
+    is not a unit; the group reciprocal (either form) reports the product as
+    no unit and those groups take the per-key divstep pass from their first
+    draw."""
     n = 300
     ref = oracle_pool.oracle_keys(wl.SEED, p, range(n))
     rpk, rsk = oracle_pool.pk_sk_arrays(ref, range(n))
     assert sum(ref[i][5] > 1 for i in range(n)) >= 5
     for G, spec in ((8, 4), (32, 1), (3, 8)):
-        pk, sk = run(ctx, p, 0, n, r3_batch=2, group_size=G, retry_parallel_attempts=spec)
+        pk, sk = run(ctx, p, 0, n, r3_batch=2, group_size=G, retry_parallel_attempts=spec, recip_jump=jump)
         assert np.array_equal(pk, rpk) and np.array_equal(sk, rsk), (p, G, spec)
 
 

@@ -130,6 +130,28 @@ def toy_elements(p, q, count, rng):
 
 
 @pytest.mark.parametrize("p", [653, 761, 857, 1277])
+def test_jump_in_r3_equals_oracle(p):
+    """The same schedule over F_3 (the batched R/3 stage's group reciprocals):
+    random elements of R/3, and for p = 761 the degree-19 factor of
+    x^761 - x - 1 mod 3 (Section 3.1.1), a non-unit."""
+    rng = np.random.default_rng(3 * p)
+    elems = [rng.integers(0, 3, size=p) for _ in range(4)]
+    for a in elems:
+        want = oracle.inv_mod(a, p, 3)
+        got = recip_jump(a, p, 3)
+        if want is None:
+            assert got is None
+        else:
+            assert np.array_equal(got, want)
+    if p == 761:
+        import ringmath as rm
+        fac = rm.gf_factor_of_degree(761, 19)
+        a = np.zeros(p, dtype=np.int64)
+        a[:len(fac)] = np.asarray(fac) % 3
+        assert oracle.inv_mod(a, p, 3) is None and recip_jump(a, p, 3) is None
+
+
+@pytest.mark.parametrize("p", [653, 761, 857, 1277])
 def test_jump_equals_oracle_reciprocal(p):
     """The jump schedule's reciprocal equals the oracle's extended-Euclid
     reciprocal, and the low n coefficients of U (f, g) vanish (the division
