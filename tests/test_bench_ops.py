@@ -57,11 +57,16 @@ def _mf_pairs(p):
 
 
 def _jump_mfmas(p):
-    """MFMAs of one jump-divstep reciprocal in R/q: eight products of two limb
-    pairs per full jump and output tile, two products for the last one."""
-    ntj = cdiv(p + 1 + 48, 256)
+    """MFMAs of one jump-divstep reciprocal in R/q: per full jump, four output
+    polynomials of two products each, four MFMAs (limb pairs) per output
+    tile of 256 coefficients; f' and g' (shifted down by 48) need the tiles
+    up to coefficient p + 48, v' and r' those up to p (the compiler drops the
+    MFMAs of a tile none of whose outputs is stored); the last jump computes
+    v' alone."""
+    nt_fg = cdiv(p + 1 + 48, 256)
+    nt_vr = cdiv(p + 1, 256)
     nj = cdiv(2 * p - 1, 48)
-    return (nj - 1) * 4 * 2 * ntj * 4 + 2 * ntj * 4
+    return (nj - 1) * (2 * 2 * nt_fg + 2 * 2 * nt_vr) * 4 + 2 * nt_vr * 4
 
 
 def expected_group_mfmas(p, n, G, W, jump):
