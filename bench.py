@@ -478,7 +478,7 @@ def main():
         dom = max(crit, key=lambda k: avg[k])
     achieved = ops[dom] / (avg[dom] / 1e3)
     jump = "true" if cfg["recip_jump"] & 1 else "false"
-    kernel_names = {"group_prefix": ("keygen_tree_kernel<%d,%s>" % (p, jump) if tree else
+    kernel_names = {"group_prefix": ("keygen_tree_{up,root,down}_kernel<%d> (root jump %s)" % (p, jump) if tree else
                                      "keygen_prefix_kernel<%d,%d,%s>" % (p, cfg["inverse_share"], jump)),
                     "group_back": ("keygen_h_kernel<%d>" if split or tree else "keygen_back_kernel<%d>") % p,
                     "r3_main": "r3_kernel<%d,%d>" % (p, cfg["lanes_per_key"]),
@@ -554,7 +554,8 @@ def main():
         # the same jobs as one launch of the persistent fused kernel
         saved = {q_: ctx.get_config(q_) for q_ in (653, 761, 857, 1277)}
         for q_ in saved:
-            ctx.set_config(q_, persistent=1, r3_batch=0, product_engine=1, lanes_per_key=2, group_size=32,
+            ctx.set_config(q_, persistent=1, r3_batch=0, group_form=0, product_engine=1, lanes_per_key=2,
+                           group_size=32,
                            inverse_share=2, use_graph=1)
         ctx.batch_keygen_mixed(wl.SEED, jobs, check=True)
         torch.cuda.synchronize()

@@ -126,12 +126,13 @@ int enqueue_keygen(ntrup_ctx* ctx, const ntrup_config& cfg, const Seed& seed, ui
     if (tree) {
         // one workgroup per group: b and t of the tree's nodes in bscr and
         // trow, c_i = 1/(3 f_i) to the key rows of tinv
+        const dim3 groups(grid_for(n, cfg.group_size));
+        hipLaunchKernelGGL((keygen_tree_up_kernel<P>), groups, dim3(64 * kTreeWaves), 0, sp, g, w.trow);
         if (cfg.recip_jump & 1)
-            hipLaunchKernelGGL((keygen_tree_kernel<P, true>), dim3(grid_for(n, cfg.group_size)), dim3(64 * kTreeWaves),
-                               0, sp, g, w.trow, w.tinv);
+            hipLaunchKernelGGL((keygen_tree_root_kernel<P, true>), groups, dim3(64), 0, sp, g, w.trow);
         else
-            hipLaunchKernelGGL((keygen_tree_kernel<P, false>), dim3(grid_for(n, cfg.group_size)),
-                               dim3(64 * kTreeWaves), 0, sp, g, w.trow, w.tinv);
+            hipLaunchKernelGGL((keygen_tree_root_kernel<P, false>), groups, dim3(64), 0, sp, g, w.trow);
+        hipLaunchKernelGGL((keygen_tree_down_kernel<P>), groups, dim3(64 * kTreeWaves), 0, sp, g, w.trow, w.tinv);
     } else if (mfma) {
         launch_prefix<P>(W, (cfg.recip_jump & 1) != 0, dim3(grid_for(n, (size_t)cfg.group_size * W)), sp, g, w.tinv);
         // with a side stream, the back-substitution (which needs only f) runs

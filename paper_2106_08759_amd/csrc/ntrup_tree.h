@@ -18,10 +18,11 @@
 // the last key of a ragged group are 1.
 //
 // Rows (global int16 [rows][p], rows kw0 + j of the group): b_j in `brow`,
-// t_j in `trow` (j in [1, G)), c_i in `crow` (the key rows).  Levels are
-// ordered by workgroup barriers; a wave owns the nodes j = first + w,
-// first + w + kTreeWaves, ... of a level, so that the two children of a
-// down-sweep node are written by the wave that read them.
+// t_j in `trow` (j in [1, G)), c_i in `crow` (the key rows).  Three kernels:
+// the up-sweep, the roots' reciprocals (one wave per group), the down-sweep.
+// Within a sweep, levels are ordered by workgroup barriers; a wave owns the
+// nodes j = first + w, first + w + kTreeWaves, ... of a level, so that the
+// two children of a down-sweep node are written by the wave that read them.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -36,6 +37,10 @@ namespace ntrup {
 
 constexpr int kTreeWaves = 8;     // waves per workgroup (one group of G keys)
 constexpr int kTreeMaxG = 256;    // G = 2^k, 2 <= G <= kTreeMaxG
+// Waves per SIMD the up- and down-sweep kernels are compiled for: four (two
+// 8-wave groups per CU, at most 128 VGPRs) where the operands fit with a few
+// spilled registers, two for p = 1277, whose wider operands would spill more.
+constexpr int tree_min_waves(int p) { return p < 1000 ? 4 : 2; }
 
 template <int P>
 struct TreeWaveLds {
@@ -46,19 +51,12 @@ struct TreeWaveLds {
     __attribute__((aligned(16))) uint8_t HH[S::HLEN];
 };
 
-// The root reciprocal's LDS (wave 0 alone, while the other waves wait at a
-// barrier, so it shares the space of the product operands).
+// The root reciprocal's LDS.
 template <int P, bool J>
 struct TreeRootLds {
     __attribute__((aligned(16))) int16_t R[RqShape<P>::JP];
     __attribute__((aligned(16))) int32_t STG[64 * RqShape<P>::RI];
     typename std::conditional<J, JumpLds<P>, char>::type JL;
-};
-
-template <int P, bool J>
-union TreeLds {
-    TreeWaveLds<P> w[kTreeWaves];
-    TreeRootLds<P, J> root;
 };
 
 // Reversed Toeplitz limb of a small operand s a_m (a an int8 row; scale 3
@@ -104,84 +102,154 @@ __device__ __forceinline__ void tree_hankel_small(const int8_t* a, int scale, ui
     }
 }
 
-// The tree for group blockIdx.x.  args: n, G, f_rows, err; brow = args.bscr.
-template <int P, bool J>
-__global__ __launch_bounds__(64 * kTreeWaves) void keygen_tree_kernel(GroupArgs args, int16_t* trow, int16_t* crow) {
-    __shared__ TreeLds<P, J> LDS;
-    const int wave = (int)(threadIdx.x >> 6);
+// Reversed Toeplitz limb of 3 f from the f bytes in registers (KgRegs
+// layout): TL[Z0 - m] = 3 f_m for m < p (bytes 0x00, 0x01, 0xFF -> 0x00,
+// 0x03, 0xFD, byte-reversed per word); the padding stays as it is.
+template <int P>
+__device__ __forceinline__ void tree_put_toeplitz_3f(const KgRegs<P>& r, uint8_t* TL) {
     const int lane = lane_id();
-    const int n = args.n, G = args.G;
-    const int kw0 = blockIdx.x * G;
-    const int gsz = min(G, n - kw0);
-    int16_t* brow = args.bscr + (size_t)kw0 * P;   // row j: b_j
-    int16_t* tr = trow + (size_t)kw0 * P;          // row j: t_j
-    const int8_t* f0 = args.f_rows + (size_t)kw0 * P;
-    TreeWaveLds<P>& L = LDS.w[wave];
-    // the operand a_i = 3 f_i of leaf G + i (nullptr: 1, past the last key)
-    auto leaf = [&](int node) -> const int8_t* {
-        const int i = node - G;
-        return i < gsz ? f0 + (size_t)i * P : nullptr;
-    };
+#pragma unroll
+    for (int u = 0; u < KgShape<P>::NU; u++) {
+        const int m0 = 4 * lane + 256 * u;
+        if (m0 < P) {
+            const uint32_t f3 = r.f[u] ^ ((r.f[u] & 0x01010101u) << 1);
+            *(uint32_t*)(TL + MfShape<P>::Z0 - m0 - 3) = __builtin_amdgcn_perm(0u, f3, 0x00010203u);
+        }
+    }
+}
 
-    // up-sweep, the leaves' parents first
-    for (int first = G / 2; first >= 1; first >>= 1) {
+// Shared set-up of the up- and down-sweep kernels: one workgroup of
+// kTreeWaves waves per group (blockIdx.x).  Operands go through registers
+// (one row load, then the limb arrays written from the registers, as in the
+// chain kernels); the limb arrays' padding is zeroed once.
+template <int P>
+struct TreeWave {
+    using S = MfShape<P>;
+    const GroupArgs& args;
+    TreeWaveLds<P>& L;
+    int G, kw0, gsz;
+    int16_t* brow;   // row j: b_j
+    int16_t* tr;     // row j: t_j
+    KgRegs<P> ra;
+    __device__ TreeWave(const GroupArgs& a, TreeWaveLds<P>& l, int16_t* trow)
+        : args(a), L(l), G(a.G), kw0((int)blockIdx.x * a.G), gsz(min(a.G, a.n - (int)blockIdx.x * a.G)),
+          brow(a.bscr + (size_t)blockIdx.x * a.G * P), tr(trow + (size_t)blockIdx.x * a.G * P) {
+        kg_zero<P>(L.TL, S::TLEN);
+        kg_zero<P>(L.TH, S::TLEN);
+        kg_zero<P>(L.HL, S::HLEN);
+        kg_zero<P>(L.HH, S::HLEN);
+        wave_sync();
+    }
+    // a_i = 3 f_i of leaf `node` as a Toeplitz (T) or Hankel (H) limb; the
+    // element 1 past the last key (whole arrays rewritten)
+    __device__ void leaf_t(int node) {
+        const int i = node - G;
+        if (i < gsz) {
+            kg_load_f<P>(args.f_rows, kw0 + i, ra);
+            tree_put_toeplitz_3f<P>(ra, L.TL);
+        } else {
+            tree_toeplitz_small<P>(nullptr, 1, L.TL);
+        }
+    }
+    __device__ void leaf_h(int node) {
+        const int i = node - G;
+        if (i < gsz) {
+            kg_load_f<P>(args.f_rows, kw0 + i, ra);
+            kg_put_3f<P>(ra, L.HL);
+        } else {
+            tree_hankel_small<P>(nullptr, 1, L.HL);
+        }
+    }
+    __device__ void big_t(const int16_t* rows, int j) {
+        kg_load_b<P>(rows, j, ra);
+        kg_put_toeplitz16<P>(ra.b, L.TL, L.TH);
+    }
+    __device__ void big_h(const int16_t* rows, int j) {
+        kg_load_b<P>(rows, j, ra);
+        put_folded16<P>(ra.b, L.HL, L.HH);
+    }
+};
+
+// Up-sweep of group blockIdx.x: b_j for every inner node j (rows of bscr),
+// the leaves' parents first.
+template <int P>
+__global__ __launch_bounds__(64 * kTreeWaves, tree_min_waves(P)) void keygen_tree_up_kernel(GroupArgs args, int16_t* trow) {
+    __shared__ TreeWaveLds<P> LW[kTreeWaves];
+    const int wave = (int)(threadIdx.x >> 6);
+    TreeWave<P> T(args, LW[wave], trow);
+    for (int first = T.G / 2; first >= 1; first >>= 1) {
         for (int j = first + wave; j < 2 * first; j += kTreeWaves) {
-            if (first == G / 2) {   // two leaves: small x small
-                tree_toeplitz_small<P>(leaf(2 * j), 3, L.TL);
-                tree_hankel_small<P>(leaf(2 * j + 1), 3, L.HL);
+            if (first == T.G / 2) {   // two leaves: small x small
+                T.leaf_t(2 * j);
+                T.leaf_h(2 * j + 1);
                 wave_sync();
-                mfma_mul<P, false, false>(L.TL, nullptr, L.HL, nullptr, nullptr, nullptr, nullptr,
-                                          brow + (size_t)j * P);
+                mfma_mul<P, false, false>(T.L.TL, nullptr, T.L.HL, nullptr, nullptr, nullptr, nullptr,
+                                          T.brow + (size_t)j * P);
             } else {
-                build_toeplitz<P>(brow + (size_t)(2 * j) * P, L.TL, L.TH);
-                build_hankel<P>(brow + (size_t)(2 * j + 1) * P, L.HL, L.HH);
+                T.big_t(T.brow, 2 * j);
+                T.big_h(T.brow, 2 * j + 1);
                 wave_sync();
-                mfma_mul<P, true>(L.TL, L.TH, L.HL, L.HH, nullptr, nullptr, nullptr, brow + (size_t)j * P);
+                mfma_mul<P, true>(T.L.TL, T.L.TH, T.L.HL, T.L.HH, nullptr, nullptr, nullptr, T.brow + (size_t)j * P);
             }
             wave_sync();
         }
         __threadfence_block();
         __syncthreads();
     }
-    // root: t_1 = 1/b_1 (b_1 != 0: a product of nonzero elements of a field)
-    if (wave == 0) {
-        TreeRootLds<P, J>& Rt = LDS.root;
-        for (int i = lane; i < P; i += 64) Rt.R[i] = brow[(size_t)P + i];
-        wave_sync();
-        int ok;
-        if constexpr (J) ok = recip_jump_wave<P>(Rt.R, Rt.R, Rt.JL);
-        else ok = recip_wave<P>(Rt.R, Rt.R, Rt.STG);
-        if (!ok && lane == 0) atomicOr(args.err, 2);
-        for (int i = lane; i < P; i += 64) tr[(size_t)P + i] = Rt.R[i];
-    }
-    __threadfence_block();
-    __syncthreads();
-    // down-sweep, from the root's children
+}
+
+// Root of every group: t_1 = 1/b_1 (b_1 != 0: a product of nonzero elements
+// of a field), one wave per group (a kernel of its own, so that the
+// reciprocal's registers do not limit the sweeps' occupancy).
+template <int P, bool J>
+__global__ __launch_bounds__(64) void keygen_tree_root_kernel(GroupArgs args, int16_t* trow) {
+    __shared__ TreeRootLds<P, J> Rt;
+    const int lane = lane_id();
+    const size_t row = (size_t)blockIdx.x * args.G + 1;
+    for (int i = lane; i < P; i += 64) Rt.R[i] = args.bscr[row * P + i];
+    wave_sync();
+    int ok;
+    if constexpr (J) ok = recip_jump_wave<P>(Rt.R, Rt.R, Rt.JL);
+    else ok = recip_wave<P>(Rt.R, Rt.R, Rt.STG);
+    if (!ok && lane == 0) atomicOr(args.err, 2);
+    for (int i = lane; i < P; i += 64) trow[row * P + i] = Rt.R[i];
+}
+
+// Down-sweep of group blockIdx.x from the root's children: t_j of the inner
+// nodes (rows of trow), c_i = 1/(3 f_i) of the keys (rows of crow).
+template <int P>
+__global__ __launch_bounds__(64 * kTreeWaves, tree_min_waves(P)) void keygen_tree_down_kernel(GroupArgs args, int16_t* trow,
+                                                                           int16_t* crow) {
+    __shared__ TreeWaveLds<P> LW[kTreeWaves];
+    const int wave = (int)(threadIdx.x >> 6);
+    TreeWave<P> T(args, LW[wave], trow);
+    const int G = T.G, kw0 = T.kw0, gsz = T.gsz;
     for (int first = 1; first < G; first <<= 1) {
         for (int j = first + wave; j < 2 * first; j += kTreeWaves) {
-            build_toeplitz<P>(tr + (size_t)j * P, L.TL, L.TH);
+            T.big_t(T.tr, j);
             if (2 * first == G) {   // children are leaves: c_i = t_j a_sibling
                 const int i0 = 2 * j - G, i1 = i0 + 1;
-                tree_hankel_small<P>(leaf(2 * j + 1), 3, L.HL);
+                T.leaf_h(2 * j + 1);
                 wave_sync();
-                mfma_mul<P, false>(L.TL, L.TH, L.HL, nullptr, nullptr, nullptr, nullptr,
+                mfma_mul<P, false>(T.L.TL, T.L.TH, T.L.HL, nullptr, nullptr, nullptr, nullptr,
                                    i0 < gsz ? crow + (size_t)(kw0 + i0) * P : nullptr);
                 wave_sync();
                 if (i1 < gsz) {
-                    tree_hankel_small<P>(leaf(2 * j), 3, L.HL);
+                    T.leaf_h(2 * j);
                     wave_sync();
-                    mfma_mul<P, false>(L.TL, L.TH, L.HL, nullptr, nullptr, nullptr, nullptr,
+                    mfma_mul<P, false>(T.L.TL, T.L.TH, T.L.HL, nullptr, nullptr, nullptr, nullptr,
                                        crow + (size_t)(kw0 + i1) * P);
                 }
             } else {
-                build_hankel<P>(brow + (size_t)(2 * j + 1) * P, L.HL, L.HH);
+                T.big_h(T.brow, 2 * j + 1);
                 wave_sync();
-                mfma_mul<P, true>(L.TL, L.TH, L.HL, L.HH, nullptr, nullptr, nullptr, tr + (size_t)(2 * j) * P);
+                mfma_mul<P, true>(T.L.TL, T.L.TH, T.L.HL, T.L.HH, nullptr, nullptr, nullptr,
+                                  T.tr + (size_t)(2 * j) * P);
                 wave_sync();
-                build_hankel<P>(brow + (size_t)(2 * j) * P, L.HL, L.HH);
+                T.big_h(T.brow, 2 * j);
                 wave_sync();
-                mfma_mul<P, true>(L.TL, L.TH, L.HL, L.HH, nullptr, nullptr, nullptr,
-                                  tr + (size_t)(2 * j + 1) * P);
+                mfma_mul<P, true>(T.L.TL, T.L.TH, T.L.HL, T.L.HH, nullptr, nullptr, nullptr,
+                                  T.tr + (size_t)(2 * j + 1) * P);
             }
             wave_sync();
         }
