@@ -34,12 +34,14 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# 256 CUs x 4 SIMDs x 16 lanes per clock x 2.4 GHz: a wave64 int32 VALU
-# instruction occupies its SIMD for 4 clocks.  (The published 157.3 TFLOP/s
-# fp32 vector peak is this rate x 2 flops per FMA x 2 for packed fp32; int32
-# has neither.)  Measured issue rates stay at or below it (calibration in
-# profiles/valu_issue_rate.md).
-VALU_PEAK = 256 * 4 * 16 * 2.4e9   # int32 lane-ops per second = 39.3 T
+# 256 CUs x 4 SIMDs x 32 lanes per clock x 2.4 GHz = 78.6 T int32 lane-ops
+# per second: the fp32 vector rate (157.3 TFLOP/s) at one operation per lane
+# instead of two flops per FMA.  Simple int32 operations (add, logic,
+# bitop3) measure up to 23.4 lanes per clock per SIMD by SQ_INSTS_VALU, above
+# the 16 of a four-clock wave64 issue, so 16 lanes is no ceiling; funnel
+# shifts and 24-bit multiply-adds run at half rate (<= 15 measured).  The
+# calibration table is in profiles/valu_issue_rate.md.
+VALU_PEAK = 256 * 4 * 32 * 2.4e9   # int32 lane-ops per second = 78.6 T
 I8_MFMA_PEAK = 5.0e15              # dense int8 matrix-core ops per second (2 per multiply-add)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "kernel_counters.json")
 
