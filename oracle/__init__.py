@@ -3,8 +3,8 @@
 Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 ``bench.py`` may import this package.  The GPU library never imports, links or
 calls it; the two share no code.  See ``ntrup_oracle.c`` for what is computed
-(OpenSSLNTRU paper, Section 3.1 KeyGen, on the rings of Section 2.1) and the
-sampling/encoding conventions.
+(OpenSSLNTRU paper, Section 3.1 KeyGen, on the rings of Section 2.1), the
+sampling/encoding conventions and the encapsulation / decapsulation core.
 
 Every function here is pinned by ``tests/test_oracle_*.py`` against things the
 paper and mathematics fix (brute force on toy rings, library routines, closed
@@ -83,6 +83,15 @@ def lib() -> ctypes.CDLL:
                                           ctypes.c_long,
                                           ctypes.POINTER(ctypes.c_uint64)]
         L.oracle_keygen_range.restype = ctypes.c_long
+        L.oracle_sample_short_stream.argtypes = [u8p, ctypes.c_uint64, ctypes.c_int,
+                                                 ctypes.c_int, ctypes.c_int, i8p]
+        L.oracle_encrypt.argtypes = [i16p, i8p, ctypes.c_int, ctypes.c_int, i16p]
+        L.oracle_decrypt.argtypes = [i16p, i8p, i8p, ctypes.c_int, ctypes.c_int,
+                                     ctypes.c_int, i8p]
+        L.oracle_encap.argtypes = [u8p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                   ctypes.c_uint64, i16p, i16p, i8p]
+        L.oracle_decap.argtypes = [i16p, i8p, i8p, i16p, ctypes.c_int, ctypes.c_int,
+                                   ctypes.c_int, i8p]
         _lib = L
     return _lib
 
@@ -124,10 +133,10 @@ def sample_small(seed, index: int, p: int, attempt: int) -> np.ndarray:
     return g
 
 
-def sample_short(seed, index: int, p: int, w: int) -> np.ndarray:
+def sample_short(seed, index: int, p: int, w: int, stream: int = 0) -> np.ndarray:
     f = np.zeros(p, dtype=np.int8)
-    rc = lib().oracle_sample_short(_ptr(_seed(seed), ctypes.c_uint8), index, p, w,
-                                   _ptr(f, ctypes.c_int8))
+    rc = lib().oracle_sample_short_stream(_ptr(_seed(seed), ctypes.c_uint8), index, p, w,
+                                          stream, _ptr(f, ctypes.c_int8))
     assert rc == 0
     return f
 
@@ -205,3 +214,66 @@ def keygen_range(seed, p: int, index0: int, n: int) -> int:
     if done != n:
         raise RuntimeError("oracle_keygen_range failed: %d" % done)
     return cs.value
+
+
+# Encapsulation / decapsulation core (see ntrup_oracle.c: Streamlined NTRU
+# Prime's published encryption, restated; the session-key hashes are not
+# computed).  r of key `index` comes from this stream of the Short sampler.
+ENCAP_STREAM = 0x8000
+
+
+def encrypt(h, r, p: int) -> np.ndarray:
+    """c = Round(h r) in R/q, centered (every c_i a multiple of 3)."""
+    _, q, _ = PARAMS[p]
+    h = np.ascontiguousarray(h, dtype=np.int16)
+    r = np.ascontiguousarray(r, dtype=np.int8)
+    c = np.zeros(p, dtype=np.int16)
+    rc = lib().oracle_encrypt(_ptr(h, ctypes.c_int16), _ptr(r, ctypes.c_int8), p, q,
+                              _ptr(c, ctypes.c_int16))
+    assert rc == 0
+    return c
+
+
+def decrypt(c, f, ginv, p: int):
+    """(r', weight_ok): r' = (3 f c mod q, mod 3) (1/g) in R/3, replaced by
+    (1,..,1,0,..,0) when its weight is not w."""
+    _, q, w = PARAMS[p]
+    c = np.ascontiguousarray(c, dtype=np.int16)
+    f = np.ascontiguousarray(f, dtype=np.int8)
+    gi = np.ascontiguousarray(ginv, dtype=np.int8)
+    r = np.zeros(p, dtype=np.int8)
+    rc = lib().oracle_decrypt(_ptr(c, ctypes.c_int16), _ptr(f, ctypes.c_int8),
+                              _ptr(gi, ctypes.c_int8), p, q, w, _ptr(r, ctypes.c_int8))
+    assert rc in (0, 1)
+    return r, bool(rc)
+
+
+def encap(seed, p: int, index: int, h):
+    """(c, r) of the encapsulation core for key `index` and public key h."""
+    _, q, w = PARAMS[p]
+    h = np.ascontiguousarray(h, dtype=np.int16)
+    c = np.zeros(p, dtype=np.int16)
+    r = np.zeros(p, dtype=np.int8)
+    rc = lib().oracle_encap(_ptr(_seed(seed), ctypes.c_uint8), p, q, w, index,
+                            _ptr(h, ctypes.c_int16), _ptr(c, ctypes.c_int16),
+                            _ptr(r, ctypes.c_int8))
+    assert rc == 0
+    return c, r
+
+
+def decap(c, f, ginv, p: int, h=None):
+    """(r', ok) of the decapsulation core; with h, ok means encrypt(r', h) = c,
+    without, that r' had weight w."""
+    _, q, w = PARAMS[p]
+    c = np.ascontiguousarray(c, dtype=np.int16)
+    f = np.ascontiguousarray(f, dtype=np.int8)
+    gi = np.ascontiguousarray(ginv, dtype=np.int8)
+    r = np.zeros(p, dtype=np.int8)
+    hp = None
+    if h is not None:
+        h = np.ascontiguousarray(h, dtype=np.int16)
+        hp = _ptr(h, ctypes.c_int16)
+    rc = lib().oracle_decap(_ptr(c, ctypes.c_int16), _ptr(f, ctypes.c_int8),
+                            _ptr(gi, ctypes.c_int8), hp, p, q, w, _ptr(r, ctypes.c_int8))
+    assert rc in (0, 1)
+    return r, bool(rc)

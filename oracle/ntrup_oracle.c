@@ -42,6 +42,9 @@
  *   - sk: f then 1/g, each coefficient c as c+1 in 2 bits, 4 per byte, LSB
  *     first, ceil(p/4) bytes each.
  *
+ * Encapsulation and decapsulation (the KEM's other two algorithms, Section 1)
+ * are computed as their arithmetic core only; see the section at the end.
+ *
  * Every function works for any odd prime modulus m and any p >= 2, so the
  * same code is checked by brute force on toy rings.
  */
@@ -153,14 +156,15 @@ static int cmp_u32(const void *a, const void *b)
     return (x > y) - (x < y);
 }
 
-/* f in Short: exactly w coefficients in {-1,1}, the rest 0. */
-int oracle_sample_short(const uint8_t seed[32], uint64_t index, int p, int w,
-                        int8_t *f)
+/* An element of Short from stream `stream`: exactly w coefficients in
+   {-1,1}, the rest 0. */
+int oracle_sample_short_stream(const uint8_t seed[32], uint64_t index, int p,
+                               int w, int stream, int8_t *f)
 {
     uint32_t *L = malloc(sizeof(uint32_t) * (size_t)p);
     int i;
     if (!L) return ORACLE_ENOMEM;
-    oracle_stream_words(seed, index, p, 0, L, p);
+    oracle_stream_words(seed, index, p, stream, L, p);
     for (i = 0; i < p; i++) {
         uint32_t v = (i < w) ? 2u * (L[i] & 1u) : 1u;
         L[i] = (L[i] & ~3u) | v;
@@ -169,6 +173,13 @@ int oracle_sample_short(const uint8_t seed[32], uint64_t index, int p, int w,
     for (i = 0; i < p; i++) f[i] = (int8_t)((int)(L[i] & 3u) - 1);
     free(L);
     return 0;
+}
+
+/* f in Short for KeyGen: stream 0. */
+int oracle_sample_short(const uint8_t seed[32], uint64_t index, int p, int w,
+                        int8_t *f)
+{
+    return oracle_sample_short_stream(seed, index, p, w, 0, f);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -406,4 +417,113 @@ out:
     *checksum = sum;
     free(f); free(g); free(gi); free(h);
     return done;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Encapsulation and decapsulation core                                      */
+/* ------------------------------------------------------------------------ */
+/*
+ * The paper uses sntrup as a KEM (Section 1: key generation, encapsulation
+ * with a public key, decapsulation with the secret key) and prints only the
+ * KeyGen steps.  What follows is the published Streamlined NTRU Prime core,
+ * restated:
+ *   encrypt(r, h), r in Short:  c = Round(h r) in R/q, where Round replaces
+ *     each centered coefficient by the nearest multiple of 3;
+ *   decrypt(c, f, v = 1/g):  e = 3 f c in R/q, centered; e reduced mod 3;
+ *     r' = e v in R/3, centered; if r' does not have weight w it is replaced
+ *     by the fixed weight-w element (1, ..., 1, 0, ..., 0) (w ones first);
+ *   decapsulation with the public key also encrypts r' again and reports
+ *     whether that gives c back.
+ * For a key pair and r in Short, decrypt(encrypt(r)) = r: the centered 3 f c
+ * equals g r + 3 f (c - h r) over Z when q > 16 w + 1 (every coefficient is
+ * below 8 w in size), so reducing mod 3 leaves g r.  The hashes that turn r
+ * and c into a session key, and a byte format for c, are not in the paper
+ * and are not computed here.
+ * Encapsulation draws r with the Short sampler from stream 0x8000 of the
+ * key's index (KeyGen uses streams 0 .. 64).
+ */
+#define ORACLE_ENCAP_STREAM 0x8000
+
+/* nearest multiple of 3 to x: 3 floor((x + 1) / 3) */
+static int64_t round3(int64_t x)
+{
+    int64_t y = x + 1;
+    int64_t fl = y >= 0 ? y / 3 : -((-y + 2) / 3);
+    return 3 * fl;
+}
+
+/* c = Round(h r) in R/q (h and r centered; c centered, a multiple of 3). */
+int oracle_encrypt(const int16_t *h, const int8_t *r, int p, int q, int16_t *c)
+{
+    int64_t *a = calloc((size_t)p, sizeof(int64_t));
+    int64_t *b = calloc((size_t)p, sizeof(int64_t));
+    int64_t *t = calloc((size_t)p, sizeof(int64_t));
+    int i, ret = ORACLE_ENOMEM;
+    if (!a || !b || !t) goto done;
+    for (i = 0; i < p; i++) { a[i] = h[i]; b[i] = r[i]; }
+    oracle_mul_mod(a, b, p, q, t);
+    for (i = 0; i < p; i++) c[i] = (int16_t)round3(center(t[i], q));
+    ret = 0;
+done:
+    free(a); free(b); free(t);
+    return ret;
+}
+
+/* r' = decrypt(c) as above; returns 1 if r' had weight w, 0 if it was
+   replaced by the fixed element, or a negative error. */
+int oracle_decrypt(const int16_t *c, const int8_t *f, const int8_t *ginv,
+                   int p, int q, int w, int8_t *r)
+{
+    int64_t *a = calloc((size_t)p, sizeof(int64_t));
+    int64_t *b = calloc((size_t)p, sizeof(int64_t));
+    int64_t *t = calloc((size_t)p, sizeof(int64_t));
+    int i, weight = 0, ret = ORACLE_ENOMEM;
+    if (!a || !b || !t) goto done;
+    /* e = 3 f c in R/q, centered, then mod 3 */
+    for (i = 0; i < p; i++) { a[i] = 3 * (int64_t)f[i]; b[i] = c[i]; }
+    oracle_mul_mod(a, b, p, q, t);
+    for (i = 0; i < p; i++) a[i] = mod_m(center(t[i], q), 3);
+    /* r' = e v in R/3 */
+    for (i = 0; i < p; i++) b[i] = ginv[i];
+    oracle_mul_mod(a, b, p, 3, t);
+    for (i = 0; i < p; i++) {
+        r[i] = (int8_t)center(t[i], 3);
+        weight += r[i] != 0;
+    }
+    if (weight != w)
+        for (i = 0; i < p; i++) r[i] = (int8_t)(i < w ? 1 : 0);
+    ret = weight == w;
+done:
+    free(a); free(b); free(t);
+    return ret;
+}
+
+/* Encapsulation core for key `index`: r in Short from the encapsulation
+   stream, c = encrypt(r, h). */
+int oracle_encap(const uint8_t seed[32], int p, int q, int w, uint64_t index,
+                 const int16_t *h, int16_t *c, int8_t *r)
+{
+    int ret = oracle_sample_short_stream(seed, index, p, w, ORACLE_ENCAP_STREAM, r);
+    if (ret != 0) return ret;
+    return oracle_encrypt(h, r, p, q, c);
+}
+
+/* Decapsulation core: r' = decrypt(c).  With h (not NULL) returns 1 iff
+   encrypt(r', h) = c; without h, 1 iff r' had weight w.  0 otherwise, or a
+   negative error. */
+int oracle_decap(const int16_t *c, const int8_t *f, const int8_t *ginv,
+                 const int16_t *h, int p, int q, int w, int8_t *r)
+{
+    int16_t *c2;
+    int i, ok = oracle_decrypt(c, f, ginv, p, q, w, r);
+    if (ok < 0 || !h) return ok;
+    c2 = malloc(sizeof(int16_t) * (size_t)p);
+    if (!c2) return ORACLE_ENOMEM;
+    ok = oracle_encrypt(h, r, p, q, c2);
+    if (ok == 0) {
+        ok = 1;
+        for (i = 0; i < p; i++) ok &= c2[i] == c[i];
+    }
+    free(c2);
+    return ok;
 }

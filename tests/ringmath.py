@@ -32,6 +32,19 @@ def mul_mod(a, b, p: int, m: int) -> np.ndarray:
     return reduce_mod_ring(full, p, m)
 
 
+def mul_z(a, b, p: int) -> np.ndarray:
+    """Product in Z[x]/(x^p - x - 1), exact (no coefficient reduction)."""
+    full = np.convolve(np.asarray(a, dtype=object), np.asarray(b, dtype=object))
+    c = [int(v) for v in full]
+    for k in range(len(c) - 1, p - 1, -1):
+        v = c[k]
+        if v:
+            c[k - p] += v
+            c[k - p + 1] += v
+            c[k] = 0
+    return np.array((c + [0] * p)[:p], dtype=np.int64)
+
+
 def mul_mod_sympy(a, b, p: int, m: int) -> np.ndarray:
     """Product in R/m computed by sympy's polynomial remainder over GF(m)."""
     import sympy as sp
