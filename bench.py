@@ -619,6 +619,39 @@ def main():
                                 "config": {"group_size": best[1], "inverse_share": best[2]},
                                 "method": "batchInv over R/3 after the invertibility screen (Algorithm 1)"}
         ctx.set_config(p, **saved)
+        # encapsulation / decapsulation core on this batch's key pairs: r and
+        # c = Round(h r); r' = decrypt(c) with the weight and re-encryption
+        # checks.  Whole-call times; checked by decap(encap) = r, ok = 1 for
+        # every key.
+        _, _, h_raw, f_raw, gi_raw = ctx.batch_keygen(p, wl.SEED, 0, n, raw=True)
+        seed_e = bytes(range(100, 132))
+        c_k, r_k = ctx.batch_encap(p, seed_e, 0, h_raw)
+        r_d, ok_d = ctx.batch_decap(p, c_k, f_raw, gi_raw, h_raw)
+        torch.cuda.synchronize()
+        if not (bool((r_d == r_k).all()) and bool((ok_d == 1).all())):
+            print("bench.py: decapsulation did not return r for every key", file=sys.stderr)
+            sys.exit(1)
+        kem = {}
+        for name, call, mfma_ops in (
+                ("encap", lambda: ctx.batch_encap(p, seed_e, 0, h_raw, c_k, r_k), 4.0 * p * p),
+                ("decap", lambda: ctx.batch_decap(p, c_k, f_raw, gi_raw, h_raw, r_d, ok_d), 10.0 * p * p)):
+            call()
+            torch.cuda.synchronize()
+            e0.record()
+            for _ in range(10):
+                call()
+            e1.record()
+            torch.cuda.synchronize()
+            k_ms = e0.elapsed_time(e1) / 10
+            kem[name] = {"keys_per_s": round(n / k_ms * 1e3, 1), "ms": round(k_ms, 4),
+                         "int8_ops_per_key": mfma_ops,
+                         "frac_of_mfma_peak": round(n * mfma_ops / (k_ms / 1e3) / I8_MFMA_PEAK, 4)}
+        kem["encap"]["call"] = "Short sampler (stream 0x8000) + kem_encap_kernel: one small x big product per key"
+        kem["decap"]["call"] = ("kem_decap_kernel: 3f c in R/q, e (1/g) in R/3, weight check, re-encryption "
+                                "Round(h r') against c")
+        kem["verified"] = "decap(encap) = r with ok = 1 for all %d keys" % n
+        extras["kem_core"] = kem
+        del h_raw, f_raw, gi_raw, c_k, r_k, r_d, ok_d
         # serving: Poisson arrivals, 70/20/10 % sntrup761/857/1277, device pools
         if args.serve_seconds > 0:
             from paper_2106_08759_amd import serve

@@ -14,7 +14,8 @@
  *   reciprocal is computed per key by constant-time divsteps (the extended-gcd
  *   algorithm of Bernstein and Yang that Section 3.1 cites), which also
  *   decides invertibility.  R = Z[x]/(x^p - x - 1), parameter sets of
- *   Section 2.1 plus sntrup1277 (q = 7879, w = 492).
+ *   Section 2.1 plus sntrup1277 (q = 7879, w = 492).  Also the encryption
+ *   core of encapsulation and decapsulation (ntrup_batch_encap/decap).
  *
  * Determinism.  Key i of a call is a pure function of (seed, p, first_index+i):
  *   randomness is ChaCha20 (RFC 8439 block function) keyed by the 32-byte
@@ -232,6 +233,33 @@ int ntrup_batch_keygen_mixed(ntrup_ctx *ctx, const uint8_t *seed, const ntrup_jo
  * Arguments, outputs and errors as for ntrup_batch_keygen. */
 int ntrup_batch_keygen_noalloc(ntrup_ctx *ctx, int p, const uint8_t *seed, uint64_t first_index, size_t n,
                                uint8_t *pk, uint8_t *sk, int16_t *h, int8_t *f, int8_t *ginv, void *stream);
+
+/* ---- encapsulation and decapsulation core ---------------------------------
+ * The KEM's other two algorithms (Section 1: encapsulation with a public key
+ * gives a ciphertext and a session key; decapsulation with the secret key
+ * gives the same session key back).  The paper prints only KeyGen; these
+ * compute Streamlined NTRU Prime's published encryption core on the batch:
+ *   ntrup_batch_encap:  r_i in Short from stream 0x8000 of key index
+ *     first_index+i (the seed and nonce layout above), c_i = Round(h_i r_i) in
+ *     R/q, Round = nearest multiple of 3 of each centered coefficient;
+ *   ntrup_batch_decap:  r'_i = ((3 f_i c_i in R/q) mod 3) (1/g)_i in R/3,
+ *     replaced by (1, .., 1, 0, .., 0) (w ones) unless it has weight w; with
+ *     h, ok_i = 1 iff Round(h_i r'_i) = c_i (the re-encryption check of the
+ *     KEM), without h, ok_i = 1 iff r'_i had weight w.
+ * For a key pair (h, (f, 1/g)) from ntrup_batch_keygen's raw outputs,
+ * decap(encap) returns r with ok = 1.  The hashes that derive a session key
+ * from r (and c), and a byte format for c, are not in the paper and are left
+ * to the caller.  All arrays are device pointers, row-major [n][p], centered
+ * (h, c int16; f, 1/g, r int8); ok is uint8 [n] (NULL = not written).  No
+ * workspace is used and nothing is allocated; calls are asynchronous on
+ * `stream` and are not ordered with other calls on the context.  n = 0 is a
+ * no-op; n above 2^23, an unknown p or a missing array give NTRUP_EINVAL.
+ * Decapsulation's instruction stream does not depend on the secret: the
+ * weight check and the fallback are selects. */
+int ntrup_batch_encap(ntrup_ctx *ctx, int p, const uint8_t *seed, uint64_t first_index, size_t n,
+                      const int16_t *h, int16_t *c, int8_t *r, void *stream);
+int ntrup_batch_decap(ntrup_ctx *ctx, int p, size_t n, const int16_t *c, const int8_t *f, const int8_t *ginv,
+                      const int16_t *h, int8_t *r, uint8_t *ok, void *stream);
 
 /* Synchronise `stream` and report the last keygen call on this context:
  * 0, NTRUP_EAGAIN, NTRUP_EFAULT or NTRUP_EIO. */

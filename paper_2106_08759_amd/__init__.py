@@ -91,6 +91,8 @@ def lib() -> ctypes.CDLL:
         "ntrup_op_recip_r3": (i32, [vp, i32, vp, vp, vp, sz, vp]),
         "ntrup_op_batch_inv_rq": (i32, [vp, i32, vp, vp, sz, sz, vp]),
         "ntrup_op_sample": (i32, [vp, i32, ctypes.c_char_p, u64, sz, i32, vp, vp, vp]),
+        "ntrup_batch_encap": (i32, [vp, i32, ctypes.c_char_p, u64, sz, vp, vp, vp, vp]),
+        "ntrup_batch_decap": (i32, [vp, i32, sz, vp, vp, vp, vp, vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -125,8 +127,8 @@ def params(p: int) -> Params:
     return Params(p, q.value, w.value, pkb.value, skb.value)
 
 
-def _ptr(t) -> int:
-    return t.data_ptr()
+def _ptr(t) -> int | None:
+    return None if t is None else t.data_ptr()
 
 
 def _stream(stream) -> int | None:
@@ -305,6 +307,44 @@ class Context:
         if check:
             self._check(self.status(stream), "keygen status")
         return outs
+
+    # ---- encapsulation / decapsulation core ------------------------------------
+    def _rows(self, t, n: int, p: int, dtype, what: str):
+        if t is None:
+            return None
+        if tuple(t.shape) != (n, p) or t.dtype != dtype or not t.is_cuda or not t.is_contiguous():
+            raise ValueError("%s must be a contiguous device tensor [%d, %d] of %s" % (what, n, p, dtype))
+        return t
+
+    def batch_encap(self, p: int, seed, first_index: int, h, c=None, r=None, stream=None):
+        """(c, r): r_i in Short from the encapsulation stream of key
+        first_index + i, c_i = Round(h_i r_i) in R/q (h: int16 [n, p])."""
+        T = self._torch
+        n = h.shape[0]
+        self._rows(h, n, p, T.int16, "h")
+        c = self._rows(c, n, p, T.int16, "c") if c is not None else self._empty((n, p), T.int16)
+        r = self._rows(r, n, p, T.int8, "r") if r is not None else self._empty((n, p), T.int8)
+        self._check(lib().ntrup_batch_encap(self._h, p, _seed_bytes(seed), first_index, n, _ptr(h), _ptr(c),
+                                            _ptr(r), _stream(stream)), "batch_encap")
+        return c, r
+
+    def batch_decap(self, p: int, c, f, ginv, h=None, r=None, ok=None, stream=None):
+        """(r', ok): r' = decrypt(c) with the weight check; ok = 1 iff
+        Round(h r') = c (with h) or r' had weight w (without)."""
+        T = self._torch
+        n = c.shape[0]
+        self._rows(c, n, p, T.int16, "c")
+        self._rows(f, n, p, T.int8, "f")
+        self._rows(ginv, n, p, T.int8, "ginv")
+        self._rows(h, n, p, T.int16, "h")
+        r = self._rows(r, n, p, T.int8, "r") if r is not None else self._empty((n, p), T.int8)
+        if ok is None:
+            ok = self._empty((n,), T.uint8)
+        elif tuple(ok.shape) != (n,) or ok.dtype != T.uint8 or not ok.is_cuda:
+            raise ValueError("ok must be a device tensor [%d] of uint8" % n)
+        self._check(lib().ntrup_batch_decap(self._h, p, n, _ptr(c), _ptr(f), _ptr(ginv), _ptr(h), _ptr(r),
+                                            _ptr(ok), _stream(stream)), "batch_decap")
+        return r, ok
 
     # ---- single operations ---------------------------------------------------
     def mul_rq(self, p: int, a, b, small_a: bool = False, stream=None):

@@ -633,6 +633,25 @@ int ntrup_op_batch_inv_rq(ntrup_ctx* ctx, int p, const int16_t* a, int16_t* out,
                    [&]() -> int { NTRUP_BY_P(p, op_batch_inv_rq<P>(ctx, mfma, a, out, n, group_size, st)); });
 }
 
+int ntrup_batch_encap(ntrup_ctx* ctx, int p, const uint8_t* seed, uint64_t first_index, size_t n, const int16_t* h,
+                      int16_t* c, int8_t* r, void* stream) {
+    if (!ctx || param_slot(p) < 0 || !seed || n > 0x7FFFFF) return NTRUP_EINVAL;
+    if (n == 0) return 0;
+    if (!h || !c || !r) return NTRUP_EINVAL;
+    if (int e = set_device(ctx)) return e;
+    const Seed sd = make_seed(seed);
+    NTRUP_BY_P(p, op_encap<P>(ctx, sd, first_index, n, h, c, r, (hipStream_t)stream));
+}
+
+int ntrup_batch_decap(ntrup_ctx* ctx, int p, size_t n, const int16_t* c, const int8_t* f, const int8_t* ginv,
+                      const int16_t* h, int8_t* r, uint8_t* ok, void* stream) {
+    if (!ctx || param_slot(p) < 0 || n > 0x7FFFFF) return NTRUP_EINVAL;
+    if (n == 0) return 0;
+    if (!c || !f || !ginv || !r) return NTRUP_EINVAL;
+    if (int e = set_device(ctx)) return e;
+    NTRUP_BY_P(p, op_decap<P>(ctx, n, c, f, ginv, h, r, ok, (hipStream_t)stream));
+}
+
 int ntrup_op_sample(ntrup_ctx* ctx, int p, const uint8_t* seed, uint64_t first_index, size_t n, int attempt,
                     int8_t* f, int8_t* g, void* stream) {
     if (!ctx || param_slot(p) < 0 || !seed || n == 0 || n > 0x7FFFFF || attempt < 0 ||

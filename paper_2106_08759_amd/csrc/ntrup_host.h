@@ -208,6 +208,16 @@ template <int P>
 int op_sample(ntrup_ctx* ctx, const Seed& sd, uint64_t first_index, size_t n, int attempt, int8_t* f, int8_t* g,
               hipStream_t st);
 
+// Encapsulation / decapsulation core (ntrup_kem.h): r sampled on the
+// encapsulation stream, c = Round(h r); r' = decrypt(c) with the weight
+// check, and with h the re-encryption check.
+template <int P>
+int op_encap(ntrup_ctx* ctx, const Seed& sd, uint64_t first_index, size_t n, const int16_t* h, int16_t* c, int8_t* r,
+             hipStream_t st);
+template <int P>
+int op_decap(ntrup_ctx* ctx, size_t n, const int16_t* c, const int8_t* f, const int8_t* ginv, const int16_t* h,
+             int8_t* r, uint8_t* ok, hipStream_t st);
+
 // Clear `count` ints (a fill kernel, not a memset node, so that captured
 // graphs replay it reliably).
 void launch_zero_ints(int* p, int count, hipStream_t st);

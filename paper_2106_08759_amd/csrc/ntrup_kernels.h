@@ -120,7 +120,8 @@ __device__ __forceinline__ void sample_short_key(const Seed& seed, uint64_t inde
     }
 }
 
-// f of four keys per 256-thread block.  A key needs only NB = ceil(p/16)
+// An element of Short (KeyGen's f: stream 0; encapsulation's r: its own
+// stream) for four keys per 256-thread block.  A key needs only NB = ceil(p/16)
 // ChaCha20 blocks (48 at p = 761, against the 64 that one block per lane of a
 // sorting wave would compute), so the block's threads compute the 4 NB blocks
 // first -- one per thread, the threads past them (a whole wave at
@@ -129,7 +130,7 @@ __device__ __forceinline__ void sample_short_key(const Seed& seed, uint64_t inde
 // writes (one ChaCha block per thread) and the reads (one slot per lane) hit
 // 64 different banks.
 template <int P>
-__global__ __launch_bounds__(256) void sample_short_kernel(Seed seed, uint64_t first_index, int n,
+__global__ __launch_bounds__(256) void sample_short_kernel(Seed seed, uint64_t first_index, int n, int stream,
                                                            int8_t* __restrict__ f_rows) {
     constexpr int W = Param<P>::w;
     constexpr int EPL = ShortShape<P>::EPL;
@@ -144,7 +145,7 @@ __global__ __launch_bounds__(256) void sample_short_kernel(Seed seed, uint64_t f
         const int k = b / NB, blk = b - k * NB;
         if (key0 + k < n) {
             uint32_t r[16];
-            chacha_block(seed, first_index + (uint64_t)(key0 + k), P, 0, (uint32_t)blk, r);
+            chacha_block(seed, first_index + (uint64_t)(key0 + k), P, stream, (uint32_t)blk, r);
             // element i = 16 blk + e sits in lane slot i / EPL at offset i % EPL
             uint32_t* dst = &words[k][(16 * blk / EPL) * SL + (16 * blk) % EPL];
 #pragma unroll

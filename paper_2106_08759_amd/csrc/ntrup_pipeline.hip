@@ -7,6 +7,7 @@
 
 #include "ntrup_host.h"
 #include "ntrup_kernels.h"
+#include "ntrup_kem.h"
 #include "ntrup_keygen.h"
 #include "ntrup_r3batch.h"
 #include "ntrup_tree.h"
@@ -115,7 +116,7 @@ int enqueue_keygen(ntrup_ctx* ctx, const ntrup_config& cfg, const Seed& seed, ui
         NTRUP_HIP(ctx, hipEventRecord(ctx->side_fork, st));
         NTRUP_HIP(ctx, hipStreamWaitEvent(ss, ctx->side_fork, 0));
     }
-    hipLaunchKernelGGL(sample_short_kernel<P>, dim3(grid_for(n, 4)), dim3(256), 0, st, seed, first_index, (int)n,
+    hipLaunchKernelGGL(sample_short_kernel<P>, dim3(grid_for(n, 4)), dim3(256), 0, st, seed, first_index, (int)n, 0,
                        w.f_rows);
     mark(1, st);
     if (side && !r3_first) {
@@ -329,8 +330,47 @@ template <int P>
 int op_sample(ntrup_ctx* ctx, const Seed& sd, uint64_t first_index, size_t n, int attempt, int8_t* f, int8_t* g,
               hipStream_t st) {
     const unsigned gw = grid_for(n * (size_t)ceil_div(P, 32), 256);
-    if (f) hipLaunchKernelGGL(sample_short_kernel<P>, dim3(grid_for(n, 4)), dim3(256), 0, st, sd, first_index, (int)n, f);
+    if (f)
+        hipLaunchKernelGGL(sample_short_kernel<P>, dim3(grid_for(n, 4)), dim3(256), 0, st, sd, first_index, (int)n, 0,
+                           f);
     if (g) hipLaunchKernelGGL(sample_small_kernel<P>, dim3(gw), dim3(256), 0, st, sd, first_index, (int)n, attempt, g);
+    NTRUP_HIP(ctx, hipGetLastError());
+    return 0;
+}
+
+template <int P>
+int op_encap(ntrup_ctx* ctx, const Seed& sd, uint64_t first_index, size_t n, const int16_t* h, int16_t* c, int8_t* r,
+             hipStream_t st) {
+    const int per = (int)((n + 7) / 8);
+    hipLaunchKernelGGL(sample_short_kernel<P>, dim3(grid_for(n, 4)), dim3(256), 0, st, sd, first_index, (int)n,
+                       kEncapStream, r);
+    KemArgs a;
+    memset(&a, 0, sizeof a);
+    a.n = (int)n;
+    a.per = per;
+    a.h = h;
+    a.c_out = c;
+    a.r = r;
+    hipLaunchKernelGGL(kem_encap_kernel<P>, dim3(8u * (unsigned)per), dim3(64), 0, st, a);
+    NTRUP_HIP(ctx, hipGetLastError());
+    return 0;
+}
+
+template <int P>
+int op_decap(ntrup_ctx* ctx, size_t n, const int16_t* c, const int8_t* f, const int8_t* ginv, const int16_t* h,
+             int8_t* r, uint8_t* ok, hipStream_t st) {
+    const int per = (int)((n + 7) / 8);
+    KemArgs a;
+    memset(&a, 0, sizeof a);
+    a.n = (int)n;
+    a.per = per;
+    a.h = h;
+    a.f = f;
+    a.ginv = ginv;
+    a.c_in = c;
+    a.r = r;
+    a.ok = ok;
+    hipLaunchKernelGGL(kem_decap_kernel<P>, dim3(8u * (unsigned)per), dim3(64), 0, st, a);
     NTRUP_HIP(ctx, hipGetLastError());
     return 0;
 }
@@ -345,6 +385,10 @@ template int op_mul_r3<NTRUP_P>(ntrup_ctx*, const int8_t*, const int8_t*, int8_t
 template int op_recip_rq<NTRUP_P>(ntrup_ctx*, bool, const int16_t*, int16_t*, int32_t*, size_t, hipStream_t);
 template int op_recip_r3<NTRUP_P>(ntrup_ctx*, int, const int8_t*, int8_t*, int32_t*, size_t, hipStream_t);
 template int op_batch_inv_rq<NTRUP_P>(ntrup_ctx*, bool, const int16_t*, int16_t*, size_t, size_t, hipStream_t);
+template int op_encap<NTRUP_P>(ntrup_ctx*, const Seed&, uint64_t, size_t, const int16_t*, int16_t*, int8_t*,
+                               hipStream_t);
+template int op_decap<NTRUP_P>(ntrup_ctx*, size_t, const int16_t*, const int8_t*, const int8_t*, const int16_t*,
+                               int8_t*, uint8_t*, hipStream_t);
 template int op_sample<NTRUP_P>(ntrup_ctx*, const Seed&, uint64_t, size_t, int, int8_t*, int8_t*, hipStream_t);
 
 }  // namespace ntrup
