@@ -120,9 +120,9 @@ def _key(device_name: str, p: int, n: int, mode: str = "auto") -> str:
     # v6: entries carry inverse_share, the launch form (eager / graph), the
     # kernel form (stage pipeline / persistent fused kernel) and the R/3 form
     # (per key / batched); G up to 256
-    # v8: and the reciprocals' forms (plain / jump divsteps), the group form
+    # v9: and the reciprocals' forms (plain / jump divsteps), the group form
     # (chain / tree)
-    return "%s|p=%d|n<=%d|%s|v8" % (device_name, p, bucket(n), mode)
+    return "%s|p=%d|n<=%d|%s|v9" % (device_name, p, bucket(n), mode)
 
 
 def load_cache(path: str | None = None) -> dict:
@@ -195,7 +195,12 @@ def tune(ctx, p: int, n: int, seed: bytes | None = None, reps: int = 3, force: b
     cur = {k: base[k] for k in KNOBS}
     cur["persistent"] = 0
     cur["r3_batch"] = 0
-    cur["recip_jump"] = 1
+    # eager launches run the per-key R/3 stage beside the prefix kernel, and
+    # the jump reciprocal's registers do not fit beside the one-lane R/3
+    # waves (it then waits for them: 2.6 vs 1.8 ms at sntrup761 N = 65536):
+    # the per-key phases time the plain reciprocal there, the batched-R/3
+    # phase the jump form; phase 2d tries the others
+    cur["recip_jump"] = 0 if ug == 0 else 1
     cur["group_form"] = 0
     ctx.set_config(p, product_engine=1)
     table = []
@@ -224,7 +229,7 @@ def tune(ctx, p: int, n: int, seed: bytes | None = None, reps: int = 3, force: b
     for g_, w_ in R3BATCH_CANDIDATES:
         if (g_, w_) not in {(c["group_size"], c["inverse_share"]) for c in group_candidates(p, n)}:
             continue
-        bc = dict(r3b, group_size=g_, inverse_share=w_, r3_batch=1, persistent=0)
+        bc = dict(r3b, group_size=g_, inverse_share=w_, r3_batch=1, persistent=0, recip_jump=1)
         bc = {k: bc[k] for k in KNOBS}
         table.append(dict(bc, ms=round(time_config(ctx, p, n, bc, seed, reps, pk, sk, ug), 4)))
     best = min(table, key=lambda r: r["ms"])
@@ -238,11 +243,13 @@ def tune(ctx, p: int, n: int, seed: bytes | None = None, reps: int = 3, force: b
         tc = {k: tc[k] for k in KNOBS}
         table.append(dict(tc, ms=round(time_config(ctx, p, n, tc, seed, reps, pk, sk, ug), 4)))
     best = min(table, key=lambda r: r["ms"])
-    # phase 2d: the reciprocal forms at the chosen setting: both plain, and
-    # with batched R/3 also jump divsteps for its group reciprocals (the
-    # persistent form always runs the plain loops)
+    # phase 2d: the other reciprocal forms at the chosen setting (plain or
+    # jump R/q reciprocal; with batched R/3 also jump divsteps for its group
+    # reciprocals; the persistent form always runs the plain loops)
     if not best["persistent"]:
-        for rj in ((0, 3) if best["r3_batch"] else (0,)):
+        for rj in sorted({0, 1, 3} if best["r3_batch"] else {0, 1}):
+            if rj == best["recip_jump"]:
+                continue
             pc = {k: best[k] for k in KNOBS}
             pc["recip_jump"] = rj
             table.append(dict(pc, ms=round(time_config(ctx, p, n, pc, seed, reps, pk, sk, ug), 4)))

@@ -3,7 +3,8 @@ inputs each (same shapes), one after the other, for a hardware-counter run
 (test_gpu_constant_time.py runs it under rocprofv3 --pmc): the R/3 reciprocal
 (bitsliced divsteps, four lane layouts), the R/q reciprocal (plain divstep
 loop and jump divsteps), the R/q product with a small and with a big
-operand, and the Short and small samplers.  Prints one line per operation."""
+operand, the Short and small samplers, and the encapsulation and
+decapsulation core.  Prints one line per operation."""
 import os
 import sys
 
@@ -52,6 +53,15 @@ def main():
         ctx.sample(p, sd, 0, n)
     torch.cuda.synchronize()
     print("samplers", flush=True)
+    # encapsulation (secret: r, from the seed) and decapsulation (secret: f
+    # and 1/g; the weight check and its fallback are selects)
+    for sd in seeds:
+        ctx.batch_encap(p, sd, 0, bigs[0])
+    cts = [(3 * torch.div(b, 3, rounding_mode="trunc")).contiguous() for b in bigs]
+    for i in range(3):
+        ctx.batch_decap(p, cts[0], smalls[i], smalls[(i + 1) % 3], bigs[0])
+    torch.cuda.synchronize()
+    print("kem encap and decap", flush=True)
     ctx.close()
 
 

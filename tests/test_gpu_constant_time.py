@@ -35,7 +35,7 @@ def test_secret_independent_instruction_counts(tmp_path):
     cmd = [rocprof, "--pmc", *COUNTERS, "--output-format", "csv", "-d", str(tmp_path / "ct"), "-o", "ct", "--",
            sys.executable, os.path.join(HERE, "ct_probe.py")]
     out = subprocess.run(cmd, cwd=str(tmp_path), env=env, capture_output=True, text=True, timeout=240)
-    assert "samplers" in out.stdout, out.stdout[-2000:] + out.stderr[-2000:]
+    assert "kem encap and decap" in out.stdout, out.stdout[-2000:] + out.stderr[-2000:]
     per = {}
     for row in counter_rows(str(tmp_path / "ct")):
         if not row["Kernel_Name"].startswith(("ntrup::", "void ntrup::")):
@@ -47,6 +47,7 @@ def test_secret_independent_instruction_counts(tmp_path):
         by_kernel.setdefault(name, []).append(tuple(c.get(k, -1.0) for k in COUNTERS))
     assert any("r3_kernel" in k for k in by_kernel) and any("recip_q_kernel" in k for k in by_kernel)
     assert any("sample_short_kernel" in k for k in by_kernel) and any("mulm_kernel" in k for k in by_kernel)
+    assert any("kem_encap_kernel" in k for k in by_kernel) and any("kem_decap_kernel" in k for k in by_kernel)
     for name, seq in by_kernel.items():
         # each operation ran on three secret inputs in a row: dispatches of one
         # kernel come in runs of three with identical counts
