@@ -270,7 +270,8 @@ def cpu_baseline(p: int, seconds: float, check: list) -> tuple:
             ref)
 
 
-CALIB_KINDS = {0: "arx (add, xor, rotate)", 1: "v_add_u32", 2: "v_bitop3_b32", 3: "v_alignbit_b32", 4: "v_mad_u32_u24"}
+CALIB_KINDS = {0: "arx (add, xor, rotate)", 1: "v_add_u32", 2: "v_bitop3_b32", 3: "v_alignbit_b32", 4: "v_mad_u32_u24",
+               5: "v_perm_b32", 6: "v_xor_b32 + v_add_u32"}
 
 
 def calib_valu(iters: int = 20000, reps: int = 5) -> dict:

@@ -9,6 +9,8 @@
 //   2 bitop3  v_bitop3_b32 with the majority function (a = maj(a, b, c) ...)
 //   3 align   v_alignbit_b32 of two registers (a = alignbit(a, b, s) ...)
 //   4 mad24   v_mad_u32_u24 (a = a * b + c on 24-bit operands)
+//   5 perm    v_perm_b32 byte permutes of two registers (a = perm(a, b, s))
+//   6 xor     v_xor_b32 and v_add_u32 (a ^= b'; b ^= a + 1)
 // Timed over grids of 1, 2, 4 or 8 waves per SIMD.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -50,9 +52,15 @@ __global__ __launch_bounds__(64) void valu_chain_kernel(uint32_t* out, int iters
             } else if constexpr (KIND == 3) {
                 a[k] = __builtin_amdgcn_alignbit(a[k], b[k], 3 + 2 * k);
                 b[k] = __builtin_amdgcn_alignbit(b[k], a[k], 29 - 2 * k);
-            } else {
+            } else if constexpr (KIND == 4) {
                 a[k] = __umul24(a[k], b[k]) + 0x5bd1e995u;
                 b[k] = __umul24(b[k], a[k]) + 0x1b873593u;
+            } else if constexpr (KIND == 5) {
+                a[k] = __builtin_amdgcn_perm(a[k], b[k], 0x05040302u + 0x01010101u * (k & 1));
+                b[k] = __builtin_amdgcn_perm(b[k], a[k], 0x02010007u);
+            } else {
+                a[k] ^= b[(k + 1) & 7];
+                b[k] ^= a[k] + 1u;
             }
         }
     }
@@ -69,20 +77,22 @@ extern "C" {
 // Launch probe `kind` (0..4) over `blocks` one-wave blocks of `iters` steps
 // each on `stream`; out: device, blocks * 64 words.  Returns a hipError_t.
 int calib_valu(int kind, int blocks, int iters, uint32_t* out, void* stream) {
-    if (blocks <= 0 || iters <= 0 || !out || kind < 0 || kind > 4) return (int)hipErrorInvalidValue;
+    if (blocks <= 0 || iters <= 0 || !out || kind < 0 || kind > 6) return (int)hipErrorInvalidValue;
     const hipStream_t st = (hipStream_t)stream;
     switch (kind) {
         case 0: hipLaunchKernelGGL(valu_chain_kernel<0>, dim3((unsigned)blocks), dim3(64), 0, st, out, iters); break;
         case 1: hipLaunchKernelGGL(valu_chain_kernel<1>, dim3((unsigned)blocks), dim3(64), 0, st, out, iters); break;
         case 2: hipLaunchKernelGGL(valu_chain_kernel<2>, dim3((unsigned)blocks), dim3(64), 0, st, out, iters); break;
         case 3: hipLaunchKernelGGL(valu_chain_kernel<3>, dim3((unsigned)blocks), dim3(64), 0, st, out, iters); break;
-        default: hipLaunchKernelGGL(valu_chain_kernel<4>, dim3((unsigned)blocks), dim3(64), 0, st, out, iters); break;
+        case 4: hipLaunchKernelGGL(valu_chain_kernel<4>, dim3((unsigned)blocks), dim3(64), 0, st, out, iters); break;
+        case 5: hipLaunchKernelGGL(valu_chain_kernel<5>, dim3((unsigned)blocks), dim3(64), 0, st, out, iters); break;
+        default: hipLaunchKernelGGL(valu_chain_kernel<6>, dim3((unsigned)blocks), dim3(64), 0, st, out, iters); break;
     }
     return (int)hipGetLastError();
 }
 
 // VALU instructions per lane and step of probe `kind` (8 chains x 3 for the
-// add-xor-rotate mix, 8 x 2 otherwise).
-int calib_valu_ops_per_step(int kind) { return kind == 0 ? 24 : 16; }
+// add-xor-rotate mix and the xor kind, 8 x 2 otherwise).
+int calib_valu_ops_per_step(int kind) { return (kind == 0 || kind == 6) ? 24 : 16; }
 
 }

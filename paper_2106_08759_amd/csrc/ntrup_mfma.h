@@ -77,6 +77,77 @@ struct MfShape {
 
 typedef int mf_v4i __attribute__((ext_vector_type(4)));
 
+// The Toeplitz fragment of a lane is 16 consecutive bytes of the reversed limb
+// array at a byte offset fixed per lane (Z0 - 16 g - r, less 64 per K-step):
+// five aligned dwords joined by v_alignbyte (four VALU operations per
+// fragment).  NTRUP_MF_UNALIGNED = 1 reads it with one ds_read_b128 at the
+// unaligned byte address instead (the LDS runs in unaligned mode on gfx950):
+// correct, but the unaligned reads stall the LDS, and a batch took 1.90
+// instead of 1.37 ms.
+#ifndef NTRUP_MF_UNALIGNED
+#define NTRUP_MF_UNALIGNED 0
+#endif
+__device__ __forceinline__ mf_v4i lds_read16(const uint8_t* p) {
+    mf_v4i v;
+    __builtin_memcpy(&v, p, 16);
+    return v;
+}
+
+// Fragment reader for one reversed limb array: 16 bytes from byte
+// s0 - 64 k at K-step k.
+struct ToeplitzFrag {
+    const uint8_t* base;   // array + s0
+    const uint32_t* w32;   // aligned-dword form
+    int sh;
+    uint32_t d[5];
+    mf_v4i v;
+    __device__ __forceinline__ ToeplitzFrag(const uint8_t* arr, int s0)
+        : base(arr + s0), w32((const uint32_t*)arr + (s0 >> 2)), sh(s0 & 3) {}
+    __device__ __forceinline__ void load(int k) {
+        if (NTRUP_MF_UNALIGNED) {
+            v = lds_read16(base - 64 * k);
+        } else {
+#pragma unroll
+            for (int j = 0; j < 5; j++) d[j] = w32[j - 16 * k];
+        }
+    }
+    __device__ __forceinline__ mf_v4i get() const {
+        if (NTRUP_MF_UNALIGNED) return v;
+        mf_v4i t;
+#pragma unroll
+        for (int j = 0; j < 4; j++) t[j] = (int)__builtin_amdgcn_alignbyte(d[j + 1], d[j], sh);
+        return t;
+    }
+};
+
+// Combining the limb partial sums of a big x big product into a centered
+// residue: s = a0 + 2^7 a1 + 2^14 a2 (mod q), where a0 sums lo x lo, a1
+// lo x hi + hi x lo and a2 hi x hi over at most p pairs.  The Toeplitz
+// operand is a centered residue (|lo| <= 64, |hi| <= AH) and the folded
+// Hankel operand a sum of two (|lo| <= 64, |hi| <= EH), so
+// |a0 + 2^7 a1| <= p (64^2 + 2^7 (64 EH + 64 AH)) and |a2| <= p AH EH.
+// With C = |2^14 mod q| (centered) the raw sum fits int32 when
+// p (64^2 + 2^7 (64 EH + 64 AH) + C AH EH) < 2^31 (p = 653, 761, 857): one
+// reduction.  Otherwise (p = 1277) a2 is reduced first, |C rr(a2)| < 3Cq/2.
+template <int P, int Q>
+struct LimbSum {
+    static constexpr int64_t C14 = ((16384 % Q) > Q / 2) ? (16384 % Q) - Q : (16384 % Q);
+    static constexpr int64_t C = C14 < 0 ? -C14 : C14;
+    static constexpr int64_t AH = ((Q - 1) / 2 + 64) / 128;
+    static constexpr int64_t EH = ((Q - 1) + 64) / 128;
+    static constexpr int64_t LOWER = (int64_t)P * (64 * 64 + 128 * (64 * EH + 64 * AH));
+    static constexpr bool DIRECT = LOWER + (int64_t)P * C * AH * EH < 2147483647LL;
+    static_assert(DIRECT || LOWER + C * (3 * Q / 2 + 1) < 2147483647LL, "a0 + 2^7 a1 + C rr(a2) fits int32");
+};
+
+template <int P, int Q>
+__device__ __forceinline__ int32_t limb_sum(int32_t a0, int32_t a1, int32_t a2) {
+    using B = LimbSum<P, Q>;
+    constexpr int32_t C14 = (int32_t)B::C14;
+    if constexpr (B::DIRECT) return freeze<Q>(a0 + 128 * a1 + C14 * a2);
+    else return freeze<Q>(a0 + 128 * a1 + C14 * reduce_rough<Q>(a2));
+}
+
 // x = 128 hi + lo, lo in [-64, 64), as two int8 values.
 __device__ __forceinline__ void split_limb(int32_t x, uint32_t& lo, uint32_t& hi) {
     const int32_t h = (x + 64) >> 7;
@@ -228,9 +299,7 @@ __device__ __forceinline__ void mfma_tiles(const uint8_t* TL, const uint8_t* TH,
     const int rc = lane & 15, g = lane >> 4;
     // Toeplitz read position of K-step 0: bytes from Z0 - 16 g - rc
     const int s0 = S::Z0 - 16 * g - rc;
-    const int sh = s0 & 3;
-    const uint32_t* tl32 = (const uint32_t*)TL + (s0 >> 2);
-    const uint32_t* th32 = (const uint32_t*)(T_BIG ? TH : TL) + (s0 >> 2);
+    ToeplitzFrag nFL(TL, s0), nFH(T_BIG ? TH : TL, s0);
     // Hankel read position of tile 0, K-step 0: block rc - g
     const uint8_t* hl = HL + S::HOFF + 16 * (rc - g);
     const uint8_t* hh = H_BIG ? HH + S::HOFF + 16 * (rc - g) : hl;
@@ -242,14 +311,10 @@ __device__ __forceinline__ void mfma_tiles(const uint8_t* TL, const uint8_t* TH,
         acc2[t] = mf_v4i{0, 0, 0, 0};
     }
     // fragments of the next K-step
-    uint32_t nDL[5], nDH[5];
     mf_v4i nBL[NTC], nBH[NTC];
     auto load_step = [&](int k) {
-#pragma unroll
-        for (int j = 0; j < 5; j++) {
-            nDL[j] = tl32[j - 16 * k];
-            if (T_BIG) nDH[j] = th32[j - 16 * k];
-        }
+        nFL.load(k);
+        if (T_BIG) nFH.load(k);
 #pragma unroll
         for (int t = 0; t < NTC; t++) {
             const int off = 16 * (16 * (T0 + t) - 4 * k);
@@ -262,25 +327,16 @@ __device__ __forceinline__ void mfma_tiles(const uint8_t* TL, const uint8_t* TH,
     for (int k = 0; k < S::NKS; k++) {
         // one K-step of fragments in flight beyond the current one
         if (NTRUP_MF_SCHED) __builtin_amdgcn_sched_barrier(0);
-        uint32_t DL[5], DH[5];
+        const ToeplitzFrag FL = nFL, FH = nFH;
         mf_v4i BL[NTC], BH[NTC];
-#pragma unroll
-        for (int j = 0; j < 5; j++) {
-            DL[j] = nDL[j];
-            if (T_BIG) DH[j] = nDH[j];
-        }
 #pragma unroll
         for (int t = 0; t < NTC; t++) {
             BL[t] = nBL[t];
             BH[t] = nBH[t];
         }
         if (k + 1 < S::NKS) load_step(k + 1);
-        mf_v4i tl, th;
-#pragma unroll
-        for (int j = 0; j < 4; j++) {
-            tl[j] = (int)__builtin_amdgcn_alignbyte(DL[j + 1], DL[j], sh);
-            if (T_BIG) th[j] = (int)__builtin_amdgcn_alignbyte(DH[j + 1], DH[j], sh);
-        }
+        const mf_v4i tl = FL.get();
+        const mf_v4i th = T_BIG ? FH.get() : tl;
 #pragma unroll
         for (int t = 0; t < NTC; t++) {
             if (H_BIG) {
@@ -294,8 +350,6 @@ __device__ __forceinline__ void mfma_tiles(const uint8_t* TL, const uint8_t* TH,
             }
         }
     }
-    // 2^14 mod q, centered
-    constexpr int32_t C14 = ((16384 % Q) > Q / 2) ? (16384 % Q) - Q : (16384 % Q);
 #pragma unroll
     for (int t = 0; t < NTC; t++) {
         const int i = 256 * (T0 + t) + 16 * rc + 4 * g;
@@ -303,8 +357,7 @@ __device__ __forceinline__ void mfma_tiles(const uint8_t* TL, const uint8_t* TH,
 #pragma unroll
         for (int e = 0; e < 4; e++) {
             if (H_BIG)
-                v[e] = freeze<Q>(reduce_rough<Q>(acc0[t][e]) + 128 * reduce_rough<Q>(acc1[t][e]) +
-                                 C14 * reduce_rough<Q>(acc2[t][e]));
+                v[e] = limb_sum<P, Q>(acc0[t][e], acc1[t][e], acc2[t][e]);
             else if (T_BIG)
                 v[e] = freeze<Q>(acc0[t][e] + 128 * acc1[t][e]);
             else
@@ -423,23 +476,17 @@ __device__ __forceinline__ void mfma_tiles2(const uint8_t* TL, const uint8_t* TH
     const int lane = lane_id();
     const int rc = lane & 15, g = lane >> 4;
     const int s0 = S::Z0 - 16 * g - rc;
-    const int sh = s0 & 3;
-    const uint32_t* tl32 = (const uint32_t*)TL + (s0 >> 2);
-    const uint32_t* th32 = (const uint32_t*)TH + (s0 >> 2);
+    ToeplitzFrag nFL(TL, s0), nFH(TH, s0);
     const int hoff = S::HOFF + 16 * (rc - g);
     mf_v4i a0[NTC], a1[NTC], a2[NTC], s0a[NTC], s1a[NTC];
 #pragma unroll
     for (int t = 0; t < NTC; t++) {
         a0[t] = a1[t] = a2[t] = s0a[t] = s1a[t] = mf_v4i{0, 0, 0, 0};
     }
-    uint32_t nDL[5], nDH[5];
     mf_v4i nBL[NTC], nBH[NTC], nBS[NTC];
     auto load_step = [&](int k) {
-#pragma unroll
-        for (int j = 0; j < 5; j++) {
-            nDL[j] = tl32[j - 16 * k];
-            nDH[j] = th32[j - 16 * k];
-        }
+        nFL.load(k);
+        nFH.load(k);
 #pragma unroll
         for (int t = 0; t < NTC; t++) {
             const int off = hoff + 16 * (16 * (T0 + t) - 4 * k);
@@ -452,13 +499,8 @@ __device__ __forceinline__ void mfma_tiles2(const uint8_t* TL, const uint8_t* TH
 #pragma unroll
     for (int k = 0; k < S::NKS; k++) {
         if (NTRUP_MF_SCHED) __builtin_amdgcn_sched_barrier(0);
-        uint32_t DL[5], DH[5];
+        const ToeplitzFrag FL = nFL, FH = nFH;
         mf_v4i BL[NTC], BH[NTC], BS[NTC];
-#pragma unroll
-        for (int j = 0; j < 5; j++) {
-            DL[j] = nDL[j];
-            DH[j] = nDH[j];
-        }
 #pragma unroll
         for (int t = 0; t < NTC; t++) {
             BL[t] = nBL[t];
@@ -466,12 +508,7 @@ __device__ __forceinline__ void mfma_tiles2(const uint8_t* TL, const uint8_t* TH
             BS[t] = nBS[t];
         }
         if (k + 1 < S::NKS) load_step(k + 1);
-        mf_v4i tl, th;
-#pragma unroll
-        for (int j = 0; j < 4; j++) {
-            tl[j] = (int)__builtin_amdgcn_alignbyte(DL[j + 1], DL[j], sh);
-            th[j] = (int)__builtin_amdgcn_alignbyte(DH[j + 1], DH[j], sh);
-        }
+        const mf_v4i tl = FL.get(), th = FH.get();
 #pragma unroll
         for (int t = 0; t < NTC; t++) {
             a0[t] = __builtin_amdgcn_mfma_i32_16x16x64_i8(tl, BL[t], a0[t], 0, 0, 0);
@@ -482,15 +519,13 @@ __device__ __forceinline__ void mfma_tiles2(const uint8_t* TL, const uint8_t* TH
             s1a[t] = __builtin_amdgcn_mfma_i32_16x16x64_i8(th, BS[t], s1a[t], 0, 0, 0);
         }
     }
-    constexpr int32_t C14 = ((16384 % Q) > Q / 2) ? (16384 % Q) - Q : (16384 % Q);
 #pragma unroll
     for (int t = 0; t < NTC; t++) {
         const int i = 256 * (T0 + t) + 16 * rc + 4 * g;
         int32_t v[4], w[4];
 #pragma unroll
         for (int e = 0; e < 4; e++) {
-            v[e] = freeze<Q>(reduce_rough<Q>(a0[t][e]) + 128 * reduce_rough<Q>(a1[t][e]) +
-                             C14 * reduce_rough<Q>(a2[t][e]));
+            v[e] = limb_sum<P, Q>(a0[t][e], a1[t][e], a2[t][e]);
             w[e] = freeze<Q>(s0a[t][e] + 128 * s1a[t][e]);
             v[e] = (i + e < P) ? v[e] : 0;
             w[e] = (i + e < P) ? w[e] : 0;
