@@ -61,7 +61,10 @@ struct JumpShape {
     static constexpr int HLEN = kJumpHOff + 256 * NT;
     static constexpr int NJUMP = ceil_div(2 * P - 1, kJumpN);
     static_assert(kJumpN + 1 <= 64, "U and the truncated f, g fit one coefficient per lane");
-    static_assert(16 * 3 + 15 >= kJumpN && kJumpZ0 >= 63 && (kJumpZ0 - 3) % 4 == 0, "one K-step covers U");
+    // output row r of a block sums u_k for k in [r - 15, r + 48] (four
+    // 16-blocks of one K-step), so every r sees all of u_0 .. u_n only for
+    // n <= 48 (a 60-step jump misses u_49 .. u_60 in rows r < 12)
+    static_assert(16 * 3 >= kJumpN && kJumpZ0 >= 63 && (kJumpZ0 - 3) % 4 == 0, "one K-step covers U");
     static_assert(kJumpN % 4 == 0, "f' = out shifted by n stays dword-aligned (full jumps only)");
     static_assert(kJumpN % 3 == 0 && (2 * P - 1) % 3 == 0, "every jump is whole three-step trips");
     static_assert(HLEN % 16 == 0, "16-byte Hankel reads stay aligned");
@@ -102,21 +105,11 @@ __device__ __forceinline__ void jump_mac(const uint8_t* TL, const uint8_t* TH, c
     const int lane = lane_id();
     const int rc = lane & 15, gq = lane >> 4;
     const int s0 = kJumpZ0 - 16 * gq - rc;   // first byte: u_{16 gq + rc}
-    const int sh = s0 & 3;
-    const uint32_t* tl32 = (const uint32_t*)TL + (s0 >> 2);
-    const uint32_t* th32 = (const uint32_t*)TH + (s0 >> 2);
-    mf_v4i tl, th;
-    uint32_t DL[5], DH[5];
-#pragma unroll
-    for (int j = 0; j < 5; j++) {
-        DL[j] = tl32[j];
-        DH[j] = th32[j];
-    }
-#pragma unroll
-    for (int j = 0; j < 4; j++) {
-        tl[j] = (int)__builtin_amdgcn_alignbyte(DL[j + 1], DL[j], sh);
-        th[j] = (int)__builtin_amdgcn_alignbyte(DH[j + 1], DH[j], sh);
-    }
+    ToeplitzFrag FL(TL, s0), FH(TH, s0);
+    FL.load(0);
+    if (LIMBS == 2) FH.load(0);
+    const mf_v4i tl = FL.get();
+    const mf_v4i th = LIMBS == 2 ? FH.get() : tl;
     const uint8_t* xl = XL + kJumpHOff + 16 * (rc - gq);
     const uint8_t* xh = XH + kJumpHOff + 16 * (rc - gq);
 #pragma unroll
@@ -164,6 +157,7 @@ __device__ __forceinline__ void jump_output(JumpLds<P>& L, int ia, int ib, const
 #pragma unroll
         for (int e = 0; e < 4; e++) {
             // |a0| + 128 |a1| + |C14| |a2| < 2^31: at most 98 limb products per output
+            // (two products of 49 coefficients of U by residues)
             const int32_t s = LIMBS == 1 ? a0[t][e] : a0[t][e] + 128 * a1[t][e] + C14 * a2[t][e];
             y[e] = (m + e <= P) ? freeze<Q>(s) : 0;
         }
@@ -184,37 +178,49 @@ __device__ __forceinline__ void jump_output(JumpLds<P>& L, int ia, int ib, const
 // Reciprocal of the centered element Bin (LDS, p entries) in R/M, M = q
 // (R/q, residues as two 7-bit limbs) or M = 3 (R/3, one limb), by jump
 // divsteps.  Writes the centered reciprocal to OUT (LDS, may alias Bin).
-// Returns 1 iff Bin is a unit.  One wave; L is its own.
-template <int P, int M = Param<P>::q, typename T = int16_t>
-__device__ int recip_jump_wave(const T* Bin, T* OUT, JumpLds<P>& L) {
+// Returns 1 iff Bin is a unit (on wave 0).
+//
+// COOP = false: one wave (wave 0, nw = 1) does everything; other waves of
+// the block need not take part.  COOP = true: all nw waves of the block call
+// it (block barriers): wave 0 runs each jump's inner steps, then the jump's
+// four output products (f', g', v', r') are dealt to the waves, output o to
+// wave o mod nw, so that they run side by side.
+template <int P, int M, typename T, bool COOP>
+__device__ int recip_jump_block(const T* Bin, T* OUT, JumpLds<P>& L, int wave, int nw) {
     using S = JumpShape<P>;
     constexpr int Q = M;
     const int lane = lane_id();
+    auto sync = [&]() {
+        if constexpr (COOP) __syncthreads();
+        else wave_sync();
+    };
     // both Hankel sets and the Toeplitz arrays start zeroed
     {
         uint32_t* z = (uint32_t*)&L.H[0][0][0][0];
-        for (int i = lane; i < 2 * 4 * 2 * S::HLEN / 4; i += 64) z[i] = 0u;
+        for (int i = lane + 64 * wave; i < 2 * 4 * 2 * S::HLEN / 4; i += 64 * nw) z[i] = 0u;
         uint32_t* zt = (uint32_t*)&L.T[0][0][0];
-        for (int i = lane; i < 4 * 2 * kJumpTLen / 4; i += 64) zt[i] = 0u;
+        for (int i = lane + 64 * wave; i < 4 * 2 * kJumpTLen / 4; i += 64 * nw) zt[i] = 0u;
     }
-    wave_sync();
+    sync();
     // set 0: f = 1 - x^(p-1) - x^p, g = Bin reversed, v = 0, r = 1
-    for (int m = 4 * lane; m <= P; m += 256) {
-        int32_t fx[4], gx[4], rx[4];
+    if (wave == 0) {
+        for (int m = 4 * lane; m <= P; m += 256) {
+            int32_t fx[4], gx[4], rx[4];
 #pragma unroll
-        for (int e = 0; e < 4; e++) {
-            const int i = m + e;
-            fx[e] = (i == 0) ? 1 : ((i == P - 1 || i == P) ? -1 : 0);
-            gx[e] = (i < P) ? (int32_t)Bin[P - 1 - i] : 0;
-            rx[e] = (i == 0) ? 1 : 0;
+            for (int e = 0; e < 4; e++) {
+                const int i = m + e;
+                fx[e] = (i == 0) ? 1 : ((i == P - 1 || i == P) ? -1 : 0);
+                gx[e] = (i < P) ? (int32_t)Bin[P - 1 - i] : 0;
+                rx[e] = (i == 0) ? 1 : 0;
+            }
+            jump_put4(L.H[0][0][0] + kJumpHOff, L.H[0][0][1] + kJumpHOff, m, fx);
+            jump_put4(L.H[0][1][0] + kJumpHOff, L.H[0][1][1] + kJumpHOff, m, gx);
+            jump_put4(L.H[0][3][0] + kJumpHOff, L.H[0][3][1] + kJumpHOff, m, rx);
         }
-        jump_put4(L.H[0][0][0] + kJumpHOff, L.H[0][0][1] + kJumpHOff, m, fx);
-        jump_put4(L.H[0][1][0] + kJumpHOff, L.H[0][1][1] + kJumpHOff, m, gx);
-        jump_put4(L.H[0][3][0] + kJumpHOff, L.H[0][3][1] + kJumpHOff, m, rx);
+        L.low[0][lane] = (lane == 0) ? 1 : 0;
+        L.low[1][lane] = (lane < P) ? (int32_t)Bin[P - 1 - lane] : 0;
     }
-    L.low[0][lane] = (lane == 0) ? 1 : 0;
-    L.low[1][lane] = (lane < P) ? (int32_t)Bin[P - 1 - lane] : 0;
-    wave_sync();
+    sync();
 
     int32_t delta = 1, fend = 1;
     constexpr int NSTEP = 2 * P - 1;
@@ -222,34 +228,36 @@ __device__ int recip_jump_wave(const T* Bin, T* OUT, JumpLds<P>& L) {
     for (int jmp = 0; jmp < S::NJUMP; jmp++) {
         const int cur = jmp & 1, nxt = cur ^ 1;
         const int n = min(kJumpN, NSTEP - jmp * kJumpN);
-        // 1. n divsteps on the low 64 coefficients, building U
-        int32_t F = L.low[0][lane], G = L.low[1][lane];
-        int32_t u00 = (lane == 0) ? 1 : 0, u01 = 0, u10 = 0, u11 = (lane == 0) ? 1 : 0;
-        // n is a multiple of 3 (2p - 1 is for every parameter set): three
-        // steps per trip, so that the updated registers are renamed, not moved
+        int32_t F = 0;
+        if (wave == 0) {
+            // 1. n divsteps on the low 64 coefficients, building U
+            F = L.low[0][lane];
+            int32_t G = L.low[1][lane];
+            int32_t u00 = (lane == 0) ? 1 : 0, u01 = 0, u10 = 0, u11 = (lane == 0) ? 1 : 0;
+            // n is a multiple of 3 (2p - 1 is for every parameter set): three
+            // steps per trip, so that the updated registers are renamed, not moved
 #pragma unroll 1
-        for (int j = 0; j < n; j += 3) {
+            for (int j = 0; j < n; j += 3) {
 #pragma unroll
-        for (int jj = 0; jj < 3; jj++) {
-            const int32_t f0 = __builtin_amdgcn_readfirstlane(F);
-            const int32_t g0 = __builtin_amdgcn_readfirstlane(G);
-            const int32_t sw = -((int32_t)(delta > 0) & (int32_t)(freeze<Q>(g0) != 0));
-            delta = bsel(sw, -delta, delta) + 1;
-            const int32_t ng0 = -g0;
-            const int32_t ng = reduce_rough<Q>(mul24(ng0, F) + mul24(f0, G));
-            const int32_t n10 = reduce_rough<Q>(mul24(ng0, u00) + mul24(f0, u10));
-            const int32_t n11 = reduce_rough<Q>(mul24(ng0, u01) + mul24(f0, u11));
-            F = bsel(sw, G, F);
-            const int32_t r0a = bsel(sw, u10, u00), r0b = bsel(sw, u11, u01);
-            G = from_next_lane(ng);
-            u00 = from_prev_lane(r0a);
-            u01 = from_prev_lane(r0b);
-            u10 = n10;
-            u11 = n11;
-        }
-        }
-        // 2. U's limbs as reversed Toeplitz bytes (coefficients above n are zero)
-        {
+            for (int jj = 0; jj < 3; jj++) {
+                const int32_t f0 = __builtin_amdgcn_readfirstlane(F);
+                const int32_t g0 = __builtin_amdgcn_readfirstlane(G);
+                const int32_t sw = -((int32_t)(delta > 0) & (int32_t)(freeze<Q>(g0) != 0));
+                delta = bsel(sw, -delta, delta) + 1;
+                const int32_t ng0 = -g0;
+                const int32_t ng = reduce_rough<Q>(mul24(ng0, F) + mul24(f0, G));
+                const int32_t n10 = reduce_rough<Q>(mul24(ng0, u00) + mul24(f0, u10));
+                const int32_t n11 = reduce_rough<Q>(mul24(ng0, u01) + mul24(f0, u11));
+                F = bsel(sw, G, F);
+                const int32_t r0a = bsel(sw, u10, u00), r0b = bsel(sw, u11, u01);
+                G = from_next_lane(ng);
+                u00 = from_prev_lane(r0a);
+                u01 = from_prev_lane(r0b);
+                u10 = n10;
+                u11 = n11;
+            }
+            }
+            // 2. U's limbs as reversed Toeplitz bytes (coefficients above n are zero)
             const int32_t ue[4] = {freeze<Q>(u00), freeze<Q>(u01), freeze<Q>(u10), freeze<Q>(u11)};
 #pragma unroll
             for (int k = 0; k < 4; k++) {
@@ -259,27 +267,36 @@ __device__ int recip_jump_wave(const T* Bin, T* OUT, JumpLds<P>& L) {
                 L.T[k][1][kJumpZ0 - lane] = (uint8_t)h;
             }
         }
-        wave_sync();
+        sync();
         // 3. apply U: f', g' shifted down by n (= 48, a multiple of 4, so
         // the shifted outputs stay dword-aligned); v', r' as they are.  The
         // last jump (n = (2p-1) mod 48 steps, any residue mod 4) needs only
         // v' and the constant term of f', which the inner steps hold exactly
-        // (lane 0 of F: its low 64 - n coefficients are f''s).
+        // (lane 0 of F on wave 0: its low 64 - n coefficients are f''s).
         uint8_t(*Hc)[2][S::HLEN] = L.H[cur];
         uint8_t(*Hn)[2][S::HLEN] = L.H[nxt];
         if (jmp + 1 < S::NJUMP) {
-            jump_output<P, M>(L, 0, 1, Hc[0][0], Hc[0][1], Hc[1][0], Hc[1][1], kJumpN, Hn[0][0], Hn[0][1], L.low[0],
-                           nullptr);
-            jump_output<P, M>(L, 2, 3, Hc[0][0], Hc[0][1], Hc[1][0], Hc[1][1], kJumpN, Hn[1][0], Hn[1][1], L.low[1],
-                           nullptr);
-            jump_output<P, M>(L, 0, 1, Hc[2][0], Hc[2][1], Hc[3][0], Hc[3][1], 0, Hn[2][0], Hn[2][1], nullptr, nullptr);
-            jump_output<P, M>(L, 2, 3, Hc[2][0], Hc[2][1], Hc[3][0], Hc[3][1], 0, Hn[3][0], Hn[3][1], nullptr, nullptr);
+            if (0 % nw == wave)
+                jump_output<P, M>(L, 0, 1, Hc[0][0], Hc[0][1], Hc[1][0], Hc[1][1], kJumpN, Hn[0][0], Hn[0][1],
+                                  L.low[0], nullptr);
+            if (1 % nw == wave)
+                jump_output<P, M>(L, 2, 3, Hc[0][0], Hc[0][1], Hc[1][0], Hc[1][1], kJumpN, Hn[1][0], Hn[1][1],
+                                  L.low[1], nullptr);
+            if (2 % nw == wave)
+                jump_output<P, M>(L, 0, 1, Hc[2][0], Hc[2][1], Hc[3][0], Hc[3][1], 0, Hn[2][0], Hn[2][1], nullptr,
+                                  nullptr);
+            if (3 % nw == wave)
+                jump_output<P, M>(L, 2, 3, Hc[2][0], Hc[2][1], Hc[3][0], Hc[3][1], 0, Hn[3][0], Hn[3][1], nullptr,
+                                  nullptr);
         } else {
-            jump_output<P, M>(L, 0, 1, Hc[2][0], Hc[2][1], Hc[3][0], Hc[3][1], 0, Hn[2][0], Hn[2][1], nullptr, L.v);
-            fend = __builtin_amdgcn_readfirstlane(F);
+            if (2 % nw == wave)
+                jump_output<P, M>(L, 0, 1, Hc[2][0], Hc[2][1], Hc[3][0], Hc[3][1], 0, Hn[2][0], Hn[2][1], nullptr,
+                                  L.v);
+            if (wave == 0) fend = __builtin_amdgcn_readfirstlane(F);
         }
-        wave_sync();
+        sync();
     }
+    if (wave != 0) return 0;
     // f0^-1 by Fermat's little theorem (uniform scalar work)
     const int32_t f0 = freeze<Q>(fend);
     int32_t inv = 1, base = f0;
@@ -302,6 +319,12 @@ __device__ int recip_jump_wave(const T* Bin, T* OUT, JumpLds<P>& L) {
     }
     wave_sync();
     return delta == 0;
+}
+
+// One wave alone (see recip_jump_block).
+template <int P, int M = Param<P>::q, typename T = int16_t>
+__device__ int recip_jump_wave(const T* Bin, T* OUT, JumpLds<P>& L) {
+    return recip_jump_block<P, M, T, false>(Bin, OUT, L, 0, 1);
 }
 
 }  // namespace ntrup

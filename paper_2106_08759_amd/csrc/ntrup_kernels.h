@@ -653,19 +653,28 @@ __global__ __launch_bounds__(64) void mulm_kernel(int n, const int16_t* a, const
     mfma_mul<P, BIG>(L.TL, L.TH, L.HL, L.HH, nullptr, nullptr, nullptr, c + (size_t)e * P);
 }
 
-// R/q reciprocals of n rows: by the plain divstep loop (J = false) or by
-// jump divsteps on the matrix cores (J = true).
+// R/q reciprocals of n rows: by the plain divstep loop on one wave
+// (J = false) or by jump divsteps on the matrix cores (J = true), the four
+// products of each jump on the block's 1 to kRecipJumpWaves waves side by
+// side (the host launches four waves per row for up to 512 rows).
+constexpr int kRecipJumpWaves = 4;
 template <int P, bool J>
-__global__ __launch_bounds__(64) void recip_q_kernel(int n, const int16_t* a, int16_t* out, int32_t* ok) {
+__global__ __launch_bounds__(J ? 64 * kRecipJumpWaves : 64) void recip_q_kernel(int n, const int16_t* a,
+                                                                                int16_t* out, int32_t* ok) {
     __shared__ GroupLds<P> L;
     __shared__ typename std::conditional<J, JumpLds<P>, char>::type JL;
     const int e = blockIdx.x;
     if (e >= n) return;
-    load_row16<P>(a + (size_t)e * P, L.Bb);
+    const int wave = (int)(threadIdx.x >> 6);
+    if (wave == 0) load_row16<P>(a + (size_t)e * P, L.Bb);
     __syncthreads();
     int r;
-    if constexpr (J) r = recip_jump_wave<P>(L.Bb, L.Bb, JL);
-    else r = recip_wave<P>(L.Bb, L.Bb, L.Pk);
+    if constexpr (J) {
+        r = recip_jump_block<P, Param<P>::q, int16_t, true>(L.Bb, L.Bb, JL, wave, (int)(blockDim.x >> 6));
+        if (wave != 0) return;
+    } else {
+        r = recip_wave<P>(L.Bb, L.Bb, L.Pk);
+    }
     for (int j = lane_id(); j < P; j += 64) out[(size_t)e * P + j] = L.Bb[j];
     if (lane_id() == 0) ok[e] = r;
 }

@@ -6,7 +6,8 @@
 //   Montgomery group of G keys.
 //   1. prefix (every wave): b_1 = 3f_1, b_i = 3f_i b_{i-1}; rows b_i kept in
 //      HBM, P_w = b_G stays in the wave's LDS;
-//   2. shared reciprocal (wave 0 alone; the others have ended): Q_0 = P_0,
+//   2. shared reciprocal (wave 0; the others have ended, or, with jump
+//      divsteps, compute the products of each jump beside it): Q_0 = P_0,
 //      Q_w = Q_{w-1} P_w, one constant-time divstep reciprocal
 //      T = 1/Q_{W-1}, then for w = W-1..1: 1/P_w = T Q_{w-1} and T <- T P_w;
 //      1/P_0 = T -- the same trick one level up; each 1/P_w goes to HBM.
@@ -465,7 +466,13 @@ __global__ __launch_bounds__(64 * W, (P < 800 ? 2 : 1)) void keygen_prefix_kerne
 
     kg_prefix_chain<P>(args, kw0, gsz, L);
     __syncthreads();
-    if (wave != 0) return;   // no barrier follows: wave 0 finishes alone
+    // with jump divsteps and W = 2 or 4 every wave of the block takes part in
+    // the reciprocal (the four products of each jump side by side);
+    // otherwise wave 0 finishes alone, and no barrier follows.  (With W = 8
+    // the waves kept for the reciprocal would hold registers that the R/3
+    // stage beside this kernel needs: 1.62 against 1.41 ms per batch.)
+    constexpr bool COOP = J && (W == 2 || W == 4);
+    if (!COOP && wave != 0) return;
 
     if (W == 1) {
         int ok;
@@ -475,19 +482,28 @@ __global__ __launch_bounds__(64 * W, (P < 800 ? 2 : 1)) void keygen_prefix_kerne
     } else {
         // Q_{w-1} -> LW[w].Cb, Q_{W-1} -> LW[0].Cb; the Hankel arrays are
         // written whole by build_hankel (zero padding included)
-        kg_copy<P>(LW[0].Bb, LW[1].Cb);
-        for (int w = 1; w < W; w++) {
+        if (wave == 0) {
+            kg_copy<P>(LW[0].Bb, LW[1].Cb);
+            for (int w = 1; w < W; w++) {
+                wave_sync();
+                build_toeplitz<P>(LW[w].Cb, L.TL, L.TH);
+                build_hankel<P>(LW[w].Bb, L.HL, L.HH);
+                wave_sync();
+                mfma_mul<P, true>(L.TL, L.TH, L.HL, L.HH, w + 1 < W ? LW[w + 1].Cb : LW[0].Cb, nullptr, nullptr,
+                                  nullptr);
+            }
             wave_sync();
-            build_toeplitz<P>(LW[w].Cb, L.TL, L.TH);
-            build_hankel<P>(LW[w].Bb, L.HL, L.HH);
-            wave_sync();
-            mfma_mul<P, true>(L.TL, L.TH, L.HL, L.HH, w + 1 < W ? LW[w + 1].Cb : LW[0].Cb, nullptr, nullptr,
-                              nullptr);
         }
-        wave_sync();
         int ok;
-        if constexpr (J) ok = recip_jump_wave<P>(LW[0].Cb, LW[0].Cb, JL);
-        else ok = recip_wave<P>(LW[0].Cb, LW[0].Cb, L.ST);
+        if constexpr (COOP) {
+            __syncthreads();
+            ok = recip_jump_block<P, Param<P>::q, int16_t, true>(LW[0].Cb, LW[0].Cb, JL, wave, W);
+            if (wave != 0) return;
+        } else if constexpr (J) {
+            ok = recip_jump_wave<P>(LW[0].Cb, LW[0].Cb, JL);
+        } else {
+            ok = recip_wave<P>(LW[0].Cb, LW[0].Cb, L.ST);
+        }
         if (!ok && lane_id() == 0) atomicOr(args.err, 2);
         for (int w = W - 1; w >= 1; w--) {
             wave_sync();

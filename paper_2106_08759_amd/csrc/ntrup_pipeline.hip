@@ -130,7 +130,8 @@ int enqueue_keygen(ntrup_ctx* ctx, const ntrup_config& cfg, const Seed& seed, ui
         const dim3 groups(grid_for(n, cfg.group_size));
         hipLaunchKernelGGL((keygen_tree_up_kernel<P>), groups, dim3(64 * kTreeWaves), 0, sp, g, w.trow);
         if (cfg.recip_jump & 1)
-            hipLaunchKernelGGL((keygen_tree_root_kernel<P, true>), groups, dim3(64), 0, sp, g, w.trow);
+            hipLaunchKernelGGL((keygen_tree_root_kernel<P, true>), groups,
+                               dim3(groups.x <= 512 ? 64 * kTreeRootWaves : 64), 0, sp, g, w.trow);
         else
             hipLaunchKernelGGL((keygen_tree_root_kernel<P, false>), groups, dim3(64), 0, sp, g, w.trow);
         hipLaunchKernelGGL((keygen_tree_down_kernel<P>), groups, dim3(64 * kTreeWaves), 0, sp, g, w.trow, w.tinv);
@@ -277,7 +278,9 @@ int op_mul_r3(ntrup_ctx* ctx, const int8_t* a, const int8_t* b, int8_t* c, size_
 
 template <int P>
 int op_recip_rq(ntrup_ctx* ctx, bool jump, const int16_t* a, int16_t* out, int32_t* ok, size_t n, hipStream_t st) {
-    if (jump) hipLaunchKernelGGL((recip_q_kernel<P, true>), dim3((unsigned)n), dim3(64), 0, st, (int)n, a, out, ok);
+    if (jump)
+        hipLaunchKernelGGL((recip_q_kernel<P, true>), dim3((unsigned)n), dim3(n <= 512 ? 64 * kRecipJumpWaves : 64), 0,
+                           st, (int)n, a, out, ok);
     else hipLaunchKernelGGL((recip_q_kernel<P, false>), dim3((unsigned)n), dim3(64), 0, st, (int)n, a, out, ok);
     NTRUP_HIP(ctx, hipGetLastError());
     return 0;

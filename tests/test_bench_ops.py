@@ -56,20 +56,20 @@ def _mf_pairs(p):
     return nt * nks
 
 
-def _jump_mfmas(p):
-    """MFMAs of one jump-divstep reciprocal in R/q: per full jump, four output
-    polynomials of two products each, four MFMAs (limb pairs) per output
-    tile of 256 coefficients; f' and g' (shifted down by 48) need the tiles
-    up to coefficient p + 48, v' and r' those up to p (the compiler drops the
-    MFMAs of a tile none of whose outputs is stored); the last jump computes
-    v' alone."""
-    nt_fg = cdiv(p + 1 + 48, 256)
+def _jump_mfmas(p, n=48):
+    """MFMAs of one jump-divstep reciprocal in R/q (n divsteps per jump): per
+    full jump, four output polynomials of two products each, four MFMAs
+    (limb pairs) per output tile of 256 coefficients; f' and g' (shifted
+    down by n) need the tiles up to coefficient p + n, v' and r' those up to
+    p (the compiler drops the MFMAs of a tile none of whose outputs is
+    stored); the last jump computes v' alone."""
+    nt_fg = cdiv(p + 1 + n, 256)
     nt_vr = cdiv(p + 1, 256)
-    nj = cdiv(2 * p - 1, 48)
+    nj = cdiv(2 * p - 1, n)
     return (nj - 1) * (2 * 2 * nt_fg + 2 * 2 * nt_vr) * 4 + 2 * nt_vr * 4
 
 
-def expected_group_mfmas(p, n, G, W, jump):
+def expected_group_mfmas(p, n, G, W, jump, jump_steps=48):
     """MFMA instructions per launch of the prefix, back-substitution and h
     kernels of the eager split path, counting 3g - 3 R/q products per group of
     g keys (Section 2.2's batchInv): g - 1 prefix products (small x big, two
@@ -80,7 +80,7 @@ def expected_group_mfmas(p, n, G, W, jump):
     groups = [min(G, n - s) for s in range(0, n, G)]
     blocks = cdiv(len(groups), W)
     prefix = sum((g - 1) * 2 * pairs for g in groups) + blocks * (3 * (W - 1) * 4 * pairs
-                                                                   + (_jump_mfmas(p) if jump & 1 else 0))
+                                                                   + (_jump_mfmas(p, jump_steps) if jump & 1 else 0))
     back = sum((g - 1) * 6 * pairs for g in groups)
     return prefix, back, n * 2 * pairs
 
@@ -99,7 +99,7 @@ def test_batchinv_products_per_group_from_counters():
     data = json.load(open(path))
     cfg = data["config"]
     p, n, G, W = cfg["p"], cfg["n_keys"], cfg["group_size"], cfg["inverse_share"]
-    prefix, back, h = expected_group_mfmas(p, n, G, W, cfg["recip_jump"])
+    prefix, back, h = expected_group_mfmas(p, n, G, W, cfg["recip_jump"], cfg.get("jump_steps", 48))
     k = data["kernels"]
     assert k["keygen_prefix_kernel<%d,%d,%s>" % (p, W, "true" if cfg["recip_jump"] & 1 else "false")]["mfma_insts"] \
         == prefix

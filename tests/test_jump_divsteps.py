@@ -190,7 +190,7 @@ def test_jump_equals_plain_divsteps_and_flags_nonunits():
             a = np.asarray(a, dtype=np.int64)
             want = oracle.inv_mod(a, p, q)
             plain = recip_plain(a, p, q)
-            for chunk in (1, 3, 5, 48):
+            for chunk in (1, 3, 5, 48, 60):
                 got = recip_jump(a, p, q, chunk=chunk, low=max(chunk + 1, 16))
                 if want is None:
                     assert got is None and plain is None
@@ -204,4 +204,5 @@ def test_chunk_schedule_covers_2p_minus_1():
     for p in PQ:
         steps = [min(CHUNK, 2 * p - 1 - d) for d in range(0, 2 * p - 1, CHUNK)]
         assert sum(steps) == 2 * p - 1 and all(0 < s <= CHUNK for s in steps)
-        assert CHUNK + 1 <= LOW   # U's 49 coefficients and the truncated f, g fit one wave
+        assert CHUNK + 1 <= LOW and CHUNK % 12 == 0   # U's 49 coefficients and the truncated f, g fit
+        # one wave; whole three-step trips, dword-aligned shifts
