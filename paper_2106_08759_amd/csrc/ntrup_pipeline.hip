@@ -203,11 +203,12 @@ int enqueue_keygen(ntrup_ctx* ctx, const ntrup_config& cfg, const Seed& seed, ui
         gi.err = w.counters + 32;
         gi.g_in = (const int8_t*)w.qrow;
         // the group products' reciprocals: latency-bound (few products), by
-        // jump divsteps on the matrix cores or the bitsliced divsteps at the
-        // most lanes per product
+        // jump divsteps on the matrix cores, one reciprocal shared by
+        // kR3Share groups, or the bitsliced divsteps at the most lanes per
+        // product
         if (cfg.recip_jump & 2)
-            hipLaunchKernelGGL((r3_recip_jump_kernel<P>), dim3(ngroups), dim3(64), 0, sr, (int)ngroups,
-                               (const int8_t*)w.qrow, w.pinv, (uint8_t*)w.lists[1]);
+            hipLaunchKernelGGL((r3_share_recip_kernel<P>), dim3(grid_for(ngroups, kR3Share)), dim3(64 * kR3Share), 0,
+                               sr, (int)ngroups, (const int8_t*)w.qrow, w.pinv, (uint8_t*)w.lists[1]);
         else
             launch_r3<P>(8, ngroups, gi, sr);
         hipLaunchKernelGGL((r3b_back_kernel<P>), dim3(ngroups), dim3(64), 0, sr, b);

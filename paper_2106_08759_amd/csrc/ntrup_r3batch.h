@@ -247,6 +247,90 @@ struct R3bLds {
     __attribute__((aligned(16))) int16_t C[RqShape<P>::JP];   // 1/g_i
 };
 
+// Two products in R/3 sharing the one-limb Toeplitz operand t (bytes TL):
+// c1 = t y1 (folded bytes H1) to dst (int16) and c2 = t y2 (H2) to the
+// Toeplitz bytes TLo (which may be TL itself), in one pass over the K-steps:
+// t's fragments are read once for both.  Wave-local like mfma_mul.
+template <int P>
+__device__ __forceinline__ void r3_mul2(const uint8_t* TL, const uint8_t* H1, const uint8_t* H2, int16_t* dst,
+                                        uint8_t* TLo) {
+    using S = MfShape<P>;
+    constexpr int NT = S::NT;
+    static_assert(NT <= NTRUP_MF_MAXC_SMALL, "one chunk of tiles");
+    const int lane = lane_id();
+    const int rc = lane & 15, g = lane >> 4;
+    const int32_t ap = (int32_t)(int8_t)TL[S::Z0 - (P - 1)];
+    const int32_t bp1 = (int32_t)(int8_t)H1[S::HOFF + P - 1];
+    const int32_t bp2 = (int32_t)(int8_t)H2[S::HOFF + P - 1];
+    ToeplitzFrag nF(TL, S::Z0 - 16 * g - rc);
+    const uint8_t* h1 = H1 + S::HOFF + 16 * (rc - g);
+    const uint8_t* h2 = H2 + S::HOFF + 16 * (rc - g);
+    mf_v4i a1[NT], a2[NT], nB1[NT], nB2[NT];
+#pragma unroll
+    for (int t = 0; t < NT; t++) a1[t] = a2[t] = mf_v4i{0, 0, 0, 0};
+    auto load_step = [&](int k) {
+        nF.load(k);
+#pragma unroll
+        for (int t = 0; t < NT; t++) {
+            const int off = 16 * (16 * t - 4 * k);
+            nB1[t] = *(const mf_v4i*)(h1 + off);
+            nB2[t] = *(const mf_v4i*)(h2 + off);
+        }
+    };
+    load_step(0);
+#pragma unroll
+    for (int k = 0; k < S::NKS; k++) {
+        if (NTRUP_MF_SCHED) __builtin_amdgcn_sched_barrier(0);
+        const ToeplitzFrag F = nF;
+        mf_v4i B1[NT], B2[NT];
+#pragma unroll
+        for (int t = 0; t < NT; t++) {
+            B1[t] = nB1[t];
+            B2[t] = nB2[t];
+        }
+        if (k + 1 < S::NKS) load_step(k + 1);
+        const mf_v4i tf = F.get();
+#pragma unroll
+        for (int t = 0; t < NT; t++) {
+            a1[t] = __builtin_amdgcn_mfma_i32_16x16x64_i8(tf, B1[t], a1[t], 0, 0, 0);
+            a2[t] = __builtin_amdgcn_mfma_i32_16x16x64_i8(tf, B2[t], a2[t], 0, 0, 0);
+        }
+    }
+    // reduce mod 3 (centered), then c_0 -= conv_{p-1} = c_{p-1} - t_{p-1} y_{p-1}
+    int32_t v1[NT][4], v2[NT][4];
+#pragma unroll
+    for (int t = 0; t < NT; t++) {
+        const int i = 256 * t + 16 * rc + 4 * g;
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+            v1[t][e] = (i + e < P) ? freeze<3>(a1[t][e]) : 0;
+            v2[t][e] = (i + e < P) ? freeze<3>(a2[t][e]) : 0;
+        }
+    }
+    const int32_t cp1 = __builtin_amdgcn_readlane(v1[S::TP][0], S::LP);
+    const int32_t cp2 = __builtin_amdgcn_readlane(v2[S::TP][0], S::LP);
+    if (lane == 0) {
+        v1[0][0] = freeze<3>(v1[0][0] - cp1 + ap * bp1);
+        v2[0][0] = freeze<3>(v2[0][0] - cp2 + ap * bp2);
+    }
+    wave_sync();   // TLo may be TL, which the K-steps read
+#pragma unroll
+    for (int t = 0; t < NT; t++) {
+        const int i = 256 * t + 16 * rc + 4 * g;
+        if (i >= P) continue;
+        if (i + 3 < P) {
+            *(uint2*)(dst + i) = make_uint2((uint32_t)(uint16_t)v1[t][0] | ((uint32_t)(uint16_t)v1[t][1] << 16),
+                                            (uint32_t)(uint16_t)v1[t][2] | ((uint32_t)(uint16_t)v1[t][3] << 16));
+        } else {
+            dst[i] = (int16_t)v1[t][0];   // p = 1 mod 4: c_{p-1} alone
+        }
+        uint32_t lo = 0;
+#pragma unroll
+        for (int e = 0; e < 4; e++) lo |= ((uint32_t)v2[t][e] & 0xFFu) << (8 * (3 - e));
+        *(uint32_t*)(TLo + S::Z0 - i - 3) = lo;
+    }
+}
+
 template <int P>
 __device__ __forceinline__ void r3b_load_g(const R3bArgs<P>& a, int key, uint32_t (&m)[KgShape<P>::NU],
                                            uint32_t (&s)[KgShape<P>::NU]) {
@@ -371,15 +455,13 @@ __global__ __launch_bounds__(64) void r3b_back_kernel(R3bArgs<P> a) {
                 w[u] = v;
             }
             put_folded8<P>(w, L.HB);
-            wave_sync();
-            mfma_mul<P, false, false, 3>(L.TL, nullptr, L.HB, nullptr, L.C, nullptr, nullptr, nullptr);
-            // t <- t g_i
+            // and t <- t g_i, in the same pass over the K-steps
             r3b_load_g<P>(a, key, m, s);
 #pragma unroll
             for (int u = 0; u < NU; u++) w[u] = spread4(m[u]) | (spread4(s[u]) * 0xFEu);
             put_folded8<P>(w, L.HG);
             wave_sync();
-            mfma_mul<P, false, false, 3>(L.TL, nullptr, L.HG, nullptr, nullptr, L.TL, nullptr, nullptr);
+            r3_mul2<P>(L.TL, L.HB, L.HG, L.C, L.TL);
         } else {
             for (int j = lane; j < P; j += 64) L.C[j] = (int16_t)(int8_t)L.TL[S::Z0 - j];   // c_1 = t
         }
@@ -399,26 +481,57 @@ __global__ __launch_bounds__(64) void r3b_back_kernel(R3bArgs<P> a) {
     }
 }
 
-// Reciprocals in R/3 of n rows of int8 coefficients in {-1, 0, 1} (the group
-// products) by jump divsteps over F_3 (recip_jump_wave with M = 3: one int8
-// limb per coefficient), one wave per row.  Writes the reciprocal's bitsliced
-// words to ibits ([WN][2][n]: plane 0 the nonzero mask, plane 1 the mask of
-// -1), two words per ballot over 64 coefficients, and ok[i] = 1 iff row i is
-// a unit (0 otherwise; its words are then meaningless).
+// The group products' reciprocals shared by up to kR3Share groups: one
+// workgroup of kR3Share waves per kR3Share consecutive group products
+// P_0 .. P_{k-1} (rows, int8): Q_0 = P_0, Q_w = Q_{w-1} P_w (wave 0), one
+// reciprocal T = 1/Q_{k-1} by jump divsteps over F_3 with the four products of
+// each jump on the waves side by side, then 1/P_w = T Q_{w-1} and T <- T P_w
+// (wave 0) -- Montgomery's trick again, as on the R/q side.  Writes each 1/P_w
+// as bitsliced words to ibits ([WN][2][n]) and ok = 1; if Q_{k-1} is not a
+// unit (some P_w is not) every group of the workgroup gets ok = 0, and their
+// keys take the per-key pass.
+constexpr int kR3Share = 4;
+
 template <int P>
-__global__ __launch_bounds__(64) void r3_recip_jump_kernel(int n, const int8_t* rows, uint32_t* ibits, uint8_t* ok) {
-    constexpr int WN = ceil_div(P, 32);
-    __shared__ JumpLds<P> JL;
-    __shared__ int8_t X[round_up(P, 64)];
-    const int e = blockIdx.x;
-    if (e >= n) return;
+struct R3ShareLds {
+    using S = MfShape<P>;
+    static constexpr int PR = round_up(P, 64);
+    __attribute__((aligned(16))) uint8_t TL[S::TLEN];
+    __attribute__((aligned(16))) uint8_t HB[S::HLEN];
+    __attribute__((aligned(16))) int16_t C[RqShape<P>::JP];
+    __attribute__((aligned(16))) int8_t Q[kR3Share][PR];   // Q_w, then 1/P_w
+    __attribute__((aligned(16))) int8_t X[PR];             // T
+    JumpLds<P> JL;
+};
+
+// dst = x y in R/3 for int8 rows in LDS (one wave): x as the Toeplitz operand,
+// y folded; TL and HB keep their zero padding.
+template <int P>
+__device__ __forceinline__ void r3_share_mul(const int8_t* x, const int8_t* y, int8_t* dst, R3ShareLds<P>& L) {
+    using S = MfShape<P>;
     const int lane = lane_id();
-    for (int i = lane; i < P; i += 64) X[i] = rows[(size_t)e * P + i];
+    for (int m = lane; m < P; m += 64) {
+        L.TL[S::Z0 - m] = (uint8_t)x[m];
+        // folded E: E_m = y_m (1 <= m < p), E_0 = y_0 + y_{p-1},
+        // E_{m-p} = y_m + y_{m-1} (1 <= m < p)
+        L.HB[S::HOFF + m] = (uint8_t)(m == 0 ? (int8_t)(y[0] + y[P - 1]) : y[m]);
+        if (m >= 1) L.HB[S::HOFF + m - P] = (uint8_t)(int8_t)(y[m] + y[m - 1]);
+    }
     wave_sync();
-    const int unit = recip_jump_wave<P, 3, int8_t>(X, X, JL);
+    mfma_mul<P, false, false, 3>(L.TL, nullptr, L.HB, nullptr, L.C, nullptr, nullptr, nullptr);
+    wave_sync();
+    for (int m = lane; m < P; m += 64) dst[m] = (int8_t)L.C[m];
+    wave_sync();
+}
+
+// 1/P_w as bitsliced words (one wave).
+template <int P>
+__device__ __forceinline__ void r3_share_store(const int8_t* x, uint32_t* ibits, int n, int e) {
+    constexpr int WN = ceil_div(P, 32);
+    const int lane = lane_id();
     for (int base = 0; base < P; base += 64) {
         const int i = base + lane;
-        const int c = (i < P) ? (int)X[i] : 0;
+        const int c = (i < P) ? (int)x[i] : 0;
         const uint64_t nz = __ballot(c != 0), neg = __ballot(c < 0);
         if (lane == 0) {
             const int k = base / 32;
@@ -430,7 +543,42 @@ __global__ __launch_bounds__(64) void r3_recip_jump_kernel(int n, const int8_t* 
             }
         }
     }
-    if (lane == 0) ok[e] = unit ? (uint8_t)1 : (uint8_t)0;
+}
+
+template <int P>
+__global__ __launch_bounds__(64 * kR3Share) void r3_share_recip_kernel(int n, const int8_t* rows, uint32_t* ibits,
+                                                                       uint8_t* ok) {
+    using S = MfShape<P>;
+    __shared__ R3ShareLds<P> L;
+    const int wave = (int)(threadIdx.x >> 6), lane = lane_id();
+    const int g0 = (int)blockIdx.x * kR3Share;
+    const int k = min(kR3Share, n - g0);   // groups of this workgroup, >= 1
+    // the Toeplitz and Hankel padding stays zero
+    for (int i = threadIdx.x; i < S::TLEN; i += 64 * kR3Share) L.TL[i] = 0;
+    for (int i = threadIdx.x; i < S::HLEN; i += 64 * kR3Share) L.HB[i] = 0;
+    __syncthreads();
+    if (wave == 0) {
+        // Q_0 = P_0, Q_w = Q_{w-1} P_w; the last one to X
+        for (int m = lane; m < P; m += 64) L.Q[0][m] = rows[(size_t)g0 * P + m];
+        wave_sync();
+        for (int w = 1; w < k; w++) r3_share_mul<P>(L.Q[w - 1], rows + (size_t)(g0 + w) * P, L.Q[w], L);
+        for (int m = lane; m < P; m += 64) L.X[m] = L.Q[k - 1][m];
+    }
+    __syncthreads();
+    const int unit = recip_jump_block<P, 3, int8_t, true>(L.X, L.X, L.JL, wave, kR3Share);
+    if (wave != 0) return;
+    if (!unit) {
+        if (lane < k) ok[g0 + lane] = 0;
+        return;
+    }
+    // 1/P_w = T Q_{w-1}, T <- T P_w (w = k-1 .. 1), 1/P_0 = T
+    for (int w = k - 1; w >= 1; w--) {
+        r3_share_mul<P>(L.X, L.Q[w - 1], L.Q[w], L);                          // 1/P_w over Q_w
+        r3_share_mul<P>(L.X, rows + (size_t)(g0 + w) * P, L.X, L);            // T <- T P_w
+        r3_share_store<P>(L.Q[w], ibits, n, g0 + w);
+    }
+    r3_share_store<P>(L.X, ibits, n, g0);
+    if (lane < k) ok[g0 + lane] = 1;
 }
 
 // c = a b in R/3 (int8 rows, centered), for the kernel tests.
