@@ -119,7 +119,8 @@ def summarize_counters(directory: str, copy_mib: int, workload: str, steps_per_r
     fs, ws = expected / cal_f, expected / cal_w
     kernels = {}
     for key, d in sorted(per.items()):
-        if not key.startswith(("r3_kernel", "keygen_", "sample_short", "group_")) or "fetch" not in d or "write" not in d:
+        if not key.startswith(("r3_kernel", "r3b_", "r3_share", "keygen_", "sample_short", "group_", "kem_")) \
+                or "fetch" not in d or "write" not in d:
             continue
         f = sum(d["fetch"]) / len(d["fetch"])
         w = sum(d["write"]) / len(d["write"])

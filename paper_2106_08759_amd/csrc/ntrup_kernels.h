@@ -57,6 +57,33 @@ __device__ __forceinline__ uint32_t med3_u32(uint32_t a, uint32_t b, uint32_t c)
 // elements [EPL*l, EPL*l + EPL)), ascending.  Branch-free: every
 // compare-exchange half is a med3 against 0 (keep the smaller) or ~0 (keep
 // the larger).
+// The value of lane lane ^ lj (lj a power of two below 64), by DPP and the
+// gfx950 row-swap permutes instead of ds_bpermute: quad permutes for 1 and 2,
+// row shifts for 4 (row_shl:4 gives lane i+4, row_shr:4 lane i-4), a row
+// rotate for 8, v_permlane16_swap / v_permlane32_swap for 16 / 32 (with both
+// operands x, the first result holds the lower row's values at the upper
+// row's lanes and the second the upper row's values at the lower row's).
+__device__ __forceinline__ uint32_t lane_xor(uint32_t x, int lj, int lane) {
+    switch (lj) {
+        case 1: return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0xB1, 0xF, 0xF, true);   // quad [1,0,3,2]
+        case 2: return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x4E, 0xF, 0xF, true);   // quad [2,3,0,1]
+        case 4: {
+            const uint32_t up = (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x104, 0xF, 0xF, true);   // row_shl:4
+            const uint32_t dn = (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x114, 0xF, 0xF, true);   // row_shr:4
+            return (lane & 4) ? dn : up;
+        }
+        case 8: return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x128, 0xF, 0xF, true);  // row_ror:8
+        case 16: {
+            const auto r = __builtin_amdgcn_permlane16_swap(x, x, false, false);
+            return (lane & 16) ? (uint32_t)r[0] : (uint32_t)r[1];
+        }
+        default: {
+            const auto r = __builtin_amdgcn_permlane32_swap(x, x, false, false);
+            return (lane & 32) ? (uint32_t)r[0] : (uint32_t)r[1];
+        }
+    }
+}
+
 template <int EPL>
 __device__ __forceinline__ void bitonic_sort_wave(uint32_t (&L)[EPL], int lane) {
     constexpr int NS = 64 * EPL;
@@ -72,7 +99,7 @@ __device__ __forceinline__ void bitonic_sort_wave(uint32_t (&L)[EPL], int lane) 
                 const uint32_t c = keep_min ? 0u : 0xFFFFFFFFu;
 #pragma unroll
                 for (int e = 0; e < EPL; e++) {
-                    const uint32_t o = (uint32_t)__shfl_xor((int)L[e], lj);
+                    const uint32_t o = lane_xor(L[e], lj, lane);
                     L[e] = med3_u32(L[e], o, c);
                 }
             } else {
