@@ -272,7 +272,8 @@ def cpu_baseline(p: int, seconds: float, check: list) -> tuple:
 
 
 CALIB_KINDS = {0: "arx (add, xor, rotate)", 1: "v_add_u32", 2: "v_bitop3_b32", 3: "v_alignbit_b32", 4: "v_mad_u32_u24",
-               5: "v_perm_b32", 6: "v_xor_b32 + v_add_u32"}
+               5: "v_perm_b32", 6: "v_xor_b32 + v_add_u32", 7: "v_med3_u32", 8: "v_min_u32 + v_max_u32",
+               9: "v_mov_b32_dpp + v_xor_b32"}
 
 
 def calib_valu(iters: int = 20000, reps: int = 5) -> dict:

@@ -11,6 +11,9 @@
 //   4 mad24   v_mad_u32_u24 (a = a * b + c on 24-bit operands)
 //   5 perm    v_perm_b32 byte permutes of two registers (a = perm(a, b, s))
 //   6 xor     v_xor_b32 and v_add_u32 (a ^= b'; b ^= a + 1)
+//   7 med3    v_med3_u32 of three registers of different chains
+//   8 minmax  v_min_u32 and v_max_u32 of registers of different chains
+//   9 dpp     v_mov_b32 with a DPP row rotation, then v_xor_b32
 // Timed over grids of 1, 2, 4 or 8 waves per SIMD.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -25,6 +28,12 @@ __device__ __forceinline__ uint32_t rotl(uint32_t x) {
 __device__ __forceinline__ uint32_t maj3(uint32_t a, uint32_t b, uint32_t c) {
     uint32_t r;
     asm volatile("v_bitop3_b32 %0, %1, %2, %3 bitop3:0xe8" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+    return r;
+}
+
+__device__ __forceinline__ uint32_t med3u(uint32_t a, uint32_t b, uint32_t c) {
+    uint32_t r;
+    asm("v_med3_u32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
     return r;
 }
 
@@ -58,9 +67,18 @@ __global__ __launch_bounds__(64) void valu_chain_kernel(uint32_t* out, int iters
             } else if constexpr (KIND == 5) {
                 a[k] = __builtin_amdgcn_perm(a[k], b[k], 0x05040302u + 0x01010101u * (k & 1));
                 b[k] = __builtin_amdgcn_perm(b[k], a[k], 0x02010007u);
-            } else {
+            } else if constexpr (KIND == 6) {
                 a[k] ^= b[(k + 1) & 7];
                 b[k] ^= a[k] + 1u;
+            } else if constexpr (KIND == 7) {
+                a[k] = med3u(a[k], b[k], a[(k + 1) & 7]);
+                b[k] = med3u(b[k], a[k], b[(k + 3) & 7]);
+            } else if constexpr (KIND == 8) {
+                a[k] = min(a[k], b[(k + 1) & 7]);
+                b[k] = max(b[k], a[(k + 2) & 7]);
+            } else {
+                a[k] = (uint32_t)__builtin_amdgcn_mov_dpp((int)b[k], 0x128, 0xF, 0xF, true);
+                b[k] ^= a[k];
             }
         }
     }
@@ -74,10 +92,10 @@ __global__ __launch_bounds__(64) void valu_chain_kernel(uint32_t* out, int iters
 
 extern "C" {
 
-// Launch probe `kind` (0..4) over `blocks` one-wave blocks of `iters` steps
+// Launch probe `kind` (0..9) over `blocks` one-wave blocks of `iters` steps
 // each on `stream`; out: device, blocks * 64 words.  Returns a hipError_t.
 int calib_valu(int kind, int blocks, int iters, uint32_t* out, void* stream) {
-    if (blocks <= 0 || iters <= 0 || !out || kind < 0 || kind > 6) return (int)hipErrorInvalidValue;
+    if (blocks <= 0 || iters <= 0 || !out || kind < 0 || kind > 9) return (int)hipErrorInvalidValue;
     const hipStream_t st = (hipStream_t)stream;
     switch (kind) {
         case 0: hipLaunchKernelGGL(valu_chain_kernel<0>, dim3((unsigned)blocks), dim3(64), 0, st, out, iters); break;
@@ -86,7 +104,10 @@ int calib_valu(int kind, int blocks, int iters, uint32_t* out, void* stream) {
         case 3: hipLaunchKernelGGL(valu_chain_kernel<3>, dim3((unsigned)blocks), dim3(64), 0, st, out, iters); break;
         case 4: hipLaunchKernelGGL(valu_chain_kernel<4>, dim3((unsigned)blocks), dim3(64), 0, st, out, iters); break;
         case 5: hipLaunchKernelGGL(valu_chain_kernel<5>, dim3((unsigned)blocks), dim3(64), 0, st, out, iters); break;
-        default: hipLaunchKernelGGL(valu_chain_kernel<6>, dim3((unsigned)blocks), dim3(64), 0, st, out, iters); break;
+        case 6: hipLaunchKernelGGL(valu_chain_kernel<6>, dim3((unsigned)blocks), dim3(64), 0, st, out, iters); break;
+        case 7: hipLaunchKernelGGL(valu_chain_kernel<7>, dim3((unsigned)blocks), dim3(64), 0, st, out, iters); break;
+        case 8: hipLaunchKernelGGL(valu_chain_kernel<8>, dim3((unsigned)blocks), dim3(64), 0, st, out, iters); break;
+        default: hipLaunchKernelGGL(valu_chain_kernel<9>, dim3((unsigned)blocks), dim3(64), 0, st, out, iters); break;
     }
     return (int)hipGetLastError();
 }

@@ -53,16 +53,30 @@ __device__ __forceinline__ uint32_t med3_u32(uint32_t a, uint32_t b, uint32_t c)
     return r;
 }
 
-// Bitonic sort of 64*EPL words held blocked across the wave (lane l holds
-// elements [EPL*l, EPL*l + EPL)), ascending.  Branch-free: every
-// compare-exchange half is a med3 against 0 (keep the smaller) or ~0 (keep
-// the larger).
-// The value of lane lane ^ lj (lj a power of two below 64), by DPP and the
-// gfx950 row-swap permutes instead of ds_bpermute: quad permutes for 1 and 2,
-// row shifts for 4 (row_shl:4 gives lane i+4, row_shr:4 lane i-4), a row
-// rotate for 8, v_permlane16_swap / v_permlane32_swap for 16 / 32 (with both
-// operands x, the first result holds the lower row's values at the upper
-// row's lanes and the second the upper row's values at the lower row's).
+// Bitonic sort of 64*EPL words held across the wave, ascending.  Branch-free:
+// every compare-exchange half is a med3 against 0 (keep the smaller) or ~0
+// (keep the larger).  A slot's rank in the network is e + EPL sort_lane(lane)
+// (slot e of lane `lane`): the network's lane bits are a permutation of the
+// physical ones, chosen so that the lane exchange that costs the most (lane
+// ^ 4: two row shifts and a select) carries the network's highest lane bit,
+// which one stage uses, and every other lane bit costs one instruction per
+// word and stage:
+//   network bit 0, 1, 2  <->  lane ^ 1, ^ 2 (quad permutes), ^ 8 (row rotate):
+//     the partner's word by one DPP move, then one med3;
+//   network bit 3, 4     <->  lane ^ 16, ^ 32: v_permlane16_swap /
+//     v_permlane32_swap of two slots (e, e+1) exchanges the rows, so that
+//     each lane holds both words of one pair (the lower row's in the first
+//     result, the upper row's in the second, whichever slot they came from),
+//     two med3, and the same swap again (an involution) puts them back;
+//   network bit 5        <->  lane ^ 4.
+// The input order is free (any order sorts); ranks are used on output.
+__device__ __forceinline__ int sort_lane(int lane) {
+    return (lane & 3) | (((lane >> 3) & 1) << 2) | (((lane >> 4) & 3) << 3) | (((lane >> 2) & 1) << 5);
+}
+
+// The value of lane lane ^ lj, lj in {1, 2, 4, 8}, by DPP: quad permutes for
+// 1 and 2, row shifts for 4 (row_shl:4 gives lane i+4, row_shr:4 lane i-4),
+// a row rotate for 8.
 __device__ __forceinline__ uint32_t lane_xor(uint32_t x, int lj, int lane) {
     switch (lj) {
         case 1: return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0xB1, 0xF, 0xF, true);   // quad [1,0,3,2]
@@ -72,42 +86,69 @@ __device__ __forceinline__ uint32_t lane_xor(uint32_t x, int lj, int lane) {
             const uint32_t dn = (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x114, 0xF, 0xF, true);   // row_shr:4
             return (lane & 4) ? dn : up;
         }
-        case 8: return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x128, 0xF, 0xF, true);  // row_ror:8
-        case 16: {
-            const auto r = __builtin_amdgcn_permlane16_swap(x, x, false, false);
-            return (lane & 16) ? (uint32_t)r[0] : (uint32_t)r[1];
-        }
-        default: {
-            const auto r = __builtin_amdgcn_permlane32_swap(x, x, false, false);
-            return (lane & 32) ? (uint32_t)r[0] : (uint32_t)r[1];
-        }
+        default: return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x128, 0xF, 0xF, true);  // row_rotate:8
+    }
+}
+
+// Rows exchanged between two slots: v_permlane16_swap (R = 16) or
+// v_permlane32_swap (R = 32) of (a, b), in place.
+template <int R>
+__device__ __forceinline__ void row_swap(uint32_t& a, uint32_t& b) {
+    if constexpr (R == 16) {
+        const auto r = __builtin_amdgcn_permlane16_swap(a, b, false, false);
+        a = (uint32_t)r[0];
+        b = (uint32_t)r[1];
+    } else {
+        const auto r = __builtin_amdgcn_permlane32_swap(a, b, false, false);
+        a = (uint32_t)r[0];
+        b = (uint32_t)r[1];
     }
 }
 
 template <int EPL>
 __device__ __forceinline__ void bitonic_sort_wave(uint32_t (&L)[EPL], int lane) {
     constexpr int NS = 64 * EPL;
+    static_assert(EPL % 2 == 0, "row swaps pair the slots");
+    const int i0 = sort_lane(lane) * EPL;   // rank of slot 0
 #pragma unroll
     for (int k = 2; k <= NS; k <<= 1) {
 #pragma unroll
         for (int j = k >> 1; j > 0; j >>= 1) {
             if (j >= EPL) {
-                // partner in lane ^ (j / EPL), same slot; the side (lower or
-                // upper of the pair) and the direction depend on the lane only
-                const int lj = j / EPL, i0 = lane * EPL;
-                const bool keep_min = ((i0 & j) == 0) == ((i0 & k) == 0);
-                const uint32_t c = keep_min ? 0u : 0xFFFFFFFFu;
+                // network lane bit jb; the direction depends on the lane only
+                const int jb = __builtin_ctz(j / EPL);
+                const uint32_t c = ((i0 & k) == 0) ? 0u : 0xFFFFFFFFu;   // 0: ascending pair
+                if (jb == 3 || jb == 4) {
 #pragma unroll
-                for (int e = 0; e < EPL; e++) {
-                    const uint32_t o = lane_xor(L[e], lj, lane);
-                    L[e] = med3_u32(L[e], o, c);
+                    for (int e = 0; e < EPL; e += 2) {
+                        uint32_t lo = L[e], hi = L[e + 1];
+                        if (jb == 3) row_swap<16>(lo, hi);
+                        else row_swap<32>(lo, hi);
+                        const uint32_t a = med3_u32(lo, hi, c), b = med3_u32(lo, hi, ~c);
+                        lo = a;
+                        hi = b;
+                        if (jb == 3) row_swap<16>(lo, hi);
+                        else row_swap<32>(lo, hi);
+                        L[e] = lo;
+                        L[e + 1] = hi;
+                    }
+                } else {
+                    // partner in lane ^ lj, same slot: keep the smaller iff
+                    // this lane is the lower side of an ascending pair
+                    const int lj = jb == 5 ? 4 : (jb == 2 ? 8 : 1 << jb);
+                    const uint32_t cc = ((i0 & j) == 0) ? c : ~c;
+#pragma unroll
+                    for (int e = 0; e < EPL; e++) {
+                        const uint32_t o = lane_xor(L[e], lj, lane);
+                        L[e] = med3_u32(L[e], o, cc);
+                    }
                 }
             } else {
 #pragma unroll
                 for (int e = 0; e < EPL; e++) {
                     if ((e & j) == 0) {
                         const int e2 = e | j;
-                        const bool up = ((lane * EPL + e) & k) == 0;
+                        const bool up = ((i0 + e) & k) == 0;
                         const uint32_t c = up ? 0u : 0xFFFFFFFFu;
                         const uint32_t a = L[e], b = L[e2];
                         L[e] = med3_u32(a, b, c);
@@ -140,9 +181,10 @@ __device__ __forceinline__ void sample_short_key(const Seed& seed, uint64_t inde
         L[e] = (i < P) ? ((L[e] & ~3u) | v) : 0xFFFFFFFFu;
     }
     bitonic_sort_wave<EPL>(L, lane);
+    const int i0 = sort_lane(lane) * EPL;
 #pragma unroll
     for (int e = 0; e < EPL; e++) {
-        const int i = lane * EPL + e;
+        const int i = i0 + e;
         if (i < P) row[i] = (int8_t)((int)(L[e] & 3u) - 1);
     }
 }
@@ -155,7 +197,9 @@ __device__ __forceinline__ void sample_short_key(const Seed& seed, uint64_t inde
 // p = 761) skip -- and pass the words through LDS to the sorting wave of
 // their key.  LDS rows are EPL + 1 words per lane slot, so that both the
 // writes (one ChaCha block per thread) and the reads (one slot per lane) hit
-// 64 different banks.
+// 64 different banks.  The sorted coefficients go back through LDS, so that
+// the four keys' rows (one contiguous range of 4p bytes) are stored as whole
+// words by all threads instead of one scattered byte per lane and slot.
 template <int P>
 __global__ __launch_bounds__(256) void sample_short_kernel(Seed seed, uint64_t first_index, int n, int stream,
                                                            int8_t* __restrict__ f_rows) {
@@ -165,7 +209,13 @@ __global__ __launch_bounds__(256) void sample_short_kernel(Seed seed, uint64_t f
     constexpr int NB = ceil_div(P, 16);         // ChaCha20 blocks per key
     constexpr int KPB = 4;                      // keys per workgroup (one wave each)
     static_assert(16 * NB <= 64 * EPL && EPL % 16 == 0, "a key's words fit its sorting network");
-    __shared__ uint32_t words[KPB][64 * SL];
+    __shared__ __attribute__((aligned(16))) uint32_t words[KPB][64 * SL];
+    // then the sorted rows of the workgroup's keys (stride RS bytes, over the
+    // words once every wave has read its own), written out as the one
+    // contiguous byte range [key0 P, (key0 + KPB) P) of f_rows
+    constexpr int RS = 64 * EPL;
+    static_assert(KPB * RS <= (int)sizeof(words), "the rows fit over the words");
+    uint8_t (*rows)[RS] = (uint8_t (*)[RS])&words[0][0];
     const int key0 = blockIdx.x * KPB;
     const int tid = threadIdx.x;
     for (int b = tid; b < KPB * NB; b += 64 * KPB) {
@@ -182,7 +232,6 @@ __global__ __launch_bounds__(256) void sample_short_kernel(Seed seed, uint64_t f
     __syncthreads();
     const int wave = tid >> 6, lane = tid & 63;
     const int key = key0 + wave;
-    if (key >= n) return;  // whole wave
     uint32_t L[EPL];
 #pragma unroll
     for (int e = 0; e < EPL; e++) {
@@ -191,12 +240,48 @@ __global__ __launch_bounds__(256) void sample_short_kernel(Seed seed, uint64_t f
         const uint32_t v = (i < W) ? 2u * (x & 1u) : 1u;
         L[e] = (i < P) ? ((x & ~3u) | v) : 0xFFFFFFFFu;
     }
-    bitonic_sort_wave<EPL>(L, lane);
-    int8_t* row = f_rows + (size_t)key * P;
+    __syncthreads();
+    if (key < n) {  // whole wave
+        bitonic_sort_wave<EPL>(L, lane);
+        // coefficient L & 3 - 1 as a byte, four to a word, ranks i0 .. i0+EPL-1
+        const int i0 = sort_lane(lane) * EPL;
 #pragma unroll
-    for (int e = 0; e < EPL; e++) {
-        const int i = lane * EPL + e;
-        if (i < P) row[i] = (int8_t)((int)(L[e] & 3u) - 1);
+        for (int q = 0; q < EPL / 16; q++) {
+            uint32_t w4[4];
+#pragma unroll
+            for (int d = 0; d < 4; d++) {
+                uint32_t x = 0;
+#pragma unroll
+                for (int t = 0; t < 4; t++) x |= (((L[16 * q + 4 * d + t] & 3u) - 1u) & 0xFFu) << (8 * t);
+                w4[d] = x;
+            }
+            *(uint4*)&rows[wave][i0 + 16 * q] = make_uint4(w4[0], w4[1], w4[2], w4[3]);
+        }
+    }
+    __syncthreads();
+    // P KPB is a multiple of 4 (P = 1 mod 4, KPB = 4): on a word-aligned
+    // f_rows the range starts and ends on a word.  Words past the last key's
+    // end (a partial last workgroup) and every word of an unaligned f_rows
+    // are written byte by byte.
+    constexpr int NW = P * KPB / 4;
+    static_assert(P * KPB % 4 == 0, "the workgroup's byte range is whole words");
+    const int live = min(KPB, n - key0) * P;   // bytes of this workgroup's keys
+    const bool aligned = ((uintptr_t)f_rows & 3u) == 0;
+    uint32_t* out = (uint32_t*)(f_rows + (size_t)key0 * P);
+    for (int d = tid; d < NW; d += 64 * KPB) {
+        uint32_t x = 0;
+#pragma unroll
+        for (int t = 0; t < 4; t++) {
+            const int b = 4 * d + t, k = b / P;
+            x |= (uint32_t)rows[k][b - k * P] << (8 * t);
+        }
+        if (aligned && 4 * d + 4 <= live) {
+            out[d] = x;
+        } else {
+#pragma unroll
+            for (int t = 0; t < 4; t++)
+                if (4 * d + t < live) ((uint8_t*)out)[4 * d + t] = (uint8_t)(x >> (8 * t));
+        }
     }
 }
 

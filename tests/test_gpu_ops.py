@@ -49,6 +49,28 @@ def test_sample_matches_oracle(ctx, p):
             assert np.array_equal(g[i], oracle.sample_small(wl.SEED, 1000 + i, p, attempt)), (p, i, attempt)
 
 
+@pytest.mark.parametrize("p", [761, 1277])
+def test_sample_short_unaligned_rows(ctx, p):
+    """f rows at an odd device address (encapsulation's r may be any int8
+    array): the sampler's word stores fall back to bytes, the rows equal the
+    oracle's and the bytes around them are untouched."""
+    import torch
+    import paper_2106_08759_amd as nk
+    _, q, w = wl.PQW[p]
+    n, off = 13, 3
+    buf = torch.full((n * p + 8,), 0x55, dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    rc = nk.lib().ntrup_op_sample(ctx._h, p, nk._seed_bytes(wl.SEED), 7, n, 0, buf.data_ptr() + off, None,
+                                  torch.cuda.current_stream().cuda_stream)
+    assert rc == 0
+    torch.cuda.synchronize()
+    b = host(buf)
+    assert (b[:off] == 0x55).all() and (b[off + n * p:] == 0x55).all()
+    f = b[off:off + n * p].view(np.int8).reshape(n, p)
+    for i in range(n):
+        assert np.array_equal(f[i], oracle.sample_short(wl.SEED, 7 + i, p, w)), (p, i)
+
+
 ENGINES = [0, 1]  # vector dot2 Toeplitz, int8 matrix cores
 
 
