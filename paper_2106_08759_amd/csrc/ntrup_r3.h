@@ -32,7 +32,8 @@ namespace ntrup {
 
 template <int P, int LPK>
 struct R3Shape {
-    static_assert(LPK == 1 || LPK == 2 || LPK == 4 || LPK == 8, "1, 2, 4 or 8 lanes per key");
+    static_assert(LPK == 1 || LPK == 2 || LPK == 4 || LPK == 8 || LPK == 16 || LPK == 32,
+                  "1, 2, 4, 8, 16 or 32 lanes per key");
     static constexpr int W = ceil_div(P + 1, 32);   // words holding p+1 coefficients
     static constexpr int W2 = ceil_div(W, LPK);     // words per lane
     static constexpr int WT = W2 * LPK;             // padded words per polynomial
@@ -44,27 +45,38 @@ struct R3Shape {
     static_assert(D >= 1, "room for x^p");
 };
 
-// Lane-group helpers.  A key owns LPK consecutive lanes (LPK divides 16, so a
-// group never straddles a DPP row); group_first broadcasts the value of the
-// group's first lane with DPP moves: a quad permute for LPK <= 4; for LPK = 8
-// the quad broadcast followed by row_shr:4 written into banks 1 and 3 only
-// (lanes 4-7 and 12-15 of each row take the broadcast of the quad below,
-// lanes 0-3 and 8-11 keep their own).
+// Lane-group helpers.  A key owns LPK consecutive lanes (a group of up to 16
+// lies in one DPP row of 16 lanes, a group of 32 in two); group_first
+// broadcasts the value of the group's first lane with DPP moves: a quad
+// permute for LPK <= 4; for LPK = 8 the quad broadcast followed by row_shr:4
+// written into banks 1 and 3 only (lanes 4-7 and 12-15 of each row take the
+// broadcast of the quad below, lanes 0-3 and 8-11 keep their own); for 16,
+// row_newbcast:0 (lane 0 of each row to its row); for 32, that followed by
+// row_bcast:15 written into rows 1 and 3 only (each takes lane 15 of the row
+// below, which by then holds that row's lane 0).
 template <int LPK>
 __device__ __forceinline__ uint32_t group_first(uint32_t x) {
     if (LPK == 1) return x;
     if (LPK == 2) return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0xA0, 0xF, 0xF, true);  // [0,0,2,2]
+    if (LPK >= 16) {
+        const int r = __builtin_amdgcn_mov_dpp((int)x, 0x150, 0xF, 0xF, true);             // row_newbcast:0
+        if (LPK == 16) return (uint32_t)r;
+        return (uint32_t)__builtin_amdgcn_update_dpp(r, r, 0x142, 0xA, 0xF, false);        // row_bcast:15
+    }
     const int q = __builtin_amdgcn_mov_dpp((int)x, 0x00, 0xF, 0xF, true);                  // [0,0,0,0]
     if (LPK == 4) return (uint32_t)q;
     return (uint32_t)__builtin_amdgcn_update_dpp(q, q, 0x114, 0xF, 0xA, false);             // row_shr:4
 }
-// lane i reads lane i+1 / lane i-1 within its row of 16 (row_shl:1 / row_shr:1);
-// a pair never straddles a row, and the caller masks the lane that must read 0
-__device__ __forceinline__ uint32_t row_next(uint32_t x) {
-    return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x101, 0xF, 0xF, true);
+// lane i reads lane i+1 / lane i-1: within its row of 16 (row_shl:1 /
+// row_shr:1) when a group lies in one row, across the wave (wave_shl:1 /
+// wave_shr:1) for groups of 32; the caller masks the lane that must read 0
+template <int LPK>
+__device__ __forceinline__ uint32_t group_next(uint32_t x) {
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, LPK == 32 ? 0x130 : 0x101, 0xF, 0xF, true);
 }
-__device__ __forceinline__ uint32_t row_prev(uint32_t x) {
-    return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x111, 0xF, 0xF, true);
+template <int LPK>
+__device__ __forceinline__ uint32_t group_prev(uint32_t x) {
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, LPK == 32 ? 0x138 : 0x111, 0xF, 0xF, true);
 }
 
 // Three-input boolean functions on gfx950 (v_bitop3_b32): the 8-bit table is
@@ -261,11 +273,11 @@ __device__ __forceinline__ int r3_divsteps(typename R3Shape<P, LPK>::Words& gm,
         uint32_t gin_m = 0, gin_s = 0, vin_m = 0, vin_s = 0;
         if (LPK > 1) {
             // the next lane's word 0 feeds this lane's top word (0 for the top lane)
-            gin_m = row_next(gm[0]) & ~last;
-            gin_s = row_next(gs[0]) & ~last;
+            gin_m = group_next<LPK>(gm[0]) & ~last;
+            gin_s = group_next<LPK>(gs[0]) & ~last;
             // the previous lane's top word feeds this lane's word 0 (0 for the bottom lane)
-            vin_m = row_prev(vm[W2 - 1]) & ~first;
-            vin_s = row_prev(vs[W2 - 1]) & ~first;
+            vin_m = group_prev<LPK>(vm[W2 - 1]) & ~first;
+            vin_s = group_prev<LPK>(vs[W2 - 1]) & ~first;
         }
 #pragma unroll
         for (int k = 0; k < W2 - 1; k++) {
