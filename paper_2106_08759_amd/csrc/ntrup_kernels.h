@@ -216,6 +216,9 @@ __global__ __launch_bounds__(256) void sample_short_kernel(Seed seed, uint64_t f
     constexpr int RS = 64 * EPL;
     static_assert(KPB * RS <= (int)sizeof(words), "the rows fit over the words");
     uint8_t (*rows)[RS] = (uint8_t (*)[RS])&words[0][0];
+    // KeyGen's f heads the launch stream's chain of kernels while the R/3
+    // stage's sampler runs beside it: its waves take issue priority
+    __builtin_amdgcn_s_setprio(2);
     const int key0 = blockIdx.x * KPB;
     const int tid = threadIdx.x;
     for (int b = tid; b < KPB * NB; b += 64 * KPB) {
