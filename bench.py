@@ -63,7 +63,8 @@ def stored_counter(kernel: str, field: str = "bytes_per_launch"):
     """A per-launch figure of `kernel` from the committed counter summary:
     bytes_per_launch (FETCH_SIZE and WRITE_SIZE scaled by a plain-copy
     calibration) or valu_insts (SQ_INSTS_VALU, wave instructions); None when
-    there is none or the kernel sources changed since it was taken."""
+    there is none or the kernel sources changed since it was taken.  A stage
+    of several kernels in a row ('a+b') sums theirs."""
     try:
         with open(TRAFFIC_FILE) as fh:
             data = json.load(fh)
@@ -71,8 +72,13 @@ def stored_counter(kernel: str, field: str = "bytes_per_launch"):
         return None
     if data.get("sources_sha256") != sources_digest():
         return None
-    entry = data.get("kernels", {}).get(kernel)
-    return None if entry is None else entry.get(field)
+    total = 0
+    for part in kernel.split("+"):
+        entry = data.get("kernels", {}).get(part)
+        if entry is None or entry.get(field) is None:
+            return None
+        total += entry[field]
+    return total
 
 
 def stored_traffic(kernel: str):
@@ -483,8 +489,13 @@ def main():
         dom = max(crit, key=lambda k: avg[k])
     achieved = ops[dom] / (avg[dom] / 1e3)
     jump = "true" if cfg["recip_jump"] & 1 else "false"
+    # with the side stream, the launch stream's stage between sampling and
+    # the join is the prefix kernel followed by the back-substitution kernel
+    # (its time and its products are both kernels'); otherwise the prefix
+    # kernel alone
+    prefix_name = "keygen_prefix_kernel<%d,%d,%s>" % (p, cfg["inverse_share"], jump)
     kernel_names = {"group_prefix": ("keygen_tree_{up,root,down}_kernel<%d> (root jump %s)" % (p, jump) if tree else
-                                     "keygen_prefix_kernel<%d,%d,%s>" % (p, cfg["inverse_share"], jump)),
+                                     prefix_name + "+keygen_cinv_kernel<%d>" % p if split else prefix_name),
                     "group_back": ("keygen_h_kernel<%d>" if split or tree else "keygen_back_kernel<%d>") % p,
                     "r3_main": "r3_kernel<%d,%d>" % (p, cfg["lanes_per_key"]),
                     "sample_short": "sample_short_kernel<%d>" % p,
@@ -559,9 +570,12 @@ def main():
         # the same jobs as one launch of the persistent fused kernel
         saved = {q_: ctx.get_config(q_) for q_ in (653, 761, 857, 1277)}
         for q_ in saved:
+            # every knob set here: the graph-mode tuning above leaves per-p
+            # retry settings (up to 8 draws side by side at 8 lanes each) that
+            # this form does not want
             ctx.set_config(q_, persistent=1, r3_batch=0, group_form=0, product_engine=1, lanes_per_key=2,
-                           group_size=32,
-                           inverse_share=2, use_graph=1)
+                           group_size=32, inverse_share=2, use_graph=1, retry_passes=1, retry_lanes_per_key=8,
+                           retry_parallel_attempts=4)
         ctx.batch_keygen_mixed(wl.SEED, jobs, check=True)
         torch.cuda.synchronize()
         e0.record()
@@ -572,7 +586,8 @@ def main():
         assert ctx.status() == 0
         pm_ms = e0.elapsed_time(e1) / 5
         extras["mixed_4x16384_persistent"] = {"keys_per_s": round(4 * 16384 / pm_ms * 1e3, 1), "ms": round(pm_ms, 3),
-                                              "launch": "one persistent fused kernel (G=32, W=2, 2 lanes per key)"}
+                                              "launch": "one persistent fused kernel (G=32, W=2, 2 lanes per key, "
+                                                        "retries 8 lanes x 4 draws)"}
         for q_, c_ in saved.items():
             ctx.set_config(q_, **c_)
         # this workload (N keys of p) in the persistent fused form, at the
