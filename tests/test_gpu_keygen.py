@@ -235,11 +235,18 @@ def test_eager_split_back_substitution(ctx, p):
         ctx.set_config(p, **base)
 
 
-# The configurations bench.py times at N = 65536 (the autotuner picks among
-# them): the per-key R/3 form with the eager split back-substitution
-# (G = 128, W = 1, one lane per key) and the batched-R/3 form (G = 32, W = 4
-# or 8).
+# Configurations bench.py times at N = 65536 (the autotuner picks among
+# them): the batched-R/3 form with the R/q group reciprocals by jump divsteps
+# (G = 64, W = 2 or 4: the tuned picks on MI355X), the same at G = 32, and the
+# per-key R/3 form with the eager split back-substitution (G = 128, W = 1,
+# one lane per key).
 TIMED_CONFIGS = [
+    dict(group_size=64, inverse_share=2, lanes_per_key=1, retry_passes=1, retry_lanes_per_key=8,
+         retry_parallel_attempts=4, use_graph=0, persistent=0, r3_batch=1, product_engine=1, recip_jump=1,
+         group_form=0),
+    dict(group_size=64, inverse_share=4, lanes_per_key=1, retry_passes=1, retry_lanes_per_key=8,
+         retry_parallel_attempts=4, use_graph=0, persistent=0, r3_batch=1, product_engine=1, recip_jump=1,
+         group_form=0),
     dict(group_size=128, inverse_share=1, lanes_per_key=1, retry_passes=1, retry_lanes_per_key=8,
          retry_parallel_attempts=4, use_graph=0, persistent=0, r3_batch=0, product_engine=1),
     dict(group_size=32, inverse_share=4, lanes_per_key=1, retry_passes=1, retry_lanes_per_key=8,
@@ -262,7 +269,8 @@ def graph_g32_65536(ctx):
         ctx.set_config(761, **base)
 
 
-@pytest.mark.parametrize("cfg", TIMED_CONFIGS, ids=["perkey_G128_W1_L1_eager", "r3batch_G32_W4_eager",
+@pytest.mark.parametrize("cfg", TIMED_CONFIGS, ids=["r3batch_G64_W2_jump_eager", "r3batch_G64_W4_jump_eager",
+                                                     "perkey_G128_W1_L1_eager", "r3batch_G32_W4_eager",
                                                      "r3batch_G32_W8_eager"])
 def test_timed_config_65536(ctx, graph_g32_65536, cfg):
     """The launch bench.py times: eager calls at N = 65536 with the tuned
