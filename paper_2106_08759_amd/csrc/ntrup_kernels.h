@@ -105,59 +105,77 @@ __device__ __forceinline__ void row_swap(uint32_t& a, uint32_t& b) {
     }
 }
 
-template <int EPL>
-__device__ __forceinline__ void bitonic_sort_wave(uint32_t (&L)[EPL], int lane) {
-    constexpr int NS = 64 * EPL;
-    static_assert(EPL % 2 == 0, "row swaps pair the slots");
-    const int i0 = sort_lane(lane) * EPL;   // rank of slot 0
+// One stage (merge size K, partner distance J) of the network; K and J are
+// template arguments, so that every slot index is a constant (a loop over
+// stages left to the unroller was expanded only in part for 32 slots per
+// lane, with indexed register access in its place).
+template <int EPL, int K, int J>
+__device__ __forceinline__ void bitonic_stage(uint32_t (&L)[EPL], int lane, int i0) {
+    if constexpr (J >= EPL) {
+        // network lane bit JB; the direction depends on the lane only
+        constexpr int JB = __builtin_ctz(J / EPL);
+        const uint32_t c = ((i0 & K) == 0) ? 0u : 0xFFFFFFFFu;   // 0: ascending pair
+        if constexpr (JB == 3 || JB == 4) {
 #pragma unroll
-    for (int k = 2; k <= NS; k <<= 1) {
+            for (int e = 0; e < EPL; e += 2) {
+                uint32_t lo = L[e], hi = L[e + 1];
+                row_swap<JB == 3 ? 16 : 32>(lo, hi);
+                const uint32_t x = med3_u32(lo, hi, c), y = med3_u32(lo, hi, ~c);
+                lo = x;
+                hi = y;
+                row_swap<JB == 3 ? 16 : 32>(lo, hi);
+                L[e] = lo;
+                L[e + 1] = hi;
+            }
+        } else {
+            // partner in lane ^ LJ, same slot: keep the smaller iff this lane
+            // is the lower side of an ascending pair
+            constexpr int LJ = JB == 5 ? 4 : (JB == 2 ? 8 : 1 << JB);
+            const uint32_t cc = ((i0 & J) == 0) ? c : ~c;
 #pragma unroll
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            if (j >= EPL) {
-                // network lane bit jb; the direction depends on the lane only
-                const int jb = __builtin_ctz(j / EPL);
-                const uint32_t c = ((i0 & k) == 0) ? 0u : 0xFFFFFFFFu;   // 0: ascending pair
-                if (jb == 3 || jb == 4) {
+            for (int e = 0; e < EPL; e++) {
+                const uint32_t o = lane_xor(L[e], LJ, lane);
+                L[e] = med3_u32(L[e], o, cc);
+            }
+        }
+    } else {
 #pragma unroll
-                    for (int e = 0; e < EPL; e += 2) {
-                        uint32_t lo = L[e], hi = L[e + 1];
-                        if (jb == 3) row_swap<16>(lo, hi);
-                        else row_swap<32>(lo, hi);
-                        const uint32_t a = med3_u32(lo, hi, c), b = med3_u32(lo, hi, ~c);
-                        lo = a;
-                        hi = b;
-                        if (jb == 3) row_swap<16>(lo, hi);
-                        else row_swap<32>(lo, hi);
-                        L[e] = lo;
-                        L[e + 1] = hi;
-                    }
-                } else {
-                    // partner in lane ^ lj, same slot: keep the smaller iff
-                    // this lane is the lower side of an ascending pair
-                    const int lj = jb == 5 ? 4 : (jb == 2 ? 8 : 1 << jb);
-                    const uint32_t cc = ((i0 & j) == 0) ? c : ~c;
-#pragma unroll
-                    for (int e = 0; e < EPL; e++) {
-                        const uint32_t o = lane_xor(L[e], lj, lane);
-                        L[e] = med3_u32(L[e], o, cc);
-                    }
-                }
-            } else {
-#pragma unroll
-                for (int e = 0; e < EPL; e++) {
-                    if ((e & j) == 0) {
-                        const int e2 = e | j;
-                        const bool up = ((i0 + e) & k) == 0;
-                        const uint32_t c = up ? 0u : 0xFFFFFFFFu;
-                        const uint32_t a = L[e], b = L[e2];
-                        L[e] = med3_u32(a, b, c);
-                        L[e2] = med3_u32(a, b, ~c);
-                    }
-                }
+        for (int e = 0; e < EPL; e++) {
+            if ((e & J) == 0) {
+                const int e2 = e | J;
+                const bool up = ((i0 + e) & K) == 0;
+                const uint32_t c = up ? 0u : 0xFFFFFFFFu;
+                const uint32_t x = L[e], y = L[e2];
+                L[e] = med3_u32(x, y, c);
+                L[e2] = med3_u32(x, y, ~c);
             }
         }
     }
+}
+
+// The stages J = J0, J0/2, .., 1 of the merge of size K.
+template <int EPL, int K, int J>
+__device__ __forceinline__ void bitonic_merge(uint32_t (&L)[EPL], int lane, int i0) {
+    if constexpr (J > 0) {
+        bitonic_stage<EPL, K, J>(L, lane, i0);
+        bitonic_merge<EPL, K, J / 2>(L, lane, i0);
+    }
+}
+
+// The merges of size K, 2K, .., 64 EPL.
+template <int EPL, int K>
+__device__ __forceinline__ void bitonic_merges_from(uint32_t (&L)[EPL], int lane, int i0) {
+    if constexpr (K <= 64 * EPL) {
+        bitonic_merge<EPL, K, K / 2>(L, lane, i0);
+        bitonic_merges_from<EPL, 2 * K>(L, lane, i0);
+    }
+}
+
+template <int EPL>
+__device__ __forceinline__ void bitonic_sort_wave(uint32_t (&L)[EPL], int lane) {
+    static_assert(EPL % 2 == 0, "row swaps pair the slots");
+    const int i0 = sort_lane(lane) * EPL;   // rank of slot 0
+    bitonic_merges_from<EPL, 2>(L, lane, i0);
 }
 
 // f of one key (key index `index`), written to `row`; one wave.

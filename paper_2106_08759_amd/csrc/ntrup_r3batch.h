@@ -85,6 +85,24 @@ struct R3Screen {
             for (int j = 0; j < F::ngroups; j++) r3_horner_step(rm[j], rs[j], cm, cs, F::g[j].d, F::g[j].m, F::g[j].s);
         }
     }
+    // Words k = WN-1 .. 0 of a bitsliced g whose nonzero plane of word k is
+    // at w[k * stride] and sign plane at w[k * stride + plane]: the loads of
+    // eight words are issued before their serial Horner steps.
+    __device__ __forceinline__ void feed_words(const uint32_t* w, size_t plane, size_t stride) {
+        constexpr int WN = ceil_div(P, 32), CH = 8;
+        for (int c = WN; c > 0; c -= CH) {
+            uint32_t wm[CH], ws[CH];
+#pragma unroll
+            for (int t = 0; t < CH; t++) {
+                const int k = c - 1 - t;
+                wm[t] = k >= 0 ? w[(size_t)k * stride] : 0u;
+                ws[t] = k >= 0 ? w[(size_t)k * stride + plane] : 0u;
+            }
+#pragma unroll
+            for (int t = 0; t < CH; t++)
+                if (c - 1 - t >= 0) feed_word(wm[t], ws[t]);
+        }
+    }
     // true iff g mod f != 0 for every small factor f
     __device__ __forceinline__ bool passes() const {
         bool ok = true;
@@ -134,8 +152,7 @@ __global__ __launch_bounds__(256) void r3b_screen_kernel(R3bArgs<P> a) {
         if (a.screen) {
             R3Screen<P> sc;
             sc.reset();
-            for (int k = WN - 1; k >= 0; k--)
-                sc.feed_word(a.gbits[(size_t)(2 * k) * n + key], a.gbits[(size_t)(2 * k + 1) * n + key]);
+            sc.feed_words(a.gbits + key, n, 2 * n);
             fail = !sc.passes();
         }
         a.attempts[key] = 0;
@@ -175,51 +192,68 @@ __global__ __launch_bounds__(256) void r3b_retry_sample_kernel(R3bArgs<P> a) {
 template <int P>
 __global__ __launch_bounds__(256) void r3b_retry_screen_kernel(R3bArgs<P> a) {
     constexpr int WN = ceil_div(P, 32);
-    const int count = *(volatile int*)a.rt_count;
+    static_assert(kR3bRetryDraws * 64 == 256, "one wave per draw");
+    // 64 listed keys per round of the workgroup; wave d screens draw 1 + d of
+    // each (the serial Horner passes of the four draws side by side), then
+    // wave 0 takes, per key, the lowest draw that passed
+    __shared__ uint8_t pass[kR3bRetryDraws][64];
+    const int count = *(volatile int*)a.rt_count;   // the same for every thread
     const size_t n = (size_t)a.n;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) {
-        const int key = a.rt_list[i];
-        const uint64_t index = a.first_index + (uint64_t)key;
-        int att = 1;
-        bool done = false;
-        if (i < a.rt_cap) {
-            for (int d = 0; d < kR3bRetryDraws && !done; d++) {
-                R3Screen<P> sc;
-                sc.reset();
-                for (int k = WN - 1; k >= 0; k--) {
-                    const size_t base = ((size_t)(d * WN + k) * 2) * a.rt_cap;
-                    sc.feed_word(a.rt_scratch[base + i], a.rt_scratch[base + a.rt_cap + i]);
-                }
-                if (sc.passes()) {
+    const int d = (int)(threadIdx.x >> 6), j = (int)(threadIdx.x & 63);
+    for (int i0 = blockIdx.x * 64; i0 < count; i0 += gridDim.x * 64) {
+        const int i = i0 + j;
+        bool ok = false;
+        if (i < count && i < a.rt_cap) {
+            R3Screen<P> sc;
+            sc.reset();
+            sc.feed_words(a.rt_scratch + ((size_t)(d * WN) * 2) * a.rt_cap + i, (size_t)a.rt_cap,
+                          2 * (size_t)a.rt_cap);
+            ok = sc.passes();
+        }
+        pass[d][j] = ok ? 1 : 0;
+        __syncthreads();
+        if (d == 0 && i < count) {
+            const int key = a.rt_list[i];
+            const uint64_t index = a.first_index + (uint64_t)key;
+            int att = 1;
+            bool done = false;
+            if (i < a.rt_cap) {
+                int win = -1;
+#pragma unroll
+                for (int dd = kR3bRetryDraws - 1; dd >= 0; dd--)
+                    if (pass[dd][j]) win = dd;
+                if (win >= 0) {
                     for (int k = 0; k < WN; k++) {
-                        const size_t base = ((size_t)(d * WN + k) * 2) * a.rt_cap;
+                        const size_t base = ((size_t)(win * WN + k) * 2) * a.rt_cap;
                         a.gbits[(size_t)(2 * k) * n + key] = a.rt_scratch[base + i];
                         a.gbits[(size_t)(2 * k + 1) * n + key] = a.rt_scratch[base + a.rt_cap + i];
                     }
-                    att = 1 + d;
+                    att = 1 + win;
                     done = true;
+                } else {
+                    att = 1 + kR3bRetryDraws;
                 }
             }
-            if (!done) att = 1 + kR3bRetryDraws;
-        }
-        for (; !done && att < kMaxAttempts; att++) {
-            R3Screen<P> sc;
-            sc.reset();
-            for (int k = WN - 1; k >= 0; k--) {
-                uint32_t mw, sw;
-                sample_small_word<P>(a.seed, index, att, k, mw, sw);
-                sw &= mw;
-                a.gbits[(size_t)(2 * k) * n + key] = mw;
-                a.gbits[(size_t)(2 * k + 1) * n + key] = sw;
-                sc.feed_word(mw, sw);
+            for (; !done && att < kMaxAttempts; att++) {
+                R3Screen<P> sc;
+                sc.reset();
+                for (int k = WN - 1; k >= 0; k--) {
+                    uint32_t mw, sw;
+                    sample_small_word<P>(a.seed, index, att, k, mw, sw);
+                    sw &= mw;
+                    a.gbits[(size_t)(2 * k) * n + key] = mw;
+                    a.gbits[(size_t)(2 * k + 1) * n + key] = sw;
+                    sc.feed_word(mw, sw);
+                }
+                if (sc.passes()) {
+                    done = true;
+                    break;
+                }
             }
-            if (sc.passes()) {
-                done = true;
-                break;
-            }
+            if (!done) atomicOr(a.err, 1);
+            a.attempts[key] = (uint8_t)(done ? att : kMaxAttempts);
         }
-        if (!done) atomicOr(a.err, 1);
-        a.attempts[key] = (uint8_t)(done ? att : kMaxAttempts);
+        __syncthreads();
     }
 }
 
