@@ -96,12 +96,12 @@ const char *ntrup_strerror(int code);
 
 /* Tuning knobs per parameter set (chosen by the autotuner or the caller).
  *   group_size           Montgomery group size G, 1..1024 (Section 2.2's n)
- *   lanes_per_key        1, 2, 4, 8, 16 or 32 lanes per key for the main R/3 pass
+ *   lanes_per_key        1, 2, 4, 8, 16, 32 or 64 lanes per key for the main R/3 pass
  *                        (more lanes: fewer registers and lower latency per
  *                        key, more cross-lane overhead; one lane per key
  *                        also skips the words of f, g, v, r that no later
  *                        divstep reads, about a fifth of the work)
- *   retry_lanes_per_key  1, 2, 4, 8, 16 or 32 lanes per key for the retry passes,
+ *   retry_lanes_per_key  1, 2, 4, 8, 16, 32 or 64 lanes per key for the retry passes,
  *                        which are latency-bound (few keys, a full divstep
  *                        run each)
  *   retry_parallel_attempts  1, 2, 4 or 8 consecutive g draws tried side by
@@ -137,7 +137,8 @@ const char *ntrup_strerror(int code);
  *                        over R/3 as in Algorithm 1 (screen of each g against
  *                        the small irreducible factors of x^p - x - 1 mod 3,
  *                        prefix products on the matrix cores, one divstep
- *                        reciprocal per group (32 lanes per group product),
+ *                        reciprocal per group (32 lanes per group product,
+ *                        64 at p = 1277),
  *                        back-substitution; a group
  *                        whose product is not a unit falls back to per-key
  *                        divsteps).  Same keys either way.  Requires

@@ -220,8 +220,8 @@ int enqueue_persistent(ntrup_ctx* ctx, void* base, const Seed& sd, const std::ve
 
 bool valid_config(const ntrup_config& c) {
     auto pow2_ok = [](int l, int hi) { return l >= 1 && l <= hi && (l & (l - 1)) == 0; };
-    return c.group_size >= 1 && c.group_size <= 1024 && pow2_ok(c.lanes_per_key, 32) &&
-           pow2_ok(c.retry_lanes_per_key, 32) && pow2_ok(c.retry_parallel_attempts, 8) &&
+    return c.group_size >= 1 && c.group_size <= 1024 && pow2_ok(c.lanes_per_key, 64) &&
+           pow2_ok(c.retry_lanes_per_key, 64) && pow2_ok(c.retry_parallel_attempts, 8) &&
            c.retry_lanes_per_key * c.retry_parallel_attempts <= 64 && c.retry_passes >= 0 &&
            c.retry_passes <= 8 && (c.use_graph == 0 || c.use_graph == 1) &&
            (c.product_engine == 0 || c.product_engine == 1) &&

@@ -34,16 +34,16 @@ void launch_r3(int lpk, size_t n, const R3Args& a, hipStream_t st) {
         case 4: hipLaunchKernelGGL((r3_kernel<P, 4>), grid, blk, 0, st, a); break;
         case 16: hipLaunchKernelGGL((r3_kernel<P, 16>), grid, blk, 0, st, a); break;
         case 32: hipLaunchKernelGGL((r3_kernel<P, 32>), grid, blk, 0, st, a); break;
+        case 64: hipLaunchKernelGGL((r3_kernel<P, 64>), grid, blk, 0, st, a); break;
         default: hipLaunchKernelGGL((r3_kernel<P, 8>), grid, blk, 0, st, a); break;
     }
 }
 
-#ifndef NTRUP_R3_GROUP_LANES
-#define NTRUP_R3_GROUP_LANES 32
-#endif
 // lanes per group product in the divstep reciprocals of the batched R/3
-// stage (few products, so each is spread over as many lanes as pays)
-constexpr int kR3GroupLanes = NTRUP_R3_GROUP_LANES;
+// stage (few products, so each is spread over as many lanes as pays: one
+// word pair per lane, 32 lanes up to p = 1023 and a whole wave above)
+template <int P>
+constexpr int r3_group_lanes() { return R3Shape<P, 32>::W2 > 1 ? 64 : 32; }
 
 // The prefix kernel with W waves per workgroup; jump: its shared reciprocal
 // by jump divsteps.
@@ -219,7 +219,7 @@ int enqueue_keygen(ntrup_ctx* ctx, const ntrup_config& cfg, const Seed& seed, ui
             hipLaunchKernelGGL((r3_share_recip_kernel<P>), dim3(grid_for(ngroups, kR3Share)), dim3(64 * kR3Share), 0,
                                sr, (int)ngroups, (const int8_t*)w.qrow, w.pinv, (uint8_t*)w.lists[1]);
         else
-            launch_r3<P>(kR3GroupLanes, ngroups, gi, sr);
+            launch_r3<P>(r3_group_lanes<P>(), ngroups, gi, sr);
         hipLaunchKernelGGL((r3b_back_kernel<P>), dim3(ngroups), dim3(64), 0, sr, b);
         mark(3, sr);
         a.list_in = w.lists[0];

@@ -32,8 +32,8 @@ namespace ntrup {
 
 template <int P, int LPK>
 struct R3Shape {
-    static_assert(LPK == 1 || LPK == 2 || LPK == 4 || LPK == 8 || LPK == 16 || LPK == 32,
-                  "1, 2, 4, 8, 16 or 32 lanes per key");
+    static_assert(LPK == 1 || LPK == 2 || LPK == 4 || LPK == 8 || LPK == 16 || LPK == 32 || LPK == 64,
+                  "1, 2, 4, 8, 16, 32 or 64 lanes per key");
     static constexpr int W = ceil_div(P + 1, 32);   // words holding p+1 coefficients
     static constexpr int W2 = ceil_div(W, LPK);     // words per lane
     static constexpr int WT = W2 * LPK;             // padded words per polynomial
@@ -53,10 +53,12 @@ struct R3Shape {
 // broadcast of the quad below, lanes 0-3 and 8-11 keep their own); for 16,
 // row_newbcast:0 (lane 0 of each row to its row); for 32, that followed by
 // row_bcast:15 written into rows 1 and 3 only (each takes lane 15 of the row
-// below, which by then holds that row's lane 0).
+// below, which by then holds that row's lane 0); for 64, the wave's first
+// lane (v_readfirstlane: every lane is active in the divstep loop).
 template <int LPK>
 __device__ __forceinline__ uint32_t group_first(uint32_t x) {
     if (LPK == 1) return x;
+    if (LPK == 64) return (uint32_t)__builtin_amdgcn_readfirstlane((int)x);
     if (LPK == 2) return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0xA0, 0xF, 0xF, true);  // [0,0,2,2]
     if (LPK >= 16) {
         const int r = __builtin_amdgcn_mov_dpp((int)x, 0x150, 0xF, 0xF, true);             // row_newbcast:0
@@ -69,14 +71,15 @@ __device__ __forceinline__ uint32_t group_first(uint32_t x) {
 }
 // lane i reads lane i+1 / lane i-1: within its row of 16 (row_shl:1 /
 // row_shr:1) when a group lies in one row, across the wave (wave_shl:1 /
-// wave_shr:1) for groups of 32; the caller masks the lane that must read 0
+// wave_shr:1) for groups of 32 or 64; the caller masks the lane that must
+// read 0
 template <int LPK>
 __device__ __forceinline__ uint32_t group_next(uint32_t x) {
-    return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, LPK == 32 ? 0x130 : 0x101, 0xF, 0xF, true);
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, LPK >= 32 ? 0x130 : 0x101, 0xF, 0xF, true);
 }
 template <int LPK>
 __device__ __forceinline__ uint32_t group_prev(uint32_t x) {
-    return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, LPK == 32 ? 0x138 : 0x111, 0xF, 0xF, true);
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, LPK >= 32 ? 0x138 : 0x111, 0xF, 0xF, true);
 }
 
 // Three-input boolean functions on gfx950 (v_bitop3_b32): the 8-bit table is

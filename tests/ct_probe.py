@@ -31,7 +31,7 @@ def main():
     bigs = [dev(wl.random_rq(p, n, tag=30 + i)) for i in range(3)]
     seeds = [bytes(rng.integers(0, 256, size=32).astype(np.uint8)) for _ in range(3)]
     torch.cuda.synchronize()
-    for lpk in (1, 2, 4, 8, 16, 32):
+    for lpk in (1, 2, 4, 8, 16, 32, 64):
         ctx.set_config(p, lanes_per_key=lpk)
         for s in smalls:
             ctx.recip_r3(p, s)

@@ -169,7 +169,7 @@ def _f3_factor(p, d):
 
 
 @pytest.mark.parametrize("p", P_ALL)
-@pytest.mark.parametrize("lpk", [1, 2, 4, 8, 16, 32])
+@pytest.mark.parametrize("lpk", [1, 2, 4, 8, 16, 32, 64])
 def test_recip_r3_matches_oracle(ctx, p, lpk):
     ctx.set_config(p, lanes_per_key=lpk)
     try:
