@@ -1,7 +1,7 @@
 """Runs the secret-dependent operations of KeyGen on three different secret
 inputs each (same shapes), one after the other, for a hardware-counter run
 (test_gpu_constant_time.py runs it under rocprofv3 --pmc): the R/3 reciprocal
-(bitsliced divsteps, four lane layouts), the R/q reciprocal (plain divstep
+(bitsliced divsteps, 1 to 64 lanes per key), the R/q reciprocal (plain divstep
 loop and jump divsteps), the R/q product with a small and with a big
 operand, the Short and small samplers, and the encapsulation and
 decapsulation core.  Prints one line per operation."""
